@@ -1,0 +1,986 @@
+// Oracle for the compact ADER-HWENO step on triangles.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is a plain, slow FP64 CPU implementation
+// of what one explicit time step of the scheme computes.  It is used by the
+// tests, by the smoke check and by the CPU-baseline leg of the benchmark, and
+// never by the product library (which shares no code with it).
+//
+// It follows the paper's Section 2 step by step, cell by cell:
+//   * finite-volume update, eq. (flx), with the space-time flux quadrature of
+//     eqs. (fx) and (flux) and the local Lax-Friedrichs flux of Sec. 2.1;
+//   * Taylor extrapolation in time, eqs. (tay)/(tayext), with time derivatives
+//     from the Lax-Wendroff formulas of Sec. 2.1 (f' and f'' taken with
+//     hyper-dual numbers applied to the flux functions themselves);
+//   * the HWENO reconstruction of Sec. 2.2, Steps 1-6: constrained least
+//     squares solved through their KKT systems in the monomial basis, the
+//     simplified smoothness indicators of eq. (smoo1), the nonlinear weights of
+//     eq. (nonlinearweight) and the combination of eq. (recon);
+//   * the derivative averages of Sec. 2.3 by Green-Gauss, eq. (derave2d2),
+//     with the interface value of eq. (timeflux) at tau = dt (eq. (taylor2dtime)).
+//
+// Readings where the paper is silent (both sides of the parity test use them):
+//   time rule: 3-point Gauss-Lobatto, nodes {0, 1/2, 1} dt, weights {1,4,1}/6;
+//   edge rule: 2-point Gauss-Legendre; alpha from the two cell averages;
+//   systems: component-wise reconstruction of the conservative variables;
+//   periodic boundaries by exact translation across seams; transmissive
+//   boundaries by a mirrored ghost cell for the stencil and W_ext := W_int
+//   at boundary Gauss points; kappa/D := 0 when kappa == 0.
+//   Non-smooth points for derivatives: d|x| = sign(x) dx with sign(0) = 0;
+//   max(a, b) takes a (the edge's first cell, the one with the lower caller
+//   index) on ties.
+//
+// Everything is templated on the scalar type: double for the forward map,
+// Dual (value + one tangent) for exact Jacobian-vector products.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <utility>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ---------------------------------------------------------------- numbers
+struct Dual {
+  double v, d;
+  Dual() : v(0), d(0) {}
+  Dual(double a) : v(a), d(0) {}
+  Dual(double a, double b) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+  double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+inline Dual& operator*=(Dual& a, Dual b) { a = a * b; return a; }
+inline double val(double a) { return a; }
+inline double val(Dual a) { return a.v; }
+inline double sgn0(double x) { return x > 0 ? 1.0 : (x < 0 ? -1.0 : 0.0); }
+inline double absval(double a) { return std::fabs(a); }
+inline Dual absval(Dual a) { return Dual(std::fabs(a.v), sgn0(a.v) * a.d); }
+inline double sqrtv(double a) { return std::sqrt(a); }
+inline Dual sqrtv(Dual a) {
+  double s = std::sqrt(a.v);
+  return Dual(s, a.d / (2.0 * s));
+}
+template <class T> inline T maxfirst(T a, T b) { return val(a) >= val(b) ? a : b; }
+
+// Hyper-dual number a + e1 b1 + e2 b2 + e1 e2 b12 over scalar T
+// (e1^2 = e2^2 = 0).  f(w + e1 x + e2 y + e1e2 z) has e1 part f'x and e1e2
+// part f''[x, y] + f'z.
+template <class T> struct HD {
+  T a, e1, e2, e12;
+};
+template <class T> HD<T> hd(T a) { return HD<T>{a, T(0.0), T(0.0), T(0.0)}; }
+template <class T> HD<T> operator+(const HD<T>& x, const HD<T>& y) {
+  return HD<T>{x.a + y.a, x.e1 + y.e1, x.e2 + y.e2, x.e12 + y.e12};
+}
+template <class T> HD<T> operator-(const HD<T>& x, const HD<T>& y) {
+  return HD<T>{x.a - y.a, x.e1 - y.e1, x.e2 - y.e2, x.e12 - y.e12};
+}
+template <class T> HD<T> operator*(const HD<T>& x, const HD<T>& y) {
+  return HD<T>{x.a * y.a, x.a * y.e1 + x.e1 * y.a, x.a * y.e2 + x.e2 * y.a,
+               x.a * y.e12 + x.e1 * y.e2 + x.e2 * y.e1 + x.e12 * y.a};
+}
+template <class T> HD<T> operator*(double c, const HD<T>& y) {
+  return HD<T>{T(c) * y.a, T(c) * y.e1, T(c) * y.e2, T(c) * y.e12};
+}
+template <class T> HD<T> recip(const HD<T>& x) {
+  T r = T(1.0) / x.a;
+  T r2 = r * r;
+  return HD<T>{r, T(0.0) - x.e1 * r2, T(0.0) - x.e2 * r2,
+               T(2.0) * x.e1 * x.e2 * r2 * r - x.e12 * r2};
+}
+template <class T> HD<T> operator/(const HD<T>& x, const HD<T>& y) { return x * recip(y); }
+
+// ---------------------------------------------------------------- options
+struct Opts {
+  int eq;           // 0 advection, 1 Burgers, 2 Euler
+  int bc;           // 0 periodic, 1 transmissive
+  double box[4];    // x0 x1 y0 y1
+  double adv[2];    // advection velocity
+  double gas_gamma; // ratio of specific heats
+  double lin_w[4];  // linear weights gamma_1..gamma_4
+  double eps;       // epsilon of the nonlinear weights
+  int linear_only;  // 1: use the linear weights (omega = gamma), for exactness pins
+};
+
+inline int ncomp(int eq) { return eq == 2 ? 4 : 1; }
+
+// Physical flux F(W) = (f(W), g(W)) of the three equations, templated so the
+// same code is evaluated on doubles, duals and hyper-duals.
+template <class N>
+void flux_fg(const Opts& o, const N* W, N* f, N* g) {
+  if (o.eq == 0) {
+    f[0] = o.adv[0] * W[0];
+    g[0] = o.adv[1] * W[0];
+  } else if (o.eq == 1) {
+    f[0] = 0.5 * (W[0] * W[0]);
+    g[0] = f[0];
+  } else {
+    const N& rho = W[0];
+    const N& mx = W[1];
+    const N& my = W[2];
+    const N& E = W[3];
+    N u = mx / rho;
+    N v = my / rho;
+    N p = (o.gas_gamma - 1.0) * (E - 0.5 * (mx * u + my * v));
+    f[0] = mx;
+    f[1] = mx * u + p;
+    f[2] = mx * v;
+    f[3] = u * (E + p);
+    g[0] = my;
+    g[1] = my * u;
+    g[2] = my * v + p;
+    g[3] = v * (E + p);
+  }
+}
+// Largest eigenvalue magnitude of d(F.n)/dW at a state (Sec. 2.1).
+template <class T>
+T spectral_radius(const Opts& o, const T* W, double nx, double ny) {
+  if (o.eq == 0) return T(std::fabs(o.adv[0] * nx + o.adv[1] * ny));
+  if (o.eq == 1) return absval(W[0] * T(nx + ny));
+  T u = W[1] / W[0], v = W[2] / W[0];
+  T p = T(o.gas_gamma - 1.0) * (W[3] - T(0.5) * (W[1] * u + W[2] * v));
+  T c = sqrtv(T(o.gas_gamma) * p / W[0]);
+  return absval(u * T(nx) + v * T(ny)) + c;
+}
+
+// ---------------------------------------------------------------- mesh
+struct Tri {
+  double x[3], y[3];  // counter-clockwise, unwrapped
+};
+inline double tri_area(const Tri& t) {
+  return 0.5 * ((t.x[1] - t.x[0]) * (t.y[2] - t.y[0]) - (t.y[1] - t.y[0]) * (t.x[2] - t.x[0]));
+}
+
+struct Face {
+  int nb;         // neighbour cell, or -1 on a transmissive boundary
+  int nb_face;    // neighbour's face index
+  double sx, sy;  // translation mapping the neighbour's frame into this cell's frame
+  double nx, ny;  // outward unit normal of this cell
+  double len;
+  Tri ghost;      // mirrored cell when nb == -1
+};
+
+struct Mesh {
+  Opts o;
+  int64_t N = 0, E = 0;
+  int m = 1;
+  std::vector<Tri> tri;
+  std::vector<double> area, cx, cy;
+  std::vector<std::array<Face, 3>> face;
+};
+
+// Cell average over a triangle of a polynomial given through a callback:
+// the three edge midpoints with weights 1/3 integrate quadratics exactly.
+template <class Fn>
+double tri_avg_quadratic(const Tri& t, Fn fn) {
+  double s = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    int k1 = (k + 1) % 3;
+    s += fn(0.5 * (t.x[k] + t.x[k1]), 0.5 * (t.y[k] + t.y[k1]));
+  }
+  return s / 3.0;
+}
+
+// ---------------------------------------------------------------- dense solve
+// Solve M x = b for several right-hand sides (partial pivoting elimination).
+// M is n x n row-major double; rhs has nr columns of scalar type T.
+template <class T>
+bool solve_dense(int n, std::vector<double> M, std::vector<T>& rhs, int nr) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(M[r * n + c]) > std::fabs(M[piv * n + c])) piv = r;
+    if (M[piv * n + c] == 0.0) return false;
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) std::swap(M[c * n + k], M[piv * n + k]);
+      for (int k = 0; k < nr; ++k) std::swap(rhs[c * nr + k], rhs[piv * nr + k]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      double f = M[r * n + c] / M[c * n + c];
+      if (f == 0.0) continue;
+      for (int k = c; k < n; ++k) M[r * n + k] -= f * M[c * n + k];
+      for (int k = 0; k < nr; ++k) rhs[r * nr + k] -= T(f) * rhs[c * nr + k];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    for (int k = 0; k < nr; ++k) {
+      T s = rhs[c * nr + k];
+      for (int j = c + 1; j < n; ++j) s -= T(M[c * n + j]) * rhs[j * nr + k];
+      rhs[c * nr + k] = s / T(M[c * n + c]);
+    }
+  }
+  return true;
+}
+
+// Equality-constrained least squares: minimise |A x - b|^2 subject to C x = d
+// through the KKT system [A^T A, C^T; C, 0] [x; mu] = [A^T b; d].
+// A: na x n, C: nc x n (row-major), b: na x nr, d: nc x nr.  Returns x: n x nr.
+template <class T>
+bool constrained_lsq(int n, int na, int nc, const double* A, const double* C,
+                     const std::vector<T>& b, const std::vector<T>& d, int nr,
+                     std::vector<T>& x) {
+  int K = n + nc;
+  std::vector<double> M(K * K, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int r = 0; r < na; ++r) s += A[r * n + i] * A[r * n + j];
+      M[i * K + j] = s;
+    }
+  for (int r = 0; r < nc; ++r)
+    for (int j = 0; j < n; ++j) {
+      M[(n + r) * K + j] = C[r * n + j];
+      M[j * K + (n + r)] = C[r * n + j];
+    }
+  std::vector<T> rhs(K * nr, T(0.0));
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < nr; ++k) {
+      T s = T(0.0);
+      for (int r = 0; r < na; ++r) s += T(A[r * n + i]) * b[r * nr + k];
+      rhs[i * nr + k] = s;
+    }
+  for (int r = 0; r < nc; ++r)
+    for (int k = 0; k < nr; ++k) rhs[(n + r) * nr + k] = d[r * nr + k];
+  if (!solve_dense(K, M, rhs, nr)) return false;
+  x.assign(n * nr, T(0.0));
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < nr; ++k) x[i * nr + k] = rhs[i * nr + k];
+  return true;
+}
+
+// ---------------------------------------------------------------- recon
+// Polynomials are kept in the monomial basis about the target cell's
+// centroid: p(x, y) = a0 + a1 X + a2 Y + a3 X^2 + a4 X Y + a5 Y^2,
+// X = x - x_K0, Y = y - y_K0 (the linear ones have a3 = a4 = a5 = 0).
+template <class T>
+struct Recon {
+  T p[4][4][6];     // [candidate l=1..4][component][coefficient]
+  T beta[4][4];     // [component][l]
+  T omega[4][4];    // [component][l]
+  double cx, cy;    // expansion point (centroid of K0)
+};
+
+// Stencil cell l of K0 (l = 0 is K0 itself), in K0's frame, and its state.
+template <class T>
+struct StencilCell {
+  Tri t;
+  double area;
+  T W[4], V[4], Y[4];
+};
+
+template <class T>
+void stencil_of(const Mesh& M, const T* s, int64_t k, StencilCell<T> st[4]) {
+  const int m = M.m;
+  const int64_t N = M.N;
+  st[0].t = M.tri[k];
+  st[0].area = M.area[k];
+  for (int c = 0; c < m; ++c) {
+    st[0].W[c] = s[(0 * m + c) * N + k];
+    st[0].V[c] = s[(1 * m + c) * N + k];
+    st[0].Y[c] = s[(2 * m + c) * N + k];
+  }
+  for (int f = 0; f < 3; ++f) {
+    const Face& F = M.face[k][f];
+    StencilCell<T>& c = st[f + 1];
+    if (F.nb >= 0) {
+      c.t = M.tri[F.nb];
+      for (int v = 0; v < 3; ++v) {
+        c.t.x[v] += F.sx;
+        c.t.y[v] += F.sy;
+      }
+      c.area = M.area[F.nb];
+      for (int q = 0; q < m; ++q) {
+        c.W[q] = s[(0 * m + q) * N + F.nb];
+        c.V[q] = s[(1 * m + q) * N + F.nb];
+        c.Y[q] = s[(2 * m + q) * N + F.nb];
+      }
+    } else {
+      // transmissive boundary: K0 mirrored across the face, state mirrored too
+      c.t = F.ghost;
+      c.area = M.area[k];
+      for (int q = 0; q < m; ++q) {
+        T vn = st[0].V[q] * T(F.nx) + st[0].Y[q] * T(F.ny);
+        c.W[q] = st[0].W[q];
+        c.V[q] = st[0].V[q] - T(2.0 * F.nx) * vn;
+        c.Y[q] = st[0].Y[q] - T(2.0 * F.ny) * vn;
+      }
+    }
+  }
+}
+
+template <class T>
+bool reconstruct(const Mesh& M, const T* s, int64_t k, Recon<T>& R) {
+  const Opts& o = M.o;
+  const int m = M.m;
+  StencilCell<T> st[4];
+  stencil_of(M, s, k, st);
+  const double x0 = M.cx[k], y0 = M.cy[k];
+  R.cx = x0;
+  R.cy = y0;
+  const double A0 = M.area[k];
+  // scaled monomials xi = X / h, eta = Y / h keep the KKT matrices O(1)
+  const double h = std::sqrt(A0);
+  auto mono_avg = [&](const Tri& t, int j) {
+    return tri_avg_quadratic(t, [&](double x, double y) {
+      double a = (x - x0) / h, b = (y - y0) / h;
+      switch (j) {
+        case 0: return 1.0;
+        case 1: return a;
+        case 2: return b;
+        case 3: return a * a;
+        case 4: return a * b;
+        default: return b * b;
+      }
+    });
+  };
+
+  // Step 1: quadratic p1 on T1 = {K0..K3}; the four cell averages exactly,
+  // the six union derivative integrals in the least-squares sense.
+  {
+    double C[4 * 6], A[6 * 6];
+    for (int l = 0; l < 4; ++l)
+      for (int j = 0; j < 6; ++j) C[l * 6 + j] = mono_avg(st[l].t, j);
+    // d/dx of (a0 + a1 xi + a2 eta + a3 xi^2 + a4 xi eta + a5 eta^2) = (a1 + 2 a3 xi + a4 eta)/h;
+    // integral over K = |K| * average.  Every row is multiplied by h/|K0|,
+    // which leaves the least-squares solution unchanged.
+    for (int l = 1; l <= 3; ++l) {
+      double* rx = &A[(l - 1) * 6];
+      double* ry = &A[(l + 2) * 6];
+      for (int j = 0; j < 6; ++j) rx[j] = ry[j] = 0.0;
+      for (int u = 0; u < 2; ++u) {
+        const StencilCell<T>& c = u == 0 ? st[0] : st[l];
+        double w = c.area / A0;
+        double mxi = mono_avg(c.t, 1), meta = mono_avg(c.t, 2);
+        rx[1] += w;
+        rx[3] += w * 2.0 * mxi;
+        rx[4] += w * meta;
+        ry[2] += w;
+        ry[4] += w * mxi;
+        ry[5] += w * 2.0 * meta;
+      }
+    }
+    std::vector<T> b(6 * m), d(4 * m), x;
+    for (int q = 0; q < m; ++q) {
+      for (int l = 0; l < 4; ++l) d[l * m + q] = st[l].W[q];
+      for (int l = 1; l <= 3; ++l) {
+        b[(l - 1) * m + q] = (T(st[l].area) * st[l].V[q] + T(A0) * st[0].V[q]) * T(h / A0);
+        b[(l + 2) * m + q] = (T(st[l].area) * st[l].Y[q] + T(A0) * st[0].Y[q]) * T(h / A0);
+      }
+    }
+    if (!constrained_lsq<T>(6, 6, 4, A, C, b, d, m, x)) return false;
+    for (int q = 0; q < m; ++q) {
+      R.p[0][q][0] = x[0 * m + q];
+      R.p[0][q][1] = x[1 * m + q] / T(h);
+      R.p[0][q][2] = x[2 * m + q] / T(h);
+      R.p[0][q][3] = x[3 * m + q] / T(h * h);
+      R.p[0][q][4] = x[4 * m + q] / T(h * h);
+      R.p[0][q][5] = x[5 * m + q] / T(h * h);
+    }
+  }
+  // Step 2: linear p2, p3, p4 on {K0, K_l}: the K0 average exactly, the K_l
+  // average and K_l derivative averages in the least-squares sense, with the
+  // rows as written (each divided by the common factor |K_l|).
+  for (int l = 1; l <= 3; ++l) {
+    auto avg_x = [&](const Tri& t) { return tri_avg_quadratic(t, [&](double x, double) { return x - x0; }); };
+    auto avg_y = [&](const Tri& t) { return tri_avg_quadratic(t, [&](double, double y) { return y - y0; }); };
+    double C[3] = {1.0, avg_x(st[0].t), avg_y(st[0].t)};
+    double A[9] = {1.0, avg_x(st[l].t), avg_y(st[l].t), 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+    std::vector<T> b(3 * m), d(m), x;
+    for (int q = 0; q < m; ++q) {
+      d[q] = st[0].W[q];
+      b[0 * m + q] = st[l].W[q];
+      b[1 * m + q] = st[l].V[q];
+      b[2 * m + q] = st[l].Y[q];
+    }
+    if (!constrained_lsq<T>(3, 3, 1, A, C, b, d, m, x)) return false;
+    for (int q = 0; q < m; ++q) {
+      R.p[l][q][0] = x[0 * m + q];
+      R.p[l][q][1] = x[1 * m + q];
+      R.p[l][q][2] = x[2 * m + q];
+      R.p[l][q][3] = R.p[l][q][4] = R.p[l][q][5] = T(0.0);
+    }
+  }
+  // Step 4: smoothness indicators at the barycentre of K0 (X = Y = 0), eq. (smoo1).
+  for (int q = 0; q < m; ++q) {
+    for (int l = 0; l < 4; ++l) {
+      const T* a = R.p[l][q];
+      T dx = a[1], dy = a[2];
+      T b = T(A0) * (dx * dx + dy * dy);
+      if (l == 0) {
+        T dxx = T(2.0) * a[3], dxy = a[4], dyy = T(2.0) * a[5];
+        b += T(A0 * A0) * (dxx * dxx + dxy * dxy + dyy * dyy);
+      }
+      R.beta[q][l] = b;
+    }
+    // Step 5: nonlinear weights, eq. (nonlinearweight).
+    T wave = (st[0].W[q] + st[1].W[q] + st[2].W[q] + st[3].W[q]) / T(4.0) + T(1e-30);
+    T* beta = R.beta[q];
+    T tsum = absval(beta[0] - beta[1]) + absval(beta[0] - beta[2]) + absval(beta[0] - beta[3]);
+    T kappa = tsum * tsum / T(9.0);
+    T wb[4];
+    T ssum = T(0.0);
+    for (int l = 0; l < 4; ++l) {
+      if (o.linear_only) {
+        wb[l] = T(o.lin_w[l]);
+      } else {
+        T w2 = wave * wave;
+        T D = w2 * w2 * T(o.eps) + w2 * beta[l];
+        T frac = val(kappa) == 0.0 ? T(0.0) : kappa / D;
+        wb[l] = T(o.lin_w[l]) * (T(1.0) + frac);
+      }
+      ssum += wb[l];
+    }
+    for (int l = 0; l < 4; ++l) R.omega[q][l] = wb[l] / ssum;
+  }
+  return true;
+}
+
+// Step 6, eq. (recon): value and derivatives of the final reconstruction at
+// (x, y) in K0's frame.  D[0..5] = W, W_x, W_y, W_xx, W_xy, W_yy.
+template <class T>
+void eval_recon(const Opts& o, const Recon<T>& R, int q, double x, double y, T D[6]) {
+  const double X = x - R.cx, Y = y - R.cy;
+  T pv[4][6];
+  for (int l = 0; l < 4; ++l) {
+    const T* a = R.p[l][q];
+    pv[l][0] = a[0] + a[1] * T(X) + a[2] * T(Y) + a[3] * T(X * X) + a[4] * T(X * Y) + a[5] * T(Y * Y);
+    pv[l][1] = a[1] + T(2.0 * X) * a[3] + T(Y) * a[4];
+    pv[l][2] = a[2] + T(X) * a[4] + T(2.0 * Y) * a[5];
+    pv[l][3] = T(2.0) * a[3];
+    pv[l][4] = a[4];
+    pv[l][5] = T(2.0) * a[5];
+  }
+  const T* w = R.omega[q];
+  const double g1 = o.lin_w[0];
+  for (int j = 0; j < 6; ++j) {
+    T inner = pv[0][j] / T(g1);
+    for (int l = 1; l < 4; ++l) inner -= T(o.lin_w[l] / g1) * pv[l][j];
+    T r = w[0] * inner;
+    for (int l = 1; l < 4; ++l) r += w[l] * pv[l][j];
+    D[j] = r;
+  }
+}
+
+// ---------------------------------------------------------------- Lax-Wendroff
+// Sec. 2.1: time derivatives from spatial ones.  D[j][q]: j = W, Wx, Wy, Wxx,
+// Wxy, Wyy.  Out: Wt, Wtx, Wty, Wtt per component.
+template <class T>
+void lax_wendroff(const Opts& o, int m, const T D[6][4], T Wt[4], T Wtx[4], T Wty[4], T Wtt[4]) {
+  HD<T> Wh[4]{}, f[4]{}, g[4]{};
+  auto eval = [&](int which, const T* a, const T* b, const T* c, T* out_e1, T* out_e12) {
+    for (int q = 0; q < m; ++q) Wh[q] = HD<T>{D[0][q], a[q], b[q], c[q]};
+    flux_fg(o, Wh, f, g);
+    for (int q = 0; q < m; ++q) {
+      const HD<T>& r = which == 0 ? f[q] : g[q];
+      if (out_e1) out_e1[q] = r.e1;
+      if (out_e12) out_e12[q] = r.e12;
+    }
+  };
+  T zero[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
+  T fWx[4], gWy[4], a1[4], a2[4];
+  // W_t = -f' W_x - g' W_y
+  eval(0, D[1], zero, zero, fWx, nullptr);
+  eval(1, D[2], zero, zero, gWy, nullptr);
+  for (int q = 0; q < m; ++q) Wt[q] = T(0.0) - fWx[q] - gWy[q];
+  // W_tx = -(f''[Wx,Wx] + f' Wxx) - (g''[Wx,Wy] + g' Wxy)
+  eval(0, D[1], D[1], D[3], nullptr, a1);
+  eval(1, D[1], D[2], D[4], nullptr, a2);
+  for (int q = 0; q < m; ++q) Wtx[q] = T(0.0) - a1[q] - a2[q];
+  // W_ty = -(f''[Wy,Wx] + f' Wxy) - (g''[Wy,Wy] + g' Wyy)
+  eval(0, D[2], D[1], D[4], nullptr, a1);
+  eval(1, D[2], D[2], D[5], nullptr, a2);
+  for (int q = 0; q < m; ++q) Wty[q] = T(0.0) - a1[q] - a2[q];
+  // W_tt = -(f''[Wt,Wx] + f' Wtx) - (g''[Wt,Wy] + g' Wty)
+  eval(0, Wt, D[1], Wtx, nullptr, a1);
+  eval(1, Wt, D[2], Wty, nullptr, a2);
+  for (int q = 0; q < m; ++q) Wtt[q] = T(0.0) - a1[q] - a2[q];
+}
+
+// ---------------------------------------------------------------- the step
+const double kGaussS[2] = {0.5 - 0.28867513459481288225, 0.5 + 0.28867513459481288225};  // 1/2 -+ sqrt(3)/6
+const double kGaussW[2] = {0.5, 0.5};
+const double kTimeL[3] = {0.0, 0.5, 1.0};
+const double kTimeW[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+
+// One cell's new state from the reconstructions (eqs. (flx), (fx), (flux),
+// (tay), (tayext), (derave2d2), (timeflux), (taylor2dtime)).
+template <class T>
+void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int64_t k, double dt,
+                 T Wn[4], T Vn[4], T Yn[4]) {
+  const Opts& o = M.o;
+  const int m = M.m;
+  const int64_t N = M.N;
+  T Fsum[4], Vs[4], Ys[4], Wbar[4];
+  for (int q = 0; q < m; ++q) {
+    Fsum[q] = Vs[q] = Ys[q] = T(0.0);
+    Wbar[q] = s[q * N + k];
+  }
+  const Tri& t = M.tri[k];
+  for (int f = 0; f < 3; ++f) {
+    const Face& F = M.face[k][f];
+    int f1 = (f + 1) % 3;
+    T Wbn[4];
+    if (F.nb >= 0)
+      for (int q = 0; q < m; ++q) Wbn[q] = s[q * N + F.nb];
+    // alpha: spectral radii at the two cell averages, the first argument
+    // belonging to the cell with the lower index
+    T alpha = T(0.0);
+    if (F.nb >= 0) {
+      T aK = spectral_radius(o, Wbar, F.nx, F.ny);
+      T aN = spectral_radius(o, Wbn, F.nx, F.ny);
+      alpha = k < F.nb ? maxfirst(aK, aN) : maxfirst(aN, aK);
+    }
+    for (int G = 0; G < 2; ++G) {
+      double xg = t.x[f] + kGaussS[G] * (t.x[f1] - t.x[f]);
+      double yg = t.y[f] + kGaussS[G] * (t.y[f1] - t.y[f]);
+      T Di[6][4], De[6][4], tmp[6];
+      for (int q = 0; q < m; ++q) {
+        eval_recon(o, R[k], q, xg, yg, tmp);
+        for (int j = 0; j < 6; ++j) Di[j][q] = tmp[j];
+      }
+      if (F.nb >= 0) {
+        for (int q = 0; q < m; ++q) {
+          eval_recon(o, R[F.nb], q, xg - F.sx, yg - F.sy, tmp);
+          for (int j = 0; j < 6; ++j) De[j][q] = tmp[j];
+        }
+      }
+      T it[4], itx[4], ity[4], itt[4], et[4], etx[4], ety[4], ett[4];
+      lax_wendroff(o, m, Di, it, itx, ity, itt);
+      if (F.nb >= 0) lax_wendroff(o, m, De, et, etx, ety, ett);
+      for (int sN = 0; sN < 3; ++sN) {
+        double tau = kTimeL[sN] * dt;
+        T Wi[4], We[4], fi[4], gi[4], fe[4], ge[4];
+        for (int q = 0; q < m; ++q) {
+          Wi[q] = Di[0][q] + T(tau) * it[q] + T(0.5 * tau * tau) * itt[q];
+          We[q] = F.nb >= 0 ? De[0][q] + T(tau) * et[q] + T(0.5 * tau * tau) * ett[q] : Wi[q];
+        }
+        flux_fg(o, Wi, fi, gi);
+        flux_fg(o, We, fe, ge);
+        for (int q = 0; q < m; ++q) {
+          T Hi = fi[q] * T(F.nx) + gi[q] * T(F.ny);
+          T He = fe[q] * T(F.nx) + ge[q] * T(F.ny);
+          T Hhat = T(0.5) * (He + Hi - alpha * (We[q] - Wi[q]));
+          Fsum[q] += Hhat * T(kTimeW[sN] * kGaussW[G] * F.len);
+        }
+        if (sN == 2) {  // tau = dt: interface value for the derivative averages
+          for (int q = 0; q < m; ++q) {
+            T What = T(0.5) * (Wi[q] + We[q]);
+            Vs[q] += What * T(F.nx * kGaussW[G] * F.len);
+            Ys[q] += What * T(F.ny * kGaussW[G] * F.len);
+          }
+        }
+      }
+    }
+  }
+  const double A = M.area[k];
+  for (int q = 0; q < m; ++q) {
+    Wn[q] = Wbar[q] - T(dt / A) * Fsum[q];
+    Vn[q] = Vs[q] / T(A);
+    Yn[q] = Ys[q] / T(A);
+  }
+}
+
+int nthreads_or_default(int nt) {
+#ifdef _OPENMP
+  return nt > 0 ? nt : omp_get_max_threads();
+#else
+  (void)nt;
+  return 1;
+#endif
+}
+
+// Step restricted to a list of cells: reconstruct every cell whose
+// reconstruction is needed (the listed cells and their face neighbours), then
+// update the listed cells.  out is [3][m][nc].
+template <class T>
+int step_cells(const Mesh& M, const T* s, const int64_t* cells, int64_t nc, T* out, double dt, int nthr) {
+  const int m = M.m;
+  std::vector<char> need(M.N, 0);
+  for (int64_t i = 0; i < nc; ++i) {
+    int64_t k = cells[i];
+    if (k < 0 || k >= M.N) return -1;
+    need[k] = 1;
+    for (int f = 0; f < 3; ++f)
+      if (M.face[k][f].nb >= 0) need[M.face[k][f].nb] = 1;
+  }
+  std::vector<Recon<T>> R(M.N);
+  int bad = 0;
+  nthr = nthreads_or_default(nthr);
+#pragma omp parallel for schedule(dynamic, 256) num_threads(nthr) reduction(+ : bad)
+  for (int64_t k = 0; k < M.N; ++k)
+    if (need[k] && !reconstruct(M, s, k, R[k])) bad += 1;
+  if (bad) return -3;
+#pragma omp parallel for schedule(dynamic, 256) num_threads(nthr)
+  for (int64_t i = 0; i < nc; ++i) {
+    T Wn[4], Vn[4], Yn[4];
+    update_cell(M, s, R, cells[i], dt, Wn, Vn, Yn);
+    for (int q = 0; q < m; ++q) {
+      out[(0 * m + q) * nc + i] = Wn[q];
+      out[(1 * m + q) * nc + i] = Vn[q];
+      out[(2 * m + q) * nc + i] = Yn[q];
+    }
+  }
+  return 0;
+}
+
+template <class T>
+int step_all(const Mesh& M, const T* s, T* out, double dt, int nthr) {
+  std::vector<int64_t> cells(M.N);
+  for (int64_t k = 0; k < M.N; ++k) cells[k] = k;
+  return step_cells(M, s, cells.data(), M.N, out, dt, nthr);
+}
+
+// ---------------------------------------------------------------- mesh build
+int build_mesh(Mesh& M, const double* nodes, int64_t nn, const int32_t* tris, int64_t nt) {
+  const Opts& o = M.o;
+  const bool periodic = o.bc == 0;
+  const double Lx = o.box[1] - o.box[0], Ly = o.box[3] - o.box[2];
+  M.N = nt;
+  M.m = ncomp(o.eq);
+  M.tri.resize(nt);
+  M.area.resize(nt);
+  M.cx.resize(nt);
+  M.cy.resize(nt);
+  M.face.resize(nt);
+  std::vector<std::array<int32_t, 3>> tv(nt);
+  for (int64_t k = 0; k < nt; ++k) {
+    int32_t v[3] = {tris[3 * k], tris[3 * k + 1], tris[3 * k + 2]};
+    for (int j = 0; j < 3; ++j)
+      if (v[j] < 0 || v[j] >= nn) return -2;
+    Tri t;
+    for (int j = 0; j < 3; ++j) {
+      t.x[j] = nodes[2 * v[j]];
+      t.y[j] = nodes[2 * v[j] + 1];
+      if (periodic && j > 0) {  // unwrap about the first vertex (minimal image)
+        double dx = t.x[j] - t.x[0], dy = t.y[j] - t.y[0];
+        t.x[j] = t.x[0] + dx - Lx * std::nearbyint(dx / Lx);
+        t.y[j] = t.y[0] + dy - Ly * std::nearbyint(dy / Ly);
+      }
+    }
+    if (tri_area(t) < 0) {  // counter-clockwise orientation
+      std::swap(t.x[1], t.x[2]);
+      std::swap(t.y[1], t.y[2]);
+      std::swap(v[1], v[2]);
+    }
+    double a = tri_area(t);
+    double lmax = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      int j1 = (j + 1) % 3;
+      lmax = std::max(lmax, std::hypot(t.x[j1] - t.x[j], t.y[j1] - t.y[j]));
+    }
+    if (!(a > 1e-14 * lmax * lmax)) return -2;
+    M.tri[k] = t;
+    M.area[k] = a;
+    M.cx[k] = (t.x[0] + t.x[1] + t.x[2]) / 3.0;
+    M.cy[k] = (t.y[0] + t.y[1] + t.y[2]) / 3.0;
+    for (int j = 0; j < 3; ++j) tv[k][j] = v[j];
+  }
+  // faces: face f joins vertices f and f+1; match by sorted node pair
+  std::map<std::pair<int32_t, int32_t>, std::vector<std::pair<int64_t, int>>> emap;
+  for (int64_t k = 0; k < nt; ++k)
+    for (int f = 0; f < 3; ++f) {
+      int32_t a = tv[k][f], b = tv[k][(f + 1) % 3];
+      emap[{std::min(a, b), std::max(a, b)}].push_back({k, f});
+    }
+  int64_t nedge = 0;
+  for (auto& kv : emap) {
+    auto& lst = kv.second;
+    if (lst.size() > 2) return -2;
+    if (lst.size() == 1 && periodic) return -2;
+    ++nedge;
+  }
+  M.E = nedge;
+  for (int64_t k = 0; k < nt; ++k) {
+    const Tri& t = M.tri[k];
+    for (int f = 0; f < 3; ++f) {
+      int f1 = (f + 1) % 3;
+      Face& F = M.face[k][f];
+      double ex = t.x[f1] - t.x[f], ey = t.y[f1] - t.y[f];
+      F.len = std::hypot(ex, ey);
+      F.nx = ey / F.len;
+      F.ny = -ex / F.len;
+      int32_t a = tv[k][f], b = tv[k][f1];
+      auto& lst = emap[{std::min(a, b), std::max(a, b)}];
+      if (lst.size() == 1) {
+        F.nb = -1;
+        F.nb_face = -1;
+        F.sx = F.sy = 0.0;
+        // mirror image of K across the face line
+        for (int v = 0; v < 3; ++v) {
+          double rx = t.x[v] - t.x[f], ry = t.y[v] - t.y[f];
+          double dn = rx * F.nx + ry * F.ny;
+          F.ghost.x[v] = t.x[v] - 2.0 * dn * F.nx;
+          F.ghost.y[v] = t.y[v] - 2.0 * dn * F.ny;
+        }
+        // keep the ghost counter-clockwise
+        std::swap(F.ghost.x[1], F.ghost.x[2]);
+        std::swap(F.ghost.y[1], F.ghost.y[2]);
+        continue;
+      }
+      auto other = lst[0].first == k && lst[0].second == f ? lst[1] : lst[0];
+      F.nb = static_cast<int>(other.first);
+      F.nb_face = other.second;
+      // translation from the neighbour's frame: compare the shared vertices
+      const Tri& tn = M.tri[other.first];
+      int g = other.second, g1 = (g + 1) % 3;
+      // neighbour's face runs b -> a
+      double sxa = t.x[f] - tn.x[g1], sya = t.y[f] - tn.y[g1];
+      double sxb = t.x[f1] - tn.x[g], syb = t.y[f1] - tn.y[g];
+      if (tv[other.first][g1] != a || tv[other.first][g] != b) return -2;
+      double tol = 1e-9 * (std::fabs(Lx) + std::fabs(Ly) + F.len);
+      if (std::fabs(sxa - sxb) > tol || std::fabs(sya - syb) > tol) return -2;
+      F.sx = sxa;
+      F.sy = sya;
+      if (!periodic && (std::fabs(F.sx) > tol || std::fabs(F.sy) > tol)) return -2;
+    }
+  }
+  return 0;
+}
+
+}  // namespace
+
+// ====================================================================== C API
+extern "C" {
+
+struct or_opts {
+  int eq;
+  int bc;
+  double box[4];
+  double adv[2];
+  double gas_gamma;
+  double lin_w[4];
+  double eps;
+  int linear_only;
+};
+
+void* or_mesh_new(const double* nodes, int64_t nn, const int32_t* tris, int64_t nt, const or_opts* o,
+                  int* status) {
+  Mesh* M = new Mesh();
+  M->o.eq = o->eq;
+  M->o.bc = o->bc;
+  for (int i = 0; i < 4; ++i) M->o.box[i] = o->box[i];
+  M->o.adv[0] = o->adv[0];
+  M->o.adv[1] = o->adv[1];
+  M->o.gas_gamma = o->gas_gamma;
+  for (int i = 0; i < 4; ++i) M->o.lin_w[i] = o->lin_w[i];
+  M->o.eps = o->eps;
+  M->o.linear_only = o->linear_only;
+  int st = build_mesh(*M, nodes, nn, tris, nt);
+  if (status) *status = st;
+  if (st != 0) {
+    delete M;
+    return nullptr;
+  }
+  return M;
+}
+
+void or_mesh_free(void* h) { delete static_cast<Mesh*>(h); }
+
+int or_mesh_sizes(void* h, int64_t* N, int64_t* E, int32_t* m) {
+  Mesh* M = static_cast<Mesh*>(h);
+  *N = M->N;
+  *E = M->E;
+  *m = M->m;
+  return 0;
+}
+
+// Per-cell geometry: area, centroid, and for each face the outward normal,
+// length, neighbour index (-1 = boundary) and translation.  face_out is
+// [N][3][6] = (nx, ny, len, nb, sx, sy).
+int or_geometry(void* h, double* area, double* cx, double* cy, double* face_out) {
+  Mesh* M = static_cast<Mesh*>(h);
+  for (int64_t k = 0; k < M->N; ++k) {
+    area[k] = M->area[k];
+    cx[k] = M->cx[k];
+    cy[k] = M->cy[k];
+    for (int f = 0; f < 3; ++f) {
+      const Face& F = M->face[k][f];
+      double* o = face_out + (k * 3 + f) * 6;
+      o[0] = F.nx;
+      o[1] = F.ny;
+      o[2] = F.len;
+      o[3] = F.nb;
+      o[4] = F.sx;
+      o[5] = F.sy;
+    }
+  }
+  return 0;
+}
+
+// Triangle vertices in the cell's own (unwrapped, counter-clockwise) frame, [N][3][2].
+int or_cell_vertices(void* h, double* out) {
+  Mesh* M = static_cast<Mesh*>(h);
+  for (int64_t k = 0; k < M->N; ++k)
+    for (int v = 0; v < 3; ++v) {
+      out[(k * 3 + v) * 2] = M->tri[k].x[v];
+      out[(k * 3 + v) * 2 + 1] = M->tri[k].y[v];
+    }
+  return 0;
+}
+
+// One step: s_in, s_out are [3][m][N] (averages of W, W_x, W_y).
+int or_step(void* h, const double* s_in, double* s_out, double dt, int nthr) {
+  return step_all(*static_cast<Mesh*>(h), s_in, s_out, dt, nthr);
+}
+
+int or_step_cells(void* h, const double* s_in, const int64_t* cells, int64_t nc, double* out, double dt,
+                  int nthr) {
+  return step_cells(*static_cast<Mesh*>(h), s_in, cells, nc, out, dt, nthr);
+}
+
+// nsteps steps in place with a fixed dt.
+int or_run(void* h, double* s, double dt, int64_t nsteps, int nthr) {
+  Mesh* M = static_cast<Mesh*>(h);
+  std::vector<double> tmp(3 * M->m * M->N);
+  for (int64_t n = 0; n < nsteps; ++n) {
+    int st = step_all(*M, s, tmp.data(), dt, nthr);
+    if (st) return st;
+    std::memcpy(s, tmp.data(), tmp.size() * sizeof(double));
+  }
+  return 0;
+}
+
+// Exact Jacobian-vector product of nsteps steps: (s, ds) -> (s_n, ds_n), in place.
+int or_jvp(void* h, double* s, double* ds, double dt, int64_t nsteps, int nthr) {
+  Mesh* M = static_cast<Mesh*>(h);
+  size_t n = 3 * M->m * M->N;
+  std::vector<Dual> a(n), b(n);
+  for (size_t i = 0; i < n; ++i) a[i] = Dual(s[i], ds[i]);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    int st = step_all(*M, a.data(), b.data(), dt, nthr);
+    if (st) return st;
+    std::swap(a, b);
+  }
+  for (size_t i = 0; i < n; ++i) {
+    s[i] = a[i].v;
+    ds[i] = a[i].d;
+  }
+  return 0;
+}
+
+// Reconstruction details of one cell: p[4][m][6] monomial coefficients about
+// the centroid, beta[m][4], omega[m][4], centroid[2].
+int or_recon_cell(void* h, const double* s, int64_t k, double* p, double* beta, double* omega,
+                  double* centroid) {
+  Mesh* M = static_cast<Mesh*>(h);
+  Recon<double> R;
+  if (!reconstruct(*M, s, k, R)) return -3;
+  for (int l = 0; l < 4; ++l)
+    for (int q = 0; q < M->m; ++q)
+      for (int j = 0; j < 6; ++j) p[(l * M->m + q) * 6 + j] = R.p[l][q][j];
+  for (int q = 0; q < M->m; ++q)
+    for (int l = 0; l < 4; ++l) {
+      beta[q * 4 + l] = R.beta[q][l];
+      omega[q * 4 + l] = R.omega[q][l];
+    }
+  centroid[0] = R.cx;
+  centroid[1] = R.cy;
+  return 0;
+}
+
+// Final reconstruction (eq. (recon)) of cell k at points (x, y) given in the
+// cell's own frame: out[np][m][6] = W, Wx, Wy, Wxx, Wxy, Wyy.
+int or_eval_recon(void* h, const double* s, int64_t k, const double* xy, int64_t np, double* out) {
+  Mesh* M = static_cast<Mesh*>(h);
+  Recon<double> R;
+  if (!reconstruct(*M, s, k, R)) return -3;
+  for (int64_t i = 0; i < np; ++i)
+    for (int q = 0; q < M->m; ++q) {
+      double D[6];
+      eval_recon(M->o, R, q, xy[2 * i], xy[2 * i + 1], D);
+      for (int j = 0; j < 6; ++j) out[(i * M->m + q) * 6 + j] = D[j];
+    }
+  return 0;
+}
+
+// Lax-Wendroff time derivatives at np points.  D is [np][6][m]; out is [np][4][m]
+// with rows W_t, W_tx, W_ty, W_tt.
+int or_lax_wendroff(const or_opts* oo, const double* D, int64_t np, double* out) {
+  Opts o{};
+  o.eq = oo->eq;
+  o.adv[0] = oo->adv[0];
+  o.adv[1] = oo->adv[1];
+  o.gas_gamma = oo->gas_gamma;
+  int m = ncomp(o.eq);
+  for (int64_t i = 0; i < np; ++i) {
+    double Dl[6][4], a[4], b[4], c[4], d[4];
+    for (int j = 0; j < 6; ++j)
+      for (int q = 0; q < m; ++q) Dl[j][q] = D[(i * 6 + j) * m + q];
+    lax_wendroff(o, m, Dl, a, b, c, d);
+    for (int q = 0; q < m; ++q) {
+      out[(i * 4 + 0) * m + q] = a[q];
+      out[(i * 4 + 1) * m + q] = b[q];
+      out[(i * 4 + 2) * m + q] = c[q];
+      out[(i * 4 + 3) * m + q] = d[q];
+    }
+  }
+  return 0;
+}
+
+// Local Lax-Friedrichs flux of Sec. 2.1 for one interface value pair:
+// Hhat = 1/2 (H(We) + H(Wi) - alpha (We - Wi)), H = F.n, alpha given.
+int or_llf(const or_opts* oo, const double* Wi, const double* We, double nx, double ny, double alpha,
+           double* out) {
+  Opts o{};
+  o.eq = oo->eq;
+  o.adv[0] = oo->adv[0];
+  o.adv[1] = oo->adv[1];
+  o.gas_gamma = oo->gas_gamma;
+  int m = ncomp(o.eq);
+  double fi[4], gi[4], fe[4], ge[4];
+  flux_fg(o, Wi, fi, gi);
+  flux_fg(o, We, fe, ge);
+  for (int q = 0; q < m; ++q)
+    out[q] = 0.5 * (fe[q] * nx + ge[q] * ny + fi[q] * nx + gi[q] * ny - alpha * (We[q] - Wi[q]));
+  return 0;
+}
+
+// Time step of the driver: cfl * min_K r_K / max_K lambda_K, with r_K the
+// inradius and lambda_K the largest signal speed over all directions at the
+// cell average.
+double or_max_dt(void* h, const double* s, double cfl) {
+  Mesh* M = static_cast<Mesh*>(h);
+  const Opts& o = M->o;
+  double rmin = 1e300, lmax = 0.0;
+  for (int64_t k = 0; k < M->N; ++k) {
+    double per = M->face[k][0].len + M->face[k][1].len + M->face[k][2].len;
+    rmin = std::min(rmin, 2.0 * M->area[k] / per);
+    double lam;
+    if (o.eq == 0) {
+      lam = std::hypot(o.adv[0], o.adv[1]);
+    } else if (o.eq == 1) {
+      lam = std::sqrt(2.0) * std::fabs(s[k]);
+    } else {
+      const int64_t N = M->N;
+      double r = s[k], u = s[N + k] / r, v = s[2 * N + k] / r;
+      double p = (o.gas_gamma - 1.0) * (s[3 * N + k] - 0.5 * r * (u * u + v * v));
+      lam = std::sqrt(u * u + v * v) + std::sqrt(o.gas_gamma * p / r);
+    }
+    lmax = std::max(lmax, lam);
+  }
+  return cfl * rmin / lmax;
+}
+
+double or_spectral_radius(const or_opts* oo, const double* W, double nx, double ny) {
+  Opts o{};
+  o.eq = oo->eq;
+  o.adv[0] = oo->adv[0];
+  o.adv[1] = oo->adv[1];
+  o.gas_gamma = oo->gas_gamma;
+  return spectral_radius(o, W, nx, ny);
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+"""Seeded synthetic triangular meshes (split squares with node jitter).
+
+The paper runs on GMSH meshes that are not available; these meshes stand in for
+them with the same kind of element (unstructured-looking triangles obtained by
+jittering the nodes of a split-square grid).  Nothing here belongs to the
+numerical method: the module only produces node coordinates and connectivity.
+
+Conventions
+-----------
+* Square (i, j) with corners a=(i,j), b=(i+1,j), c=(i+1,j+1), d=(i,j+1) is split
+  along the a-c diagonal into the triangles (a, b, c) and (a, c, d); both are
+  counter-clockwise.  Triangle 2*(j*n+i) is the lower one, 2*(j*n+i)+1 the
+  upper one.
+* Periodic meshes are tori: n x n distinct nodes, node (i, j) has index j*n+i and
+  triangles reference nodes modulo n.  Coordinates lie in [x0, x1) x [y0, y1);
+  a triangle that straddles a seam is unwrapped by the consumer.
+* Non-periodic meshes have (n+1) x (n+1) nodes.
+* Jitter: nodes strictly inside the box get an independent uniform offset in
+  [-f*h, f*h] per coordinate, drawn from ``numpy.random.default_rng(seed)`` as
+  one array of shape (rows, cols, 2) in row-major node order; nodes on the box
+  boundary (and on the periodic seams) stay on the grid.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Mesh2D:
+    nodes: np.ndarray      # (V, 2) float64
+    tris: np.ndarray       # (N, 3) int32, counter-clockwise
+    box: tuple             # (x0, x1, y0, y1)
+    periodic: bool
+    n: int                 # squares per side
+    h: float               # square side (x direction)
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.tris.shape[0])
+
+
+def split_square_mesh(n: int, box=(0.0, 1.0, 0.0, 1.0), jitter: float = 0.0,
+                      seed: int | None = None, periodic: bool = True) -> Mesh2D:
+    """Return an n x n split-square mesh of ``box`` (2 n^2 triangles)."""
+    if n < 3:
+        raise ValueError("need at least 3 squares per side")
+    x0, x1, y0, y1 = map(float, box)
+    hx = (x1 - x0) / n
+    hy = (y1 - y0) / n
+    nn = n if periodic else n + 1
+    jj, ii = np.meshgrid(np.arange(nn), np.arange(nn), indexing="ij")
+    xs = x0 + ii * hx
+    ys = y0 + jj * hy
+    if jitter and jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        off = rng.uniform(-1.0, 1.0, size=(nn, nn, 2))
+        inner = (ii >= 1) & (ii <= n - 1) & (jj >= 1) & (jj <= n - 1)
+        xs = xs + np.where(inner, off[..., 0] * jitter * hx, 0.0)
+        ys = ys + np.where(inner, off[..., 1] * jitter * hy, 0.0)
+    nodes = np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.float64)
+
+    def nid(i, j):
+        if periodic:
+            return (j % n) * n + (i % n)
+        return j * (n + 1) + i
+
+    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    I = I.ravel()
+    J = J.ravel()
+    a = nid(I, J)
+    b = nid(I + 1, J)
+    c = nid(I + 1, J + 1)
+    d = nid(I, J + 1)
+    tris = np.empty((2 * n * n, 3), dtype=np.int32)
+    tris[0::2] = np.stack([a, b, c], axis=1)
+    tris[1::2] = np.stack([a, c, d], axis=1)
+    return Mesh2D(nodes=nodes, tris=tris, box=(x0, x1, y0, y1), periodic=periodic, n=n, h=hx)
+
+
+def unwrapped_triangles(mesh: Mesh2D) -> np.ndarray:
+    """Vertex coordinates per triangle, (N, 3, 2), seams unwrapped about vertex 0."""
+    P = mesh.nodes[mesh.tris]                     # (N, 3, 2)
+    if mesh.periodic:
+        L = np.array([mesh.box[1] - mesh.box[0], mesh.box[3] - mesh.box[2]])
+        d = P - P[:, :1, :]
+        d -= L * np.round(d / L)
+        P = P[:, :1, :] + d
+    return P

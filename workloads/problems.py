@@ -1,0 +1,329 @@
+"""Seeded synthetic workloads: initial data, exact solutions and cell averages.
+
+Every array produced here is an *input* (or an exact reference solution) that is
+handed unchanged to both the CPU oracle and the GPU library.  The module holds
+none of the numerical method: it only evaluates the paper's initial conditions
+and integrates them exactly (to quadrature accuracy) over each triangle.
+
+State layout used throughout: ``state[3][m][N]`` float64 with block 0 the cell
+averages of W, block 1 the cell averages of W_x and block 2 those of W_y
+(the quantities of the paper's eq. (aver)).
+
+Quadrature (input preparation only):
+* cell averages of W: Duffy-collapsed 8 x 8 Gauss-Legendre rule per triangle;
+* cell averages of W_x, W_y: divergence theorem, 8-point Gauss-Legendre per edge;
+* the four-quadrant Riemann data is piecewise constant, so both are computed
+  exactly by clipping triangles and splitting edges at the quadrant lines.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable
+
+import numpy as np
+
+from .meshes import Mesh2D, split_square_mesh, unwrapped_triangles
+
+EQ_ADVECTION, EQ_BURGERS, EQ_EULER = 0, 1, 2
+GAMMA_GAS = 1.4
+
+_gl_x, _gl_w = np.polynomial.legendre.leggauss(8)
+_GL_T = 0.5 * (_gl_x + 1.0)          # nodes on [0, 1]
+_GL_W = 0.5 * _gl_w                  # weights summing to 1
+
+
+def _triangle_rule():
+    """Duffy-collapsed tensor rule on the reference triangle, weights sum to 1."""
+    u, v = np.meshgrid(_GL_T, _GL_T, indexing="ij")
+    wu, wv = np.meshgrid(_GL_W, _GL_W, indexing="ij")
+    # x = P0 + u (P1 - P0) + u v (P2 - P1); Jacobian 2|K| u
+    a1 = (u * (1.0 - v)).ravel()     # barycentric weight of P1
+    a2 = (u * v).ravel()             # barycentric weight of P2
+    w = (2.0 * wu * wv * u).ravel()
+    return a1, a2, w
+
+
+_TRI_A1, _TRI_A2, _TRI_W = _triangle_rule()
+
+
+# ----------------------------------------------------------------------------
+# pointwise initial data / exact solutions: f(x, y, t) -> (..., m)
+# ----------------------------------------------------------------------------
+
+def _prim_to_cons(rho, u, v, p, gamma=GAMMA_GAS):
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return np.stack([rho, rho * u, rho * v, E], axis=-1)
+
+
+def advection_sine(x, y, t, k=np.pi, a=(1.0, 1.0)):
+    """0.5 + sin(k (x + y)) translated with velocity a."""
+    return (0.5 + np.sin(k * ((x - a[0] * t) + (y - a[1] * t))))[..., None]
+
+
+def burgers_sine(x, y, t, k=0.5 * np.pi):
+    """Exact solution of u_t + (u^2/2)_x + (u^2/2)_y = 0 with u0 = 0.5 + sin(k(x+y)).
+
+    Characteristics: u = u0(x - u t, y - u t); solved by Newton's method, valid
+    before the breaking time 1/k (the paper's Example 4.1 uses T = 0.5/pi)."""
+    s = x + y
+    u = 0.5 + np.sin(k * s)
+    if t == 0.0:
+        return u[..., None]
+    for _ in range(60):
+        arg = k * (s - 2.0 * u * t)
+        F = u - 0.5 - np.sin(arg)
+        dF = 1.0 + 2.0 * k * t * np.cos(arg)
+        du = F / dF
+        u = u - du
+        if np.max(np.abs(du)) < 1e-15:
+            break
+    return u[..., None]
+
+
+def euler_density_wave(x, y, t):
+    """Paper Example 4.2: rho = 1 + 0.2 sin(pi/2 (x + y)), u = v = p = 1, translating."""
+    rho = 1.0 + 0.2 * np.sin(0.5 * np.pi * ((x - t) + (y - t)))
+    one = np.ones_like(rho)
+    return _prim_to_cons(rho, one, one, one)
+
+
+def make_vortex(center=(5.0, 5.0), strength=5.0, period=(10.0, 10.0), gamma=GAMMA_GAS):
+    """Paper Example 4.3 isentropic vortex, translating with velocity (1, 1).
+
+    The vortex centre is taken modulo the period (minimal image), which is how
+    the periodic initial condition is defined on the torus."""
+    cx, cy = center
+    Lx, Ly = period
+
+    def f(x, y, t):
+        dx = x - (cx + t)
+        dy = y - (cy + t)
+        dx = dx - Lx * np.round(dx / Lx)
+        dy = dy - Ly * np.round(dy / Ly)
+        r2 = dx * dx + dy * dy
+        e = np.exp(1.0 - r2)
+        T = 1.0 - strength ** 2 * (gamma - 1.0) / (8.0 * gamma * np.pi ** 2) * e
+        rho = T ** (1.0 / (gamma - 1.0))
+        g = strength / (2.0 * np.pi) * np.exp(0.5 * (1.0 - r2))
+        u = 1.0 - g * dy
+        v = 1.0 + g * dx
+        p = rho ** gamma
+        return _prim_to_cons(rho, u, v, p, gamma)
+
+    return f
+
+
+RIEMANN_QUADRANTS = (  # (rho, u, v, p) for quadrants 1..4 (x>0.5,y>0.5), (x<,y>), (x<,y<), (x>,y<)
+    (1.5, 0.0, 0.0, 1.5),
+    (0.5323, 1.206, 0.0, 0.3),
+    (0.138, 1.206, 1.206, 0.029),
+    (0.5323, 0.0, 1.206, 0.3),
+)
+
+
+def riemann_state(q, gamma=GAMMA_GAS):
+    rho, u, v, p = RIEMANN_QUADRANTS[q]
+    return _prim_to_cons(np.float64(rho), np.float64(u), np.float64(v), np.float64(p), gamma)
+
+
+def riemann_pointwise(x, y, t=0.0, split=(0.5, 0.5)):
+    q = np.where(x >= split[0], np.where(y >= split[1], 0, 3), np.where(y >= split[1], 1, 2))
+    states = np.stack([riemann_state(k) for k in range(4)])   # (4, 4)
+    return states[q]
+
+
+# ----------------------------------------------------------------------------
+# cell averages
+# ----------------------------------------------------------------------------
+
+def _chunks(N, size=65536):
+    for s in range(0, N, size):
+        yield slice(s, min(N, s + size))
+
+
+def cell_average_states(mesh: Mesh2D, f: Callable, t: float = 0.0) -> np.ndarray:
+    """[3][m][N] cell averages of f(., t), f_x and f_y for a smooth f."""
+    P = unwrapped_triangles(mesh)
+    N = P.shape[0]
+    out = None
+    for sl in _chunks(N):
+        Pc = P[sl]
+        P0, P1, P2 = Pc[:, 0, :], Pc[:, 1, :], Pc[:, 2, :]
+        X = P0[:, None, :] + _TRI_A1[None, :, None] * (P1 - P0)[:, None, :] \
+            + _TRI_A2[None, :, None] * (P2 - P0)[:, None, :]
+        vals = f(X[..., 0], X[..., 1], t)                     # (n, q, m)
+        m = vals.shape[-1]
+        if out is None:
+            out = np.zeros((3, m, N))
+        out[0, :, sl] = np.einsum("nqm,q->mn", vals, _TRI_W)
+        area = 0.5 * ((P1[:, 0] - P0[:, 0]) * (P2[:, 1] - P0[:, 1])
+                      - (P1[:, 1] - P0[:, 1]) * (P2[:, 0] - P0[:, 0]))
+        gx = np.zeros((m, Pc.shape[0]))
+        gy = np.zeros((m, Pc.shape[0]))
+        for k in range(3):
+            A = Pc[:, k, :]
+            B = Pc[:, (k + 1) % 3, :]
+            Y = A[:, None, :] + _GL_T[None, :, None] * (B - A)[:, None, :]
+            ev = f(Y[..., 0], Y[..., 1], t)                   # (n, 8, m)
+            line = np.einsum("nqm,q->mn", ev, _GL_W)          # mean of f along the edge
+            gx += line * (B[:, 1] - A[:, 1])[None, :]
+            gy -= line * (B[:, 0] - A[:, 0])[None, :]
+        out[1, :, sl] = gx / area[None, :]
+        out[2, :, sl] = gy / area[None, :]
+    return out
+
+
+def _clip(poly, axis, value, keep_ge):
+    """Clip a convex polygon (list of (x, y)) against x_axis >= value (or <)."""
+    out = []
+    n = len(poly)
+    for i in range(n):
+        A = poly[i]
+        B = poly[(i + 1) % n]
+        ina = (A[axis] >= value) if keep_ge else (A[axis] < value)
+        inb = (B[axis] >= value) if keep_ge else (B[axis] < value)
+        if ina:
+            out.append(A)
+        if ina != inb:
+            s = (value - A[axis]) / (B[axis] - A[axis])
+            out.append((A[0] + s * (B[0] - A[0]), A[1] + s * (B[1] - A[1])))
+    return out
+
+
+def _poly_area(poly):
+    if len(poly) < 3:
+        return 0.0
+    a = 0.0
+    for i in range(len(poly)):
+        x0, y0 = poly[i]
+        x1, y1 = poly[(i + 1) % len(poly)]
+        a += x0 * y1 - x1 * y0
+    return 0.5 * a
+
+
+def riemann_average_states(mesh: Mesh2D, split=(0.5, 0.5)) -> np.ndarray:
+    """Exact [3][4][N] averages of the piecewise-constant four-quadrant data."""
+    P = unwrapped_triangles(mesh)
+    N = P.shape[0]
+    cen = P.mean(axis=1)
+    out = np.zeros((3, 4, N))
+    out[0] = riemann_pointwise(cen[:, 0], cen[:, 1], 0.0, split).T
+    sx, sy = split
+    straddle = ((P[:, :, 0].min(1) < sx) & (P[:, :, 0].max(1) > sx)) | \
+               ((P[:, :, 1].min(1) < sy) & (P[:, :, 1].max(1) > sy))
+    states = np.stack([riemann_state(k) for k in range(4)])
+    for c in np.nonzero(straddle)[0]:
+        tri = [tuple(P[c, k]) for k in range(3)]
+        area = _poly_area(tri)
+        acc = np.zeros(4)
+        for q, (gx, gy) in enumerate(((True, True), (False, True), (False, False), (True, False))):
+            part = _clip(_clip(tri, 0, sx, gx), 1, sy, gy)
+            acc += _poly_area(part) * states[q]
+        out[0, :, c] = acc / area
+        gxs = np.zeros(4)
+        gys = np.zeros(4)
+        for k in range(3):
+            A = np.array(tri[k])
+            B = np.array(tri[(k + 1) % 3])
+            ts = [0.0, 1.0]
+            for ax, val in ((0, sx), (1, sy)):
+                den = B[ax] - A[ax]
+                if den != 0.0:
+                    s = (val - A[ax]) / den
+                    if 0.0 < s < 1.0:
+                        ts.append(s)
+            ts = sorted(ts)
+            line = np.zeros(4)
+            for t0, t1 in zip(ts[:-1], ts[1:]):
+                M = A + 0.5 * (t0 + t1) * (B - A)
+                line += (t1 - t0) * riemann_pointwise(np.array(M[0]), np.array(M[1]), 0.0, split)
+            gxs += line * (B[1] - A[1])
+            gys -= line * (B[0] - A[0])
+        out[1, :, c] = gxs / area
+        out[2, :, c] = gys / area
+    return out
+
+
+# ----------------------------------------------------------------------------
+# the workloads
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    eq: int
+    m: int
+    mesh: Mesh2D
+    state0: np.ndarray                  # [3][m][N]
+    T: float
+    cfl: float
+    exact: Callable | None = None       # f(x, y, t) -> (..., m), or None
+    adv: tuple = (1.0, 1.0)
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def bc(self) -> int:
+        return 0 if self.mesh.periodic else 1
+
+    def exact_state(self, t: float) -> np.ndarray:
+        if self.exact is None:
+            raise ValueError(f"{self.name}: no exact solution")
+        return cell_average_states(self.mesh, self.exact, t)
+
+
+def advection_workload(n=20, jitter=0.0, seed=1, T=0.5, cfl=0.3):
+    """2-D linear advection u_t + u_x + u_y = 0 on periodic [0,2]^2, u0 = 0.5 + sin(pi(x+y))."""
+    mesh = split_square_mesh(n, (0.0, 2.0, 0.0, 2.0), jitter, seed, periodic=True)
+    f = advection_sine
+    return Workload("advection", EQ_ADVECTION, 1, mesh, cell_average_states(mesh, f), T, cfl, f)
+
+
+def burgers_workload(n=160, jitter=0.1, seed=2, T=0.5 / np.pi, cfl=0.3, box=(0.0, 4.0, 0.0, 4.0)):
+    """2-D Burgers on a periodic square of side 4, u0 = 0.5 + sin(pi(x+y)/2)."""
+    mesh = split_square_mesh(n, box, jitter, seed, periodic=True)
+    f = burgers_sine
+    return Workload("burgers", EQ_BURGERS, 1, mesh, cell_average_states(mesh, f), T, cfl,
+                    f if T < 1.0 / np.pi else None)
+
+
+def density_wave_workload(n=16, jitter=0.1, seed=7, T=1.0, cfl=0.3):
+    """Paper Example 4.2 smooth Euler density wave on periodic (-2,2)^2."""
+    mesh = split_square_mesh(n, (-2.0, 2.0, -2.0, 2.0), jitter, seed, periodic=True)
+    f = euler_density_wave
+    return Workload("density_wave", EQ_EULER, 4, mesh, cell_average_states(mesh, f), T, cfl, f)
+
+
+def vortex_workload(n=320, jitter=0.1, seed=3, T=2.0, cfl=0.3, center=(5.0, 5.0)):
+    """Isentropic vortex (strength 5) on background (1,1,1,1) over periodic [0,10]^2."""
+    mesh = split_square_mesh(n, (0.0, 10.0, 0.0, 10.0), jitter, seed, periodic=True)
+    f = make_vortex(center)
+    return Workload("vortex", EQ_EULER, 4, mesh, cell_average_states(mesh, f), T, cfl, f)
+
+
+def riemann_workload(n=700, jitter=0.2, seed=4, T=0.3, cfl=0.3):
+    """Four-quadrant Euler Riemann problem on [0,1]^2 with transmissive boundaries."""
+    mesh = split_square_mesh(n, (0.0, 1.0, 0.0, 1.0), jitter, seed, periodic=False)
+    return Workload("riemann", EQ_EULER, 4, mesh, riemann_average_states(mesh), T, cfl, None)
+
+
+def perturbed_vortex_target_center(seed=5, sigma=0.3, base=(5.0, 5.0)):
+    """Centre of the target vortex for the adjoint misfit: base + N(0, sigma^2) per axis."""
+    rng = np.random.default_rng(seed)
+    d = rng.normal(0.0, sigma, size=2)
+    return (base[0] + float(d[0]), base[1] + float(d[1]))
+
+
+def fd_directions(N, count=32, seed=6):
+    """Unit-norm Gaussian directions over a density slice, shape (count, N)."""
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=(count, N))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def random_state(m, N, seed, scale=1.0, base=1.0):
+    """A seeded random positive state [3][m][N] for unit-level parity checks."""
+    rng = np.random.default_rng(seed)
+    s = np.empty((3, m, N))
+    s[0] = base + 0.1 * scale * rng.uniform(-1.0, 1.0, size=(m, N))
+    s[1:] = scale * rng.uniform(-1.0, 1.0, size=(2, m, N))
+    return s
