@@ -1,0 +1,179 @@
+"""Benchmark of the explicit ADER-HWENO step on one MI355X.
+
+Workload: 2-D Euler (gamma = 1.4) isentropic vortex of strength 5 on the
+periodic square [0,10]^2, 320 x 320 split squares with +-0.1h seeded node
+jitter (204,800 triangles).  A step is one call of hwe_step (reconstruction,
+edge and update kernels) on state already resident in HBM.
+
+Prints one JSON line: cell-steps/s of the FP64 step (``value``), the mixed
+(FP32 bulk) step and its speedup, the adjoint/forward time ratio, the roofline
+of the dominant kernel measured live with HIP events, and the CPU oracle timed
+on the host cores on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def kernel_bytes(N, E, m, s):
+    """Algorithmic bytes per launch of the three kernels (each array once).
+
+    s = bytes of the bulk real type (8 FP64, 4 mixed).  Counts the per-cell and
+    per-edge arrays each kernel must read or write at least once.
+    """
+    recon = N * (m * 8 + 2 * m * s + 12 + 55 * s + 9 * s + 8 + 3 * s + 6 * m * s)
+    edge = E * (8 + 24 + 8 * s + m * 8 + m * s) + N * (6 * m * s + m * 8)
+    update = N * (m * 8 + 12 + 12 + 6 * s + 8 + m * 8 + 2 * m * s) + E * (m * 8 + m * s)
+    return {"recon": recon, "edge": edge, "update": update}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_leg(wl, steps, warmup, precision):
+    import torch
+    from paper_2607_10809_amd.hwe import Mesh
+    mesh = Mesh.from_workload(wl, precision=precision)
+    w0, g0 = mesh.to_device(wl.state0)
+    dt = mesh.max_dt(w0, wl.cfl)
+    bufs = [(w0.clone(), g0.clone()), mesh.empty_state()]
+    stream = torch.cuda.current_stream()
+
+    def run(k, start=0):
+        for i in range(k):
+            a, b = bufs[(start + i) % 2], bufs[(start + i + 1) % 2]
+            mesh.step(a[0], a[1], dt, out=b)
+        return start + k
+
+    pos = run(warmup)
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    pos = run(steps, pos)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    ms = ev0.elapsed_time(ev1)
+    flags = mesh.check_state(bufs[pos % 2][0])
+    # per-kernel durations with events around each kernel (separate profiled loop)
+    nprof = min(steps, 2000)
+    mesh.profile_begin(nprof)
+    pos = run(nprof, pos)
+    kms, nk = mesh.profile_end()
+    torch.cuda.synchronize()
+    return dict(mesh=mesh, dt=dt, ms=ms, wall=t_wall, flags=flags, kernel_ms=[k / nk for k in kms])
+
+
+def cpu_leg(wl, budget_s=12.0):
+    from oracle import OracleMesh
+    om = OracleMesh.from_workload(wl)
+    dt = om.max_dt(wl.state0, wl.cfl)
+    s = wl.state0
+    t0 = time.perf_counter()
+    s = om.step(s, dt)
+    n = 1
+    while time.perf_counter() - t0 < budget_s:
+        s = om.step(s, dt)
+        n += 1
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=om.N * n / el, unit="cell-steps/s", cores=cores, kind="oracle",
+                sample=f"{n} full FP64 steps of the 204,800-triangle vortex mesh ({el:.1f} s wall)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--n", type=int, default=320, help="squares per side (default: 320 -> 204,800 triangles)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(2)
+    from paper_2607_10809_amd import _lib
+    _lib.load_library()
+    from workloads import vortex_workload
+
+    log("building workload ...")
+    wl = vortex_workload(n=args.n)
+    N = wl.mesh.n_cells
+    log(f"N = {N}; FP64 leg ...")
+    f64 = gpu_leg(wl, args.steps, args.warmup, "fp64")
+    log(f"FP64: {f64['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {f64['kernel_ms']}")
+    mix = gpu_leg(wl, args.steps, args.warmup, "mixed")
+    log(f"mixed: {mix['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {mix['kernel_ms']}")
+    E, m = f64["mesh"].E, f64["mesh"].m
+    value = N * args.steps / (f64["ms"] * 1e-3)
+    value_mixed = N * args.steps / (mix["ms"] * 1e-3)
+
+    names = ["recon", "edge", "update"]
+    kb64 = kernel_bytes(N, E, m, 8)
+    kbm = kernel_bytes(N, E, m, 4)
+    per_kernel = {}
+    for tag, leg, kb in (("fp64", f64, kb64), ("mixed", mix, kbm)):
+        per_kernel[tag] = {n: {"us": round(t * 1e3, 2), "alg_bytes": int(kb[n]),
+                               "GBps": round(kb[n] / (t * 1e-3) / 1e9, 1)}
+                           for n, t in zip(names, leg["kernel_ms"])}
+    dom = names[int(np.argmax(f64["kernel_ms"]))]
+    achieved = kb64[dom] / (f64["kernel_ms"][names.index(dom)] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"{dom}_kernel<euler,fp64>",
+                "per_launch_bytes": int(kb64[dom])}
+    step_bytes = sum(kb64.values())
+    out = {
+        "metric": "cell-steps/s FP64 vs FP32 + adjoint/forward time ratio, Euler 204,800 tris",
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f64["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"euler isentropic vortex, periodic [0,10]^2, {args.n}x{args.n} split squares "
+                               f"+-0.1h jitter seed 3 ({N} triangles)", "cells": N, "edges": E,
+                   "dt": f64["dt"], "parallelism": "1 GPU"},
+        "mixed": {"value": value_mixed, "ms_per_step": mix["ms"] / args.steps, "dtype": "f32 bulk + f64 averages/weights",
+                  "speedup_vs_fp64": value_mixed / value},
+        "adjoint_forward_ratio": None,
+        "step_alg_bytes": {"fp64": int(step_bytes), "mixed": int(sum(kbm.values()))},
+        "step_GBps": {"fp64": round(step_bytes / (f64["ms"] / args.steps * 1e-3) / 1e9, 1),
+                      "mixed": round(sum(kbm.values()) / (mix["ms"] / args.steps * 1e-3) / 1e9, 1)},
+        "kernels": per_kernel,
+        "roofline": roofline,
+        "state_flags": {"fp64": f64["flags"], "mixed": mix["flags"]},
+    }
+    if not args.no_cpu:
+        log("CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_leg(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * hwe.h -- C ABI of the MI355X (gfx950) explicit step of the compact
+ * ADER-HWENO finite-volume scheme on triangular meshes
+ * (Luo, Zhao, Qiu, Chen: "A compact simple HWENO scheme with ADER time
+ * discretization for hyperbolic conservation laws II: triangular meshes").
+ *
+ * The scheme advances, for every triangle K, the cell average of the solution
+ * W and the cell averages of W_x and W_y (Sec. 2.2, eq. (aver)) by one
+ * explicit step (eq. (flx) for the averages of W; eqs. (derave2d1)-(derave2d2)
+ * for the derivative averages).  Only plain pointers and sizes cross this
+ * boundary; no C++ or torch types.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns hwe_status (HWE_OK = 0).  On failure a message is
+ *    available from hwe_last_error() (thread-local) and no work is launched.
+ *  - Device pointers are HIP device memory on the mesh's device; "stream" is a
+ *    hipStream_t passed as void* (NULL = the default stream).  Launches are
+ *    asynchronous on that stream; the library never synchronises the device
+ *    inside hwe_step / hwe_step_adjoint.  Device faults surface at the caller's
+ *    next synchronisation.
+ *  - Cell order: the library renumbers cells along a Morton curve of their
+ *    centroids.  All state buffers are in this internal order;
+ *    hwe_mesh_cell_perm() gives the map to the caller's triangle order.
+ *  - State layout (structure of arrays, component-major):
+ *      wbar : double [m][N]          cell averages of W         (eq. (aver))
+ *      grad : [2][m][N]              averages of W_x, then W_y  (eq. (aver))
+ *             double for HWE_FP64, float for HWE_MIXED
+ *    m = 1 (advection, Burgers) or 4 (Euler: rho, rho u, rho v, E).
+ *  - A mesh handle owns device scratch; one handle must not be used by two
+ *    streams at once (calls on one handle serialise on the stream given).
+ *  - Memory given by the caller is never freed or reallocated by the library.
+ */
+#ifndef HWE_H
+#define HWE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hwe_mesh_s* hwe_mesh; /* opaque, library-owned */
+
+typedef enum {
+  HWE_OK = 0,
+  HWE_EINVAL = -1,     /* bad argument (null, aliasing, dt <= 0 or not finite, size) */
+  HWE_EMESH = -2,      /* degenerate / non-manifold / unmatched periodic mesh */
+  HWE_ESINGULAR = -3,  /* rank-deficient reconstruction least-squares system */
+  HWE_ENOMEM = -4,     /* host or device allocation failed */
+  HWE_EHIP = -5,       /* a HIP runtime call or kernel launch failed */
+  HWE_ENODEV = -6      /* operation needs a device but the handle is host-only */
+} hwe_status;
+
+typedef enum { HWE_ADVECTION = 0, HWE_BURGERS = 1, HWE_EULER = 2 } hwe_equation;
+typedef enum { HWE_BC_PERIODIC = 0, HWE_BC_TRANSMISSIVE = 1 } hwe_bc;
+typedef enum { HWE_FP64 = 0, HWE_MIXED = 1 } hwe_precision;
+
+typedef struct {
+  int32_t eq;             /* hwe_equation; linear advection u_t + a.grad u = 0,
+                             Burgers (Example 4.1), Euler gamma-law gas (eq. (2d)) */
+  int32_t bc;             /* hwe_bc: periodic (box is the period) or transmissive */
+  int32_t prec;           /* hwe_precision.  HWE_MIXED: FP32 tables, derivative
+                             averages, reconstruction coefficients, Lax-Wendroff and
+                             fluxes; FP64 cell averages of W, their accumulation,
+                             smoothness-indicator sums and nonlinear weights */
+  int32_t linear_weights; /* 1: omega = gamma (Step 3 weights only); 0: the
+                             nonlinear weights of Step 5, eq. (nonlinearweight) */
+  double box[4];          /* x0, x1, y0, y1 of the domain */
+  double adv[2];          /* advection velocity (HWE_ADVECTION) */
+  double gas_gamma;       /* ratio of specific heats (HWE_EULER), e.g. 1.4 */
+  double lin_w[4];        /* linear weights gamma_1..gamma_4 (Step 3): 0.94, 0.02 x3 */
+  double eps;             /* epsilon of eq. (nonlinearweight): 1e-8 */
+  int32_t device;         /* HIP device ordinal; -1 = host precompute only (no
+                             device memory; hwe_step etc. return HWE_ENODEV) */
+  int32_t reserved;       /* must be 0 */
+} hwe_opts;
+
+/* Fill *o with the paper's defaults: linear weights 0.94/0.02/0.02/0.02
+ * (Step 3), eps = 1e-8 (Step 5), gas_gamma = 1.4, adv = (1, 1), periodic unit
+ * box, FP64, device 0. */
+hwe_status hwe_opts_default(hwe_opts* o);
+
+/* Build a mesh handle (host FP64 precompute + one upload).
+ *  nodes : host double [n_nodes][2] vertex coordinates
+ *  tris  : host int32 [n_tris][3] vertex indices, any orientation
+ *  Periodic meshes are tori: triangles may reference nodes across the seams
+ *  and are unwrapped by minimal image about their first vertex.
+ * Precomputes geometry, the 2-point Gauss-Legendre points of every edge, the
+ * face-neighbour stencils {K0, K1, K2, K3} of Step 1 (Fig. 1; ghost mirror cells
+ * on transmissive boundaries) and, per cell, the linear maps of the
+ * constrained least-squares problems of Steps 1 and 2.  Copies the inputs;
+ * the caller keeps ownership.  Returns HWE_EMESH or HWE_ESINGULAR for bad
+ * meshes, HWE_EHIP / HWE_ENOMEM for device failures.  *out is valid only on
+ * HWE_OK. */
+hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tris, int64_t n_tris,
+                         const hwe_opts* opts, hwe_mesh* out);
+
+/* Release the handle and all its device memory (synchronises its device). */
+hwe_status hwe_mesh_destroy(hwe_mesh m);
+
+/* Sizes: number of cells N, edges E, and components m. Any pointer may be NULL. */
+hwe_status hwe_mesh_info(hwe_mesh m, int64_t* n_cells, int64_t* n_edges, int32_t* m_comp);
+
+/* perm_host[i] = caller's triangle index of internal cell i (host int64 [N]). */
+hwe_status hwe_mesh_cell_perm(hwe_mesh m, int64_t* perm_host);
+
+/* One explicit step of size dt (Sec. 2): reconstruction (Steps 1-6), the
+ * Lax-Wendroff procedure and Taylor extrapolation at the edge Gauss points,
+ * the space-time quadrature of the local Lax-Friedrichs flux (eqs. (fx),
+ * (flux)), the update of eq. (flx) and the Green-Gauss derivative averages
+ * (eqs. (derave2d2), (timeflux), (taylor2dtime)).
+ *  wbar_in, grad_in   : device, state at t_n (layouts above); read only
+ *  wbar_out, grad_out : device, state at t_n + dt; must not overlap the inputs
+ * Time rule: 3-point Gauss-Lobatto (0, dt/2, dt; weights 1/6, 4/6, 1/6) whose
+ * last node also gives the interface value of eq. (timeflux). */
+hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out,
+                    void* grad_out, double dt, void* stream);
+
+/* Vector-Jacobian product of hwe_step at the state (wbar_n, grad_n) with the
+ * same dt (dt is a constant, not differentiated):
+ *   (lam_wbar_n, lam_grad_n) = J(wbar_n, grad_n)^T (lam_wbar_np1, lam_grad_np1).
+ * Same layouts and precision as hwe_step; outputs must not overlap inputs.
+ * Non-smooth points: d|x| = sign(x) dx with sign(0) = 0; the max of the two
+ * spectral radii in the flux viscosity takes the edge's first cell (the one
+ * with the lower caller index) on ties. */
+hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n,
+                            const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n,
+                            void* lam_grad_n, double dt, void* stream);
+
+/* Largest stable step of the driver: dt = cfl * min_K r_K / max_K lambda_K
+ * (r_K inradius, lambda_K the largest signal speed at the cell average).
+ * Writes one double to device memory dt_dev. */
+hwe_status hwe_max_dt(hwe_mesh m, const double* wbar, double cfl, double* dt_dev, void* stream);
+
+/* State diagnostics into device int32 flags_dev[1] (overwritten):
+ * bit 0 = a non-finite cell average, bit 1 = density <= 0, bit 2 = pressure <= 0
+ * (bits 1-2 for Euler only). */
+hwe_status hwe_check_state(hwe_mesh m, const double* wbar, int32_t* flags_dev, void* stream);
+
+/* Reconstruction only (Steps 1-6) for kernel-level tests: R_out is device
+ * [6][m][N] of double (FP64) or float (MIXED) holding, per cell and component,
+ * the coefficients a0..a5 of R - Wbar in the monomial basis about the cell
+ * centroid: R(x,y) - Wbar = a0 + a1 X + a2 Y + a3 X^2 + a4 XY + a5 Y^2. */
+hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, void* R_out, void* stream);
+
+/* Host copy of a precomputed per-cell array for host-logic tests (works for
+ * host-only handles).  which: 0 = p1 map [55][N] (rows: c1..c5 of the
+ * zero-mean basis X, Y, X^2-Mxx, XY-Mxy, Y^2-Myy; columns: dW1..dW3, V0..V3,
+ * Y0..Y3), 1 = centroid [2][N], 2 = area [N], 3 = moments [3][N],
+ * 4 = neighbours [3][N] (as double; negative = boundary).  out is host double
+ * with room for the stated size. */
+hwe_status hwe_debug_host_array(hwe_mesh m, int32_t which, double* out);
+
+/* Per-kernel timing for measurement tools.  hwe_profile_begin arms HIP events
+ * around the three kernels of the next n_steps calls of hwe_step on this
+ * handle (the events are recorded on each call's stream; no synchronisation
+ * inside hwe_step).  hwe_profile_end synchronises on the recorded events and
+ * returns in ms_sum[3] the summed durations in milliseconds of the
+ * reconstruction, edge and update kernels, and in *n_steps_done the number of
+ * profiled steps; it disarms profiling. */
+hwe_status hwe_profile_begin(hwe_mesh m, int32_t n_steps);
+hwe_status hwe_profile_end(hwe_mesh m, double* ms_sum, int32_t* n_steps_done);
+
+/* Thread-local message for the last failing call on this thread. */
+const char* hwe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HWE_H */

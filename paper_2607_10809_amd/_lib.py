@@ -1,0 +1,76 @@
+"""ctypes view of the hwe C ABI (include/hwe.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhwe.so")
+
+HWE_OK = 0
+STATUS = {0: "HWE_OK", -1: "HWE_EINVAL", -2: "HWE_EMESH", -3: "HWE_ESINGULAR", -4: "HWE_ENOMEM",
+          -5: "HWE_EHIP", -6: "HWE_ENODEV"}
+EQUATIONS = {"advection": 0, "burgers": 1, "euler": 2}
+BCS = {"periodic": 0, "transmissive": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+
+class HweOpts(C.Structure):
+    _fields_ = [("eq", C.c_int32), ("bc", C.c_int32), ("prec", C.c_int32), ("linear_weights", C.c_int32),
+                ("box", C.c_double * 4), ("adv", C.c_double * 2), ("gas_gamma", C.c_double),
+                ("lin_w", C.c_double * 4), ("eps", C.c_double), ("device", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class HweError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library():
+    """Load libhwe.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2607_10809_amd.build` "
+                           "(the HIP library is required; there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, i64, i32 = C.c_void_p, C.POINTER(C.c_double), C.c_int64, C.c_int32
+    L.hwe_opts_default.argtypes = [C.POINTER(HweOpts)]
+    L.hwe_mesh_init.argtypes = [dp, i64, C.POINTER(C.c_int32), i64, C.POINTER(HweOpts), C.POINTER(vp)]
+    L.hwe_mesh_destroy.argtypes = [vp]
+    L.hwe_mesh_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]
+    L.hwe_mesh_cell_perm.argtypes = [vp, C.POINTER(i64)]
+    L.hwe_step.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp]
+    L.hwe_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_double, vp]
+    L.hwe_max_dt.argtypes = [vp, vp, C.c_double, vp, vp]
+    L.hwe_check_state.argtypes = [vp, vp, vp, vp]
+    L.hwe_debug_recon.argtypes = [vp, vp, vp, vp, vp]
+    L.hwe_debug_host_array.argtypes = [vp, i32, dp]
+    L.hwe_profile_begin.argtypes = [vp, i32]
+    L.hwe_profile_end.argtypes = [vp, dp, C.POINTER(i32)]
+    L.hwe_last_error.restype = C.c_char_p
+    for name in ("hwe_opts_default", "hwe_mesh_init", "hwe_mesh_destroy", "hwe_mesh_info", "hwe_mesh_cell_perm",
+                 "hwe_step", "hwe_step_adjoint", "hwe_max_dt", "hwe_check_state", "hwe_debug_recon",
+                 "hwe_debug_host_array", "hwe_profile_begin", "hwe_profile_end"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != HWE_OK:
+        msg = _lib.hwe_last_error().decode() if _lib is not None else ""
+        raise HweError(status, msg)
+
+
+def exported_symbols():
+    """Names declared in include/hwe.h (for the export test)."""
+    return ["hwe_opts_default", "hwe_mesh_init", "hwe_mesh_destroy", "hwe_mesh_info", "hwe_mesh_cell_perm",
+            "hwe_step", "hwe_step_adjoint", "hwe_max_dt", "hwe_check_state", "hwe_debug_recon",
+            "hwe_debug_host_array", "hwe_profile_begin", "hwe_profile_end", "hwe_last_error"]

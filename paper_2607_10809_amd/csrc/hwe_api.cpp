@@ -1,0 +1,299 @@
+// C-ABI entry points of the hwe library: argument validation, handle lifetime
+// and dispatch to the host precompute and the HIP launchers.  No C++
+// exception crosses this boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hwe_internal.h"
+
+namespace hwe {
+namespace {
+thread_local std::string g_last_error;
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+hwe_status need_device(hwe_mesh m) {
+  if (!m) {
+    set_error("null mesh handle");
+    return HWE_EINVAL;
+  }
+  if (m->d.device < 0) {
+    set_error("host-only mesh handle (opts.device = -1)");
+    return HWE_ENODEV;
+  }
+  return HWE_OK;
+}
+
+hwe_status check_dt(double dt) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) {
+    set_error("dt must be positive and finite");
+    return HWE_EINVAL;
+  }
+  return HWE_OK;
+}
+
+size_t real_size(hwe_mesh m) { return m->opts.prec == HWE_FP64 ? sizeof(double) : sizeof(float); }
+
+hwe_status set_dev(hwe_mesh m) {
+  hipError_t e = hipSetDevice(m->d.device);
+  if (e != hipSuccess) {
+    set_error(std::string("hipSetDevice: ") + hipGetErrorString(e));
+    return HWE_EHIP;
+  }
+  return HWE_OK;
+}
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace hwe
+
+using namespace hwe;
+
+extern "C" {
+
+const char* hwe_last_error(void) { return g_last_error.c_str(); }
+
+hwe_status hwe_opts_default(hwe_opts* o) {
+  if (!o) {
+    set_error("null opts");
+    return HWE_EINVAL;
+  }
+  std::memset(o, 0, sizeof(*o));
+  o->eq = HWE_ADVECTION;
+  o->bc = HWE_BC_PERIODIC;
+  o->prec = HWE_FP64;
+  o->linear_weights = 0;
+  o->box[0] = 0.0;
+  o->box[1] = 1.0;
+  o->box[2] = 0.0;
+  o->box[3] = 1.0;
+  o->adv[0] = 1.0;
+  o->adv[1] = 1.0;
+  o->gas_gamma = 1.4;
+  o->lin_w[0] = 0.94;
+  o->lin_w[1] = 0.02;
+  o->lin_w[2] = 0.02;
+  o->lin_w[3] = 0.02;
+  o->eps = 1e-8;
+  o->device = 0;
+  return HWE_OK;
+}
+
+hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tris, int64_t n_tris,
+                         const hwe_opts* opts, hwe_mesh* out) {
+  if (!nodes || !tris || !opts || !out) {
+    set_error("null argument");
+    return HWE_EINVAL;
+  }
+  *out = nullptr;
+  const hwe_opts& o = *opts;
+  if (o.eq < HWE_ADVECTION || o.eq > HWE_EULER || o.bc < 0 || o.bc > 1 || o.prec < 0 || o.prec > 1 ||
+      o.reserved != 0) {
+    set_error("invalid option value");
+    return HWE_EINVAL;
+  }
+  if (!(o.lin_w[0] > 0) || !(o.eps > 0) || (o.eq == HWE_EULER && !(o.gas_gamma > 1.0))) {
+    set_error("invalid weights, eps or gas_gamma");
+    return HWE_EINVAL;
+  }
+  hwe_mesh_s* M = new (std::nothrow) hwe_mesh_s();
+  if (!M) {
+    set_error("out of host memory");
+    return HWE_ENOMEM;
+  }
+  M->opts = o;
+  hwe_status s;
+  try {
+    s = build_host_mesh(nodes, n_nodes, tris, n_tris, o, M->h);
+  } catch (const std::bad_alloc&) {
+    set_error("out of host memory");
+    s = HWE_ENOMEM;
+  } catch (...) {
+    set_error("unexpected failure in the host precompute");
+    s = HWE_EMESH;
+  }
+  if (s == HWE_OK && o.device >= 0) {
+    if (M->h.N >= (int64_t(1) << 31) / 6 || M->h.E >= (int64_t(1) << 29)) {
+      set_error("mesh too large for 32-bit device indexing");
+      s = HWE_EINVAL;
+    } else {
+      s = upload_mesh(M);
+    }
+  }
+  if (s != HWE_OK) {
+    free_device(M);
+    delete M;
+    return s;
+  }
+  *out = M;
+  return HWE_OK;
+}
+
+hwe_status hwe_mesh_destroy(hwe_mesh m) {
+  if (!m) return HWE_OK;
+  free_device(m);
+  delete m;
+  return HWE_OK;
+}
+
+hwe_status hwe_mesh_info(hwe_mesh m, int64_t* n_cells, int64_t* n_edges, int32_t* m_comp) {
+  if (!m) {
+    set_error("null mesh handle");
+    return HWE_EINVAL;
+  }
+  if (n_cells) *n_cells = m->h.N;
+  if (n_edges) *n_edges = m->h.E;
+  if (m_comp) *m_comp = m->h.m;
+  return HWE_OK;
+}
+
+hwe_status hwe_mesh_cell_perm(hwe_mesh m, int64_t* perm_host) {
+  if (!m || !perm_host) {
+    set_error("null argument");
+    return HWE_EINVAL;
+  }
+  std::memcpy(perm_host, m->h.perm.data(), sizeof(int64_t) * m->h.N);
+  return HWE_OK;
+}
+
+hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,
+                    double dt, void* stream) {
+  hwe_status s = need_device(m);
+  if (s != HWE_OK) return s;
+  if ((s = check_dt(dt)) != HWE_OK) return s;
+  if (!wbar_in || !grad_in || !wbar_out || !grad_out) {
+    set_error("null state pointer");
+    return HWE_EINVAL;
+  }
+  const size_t N = size_t(m->h.N), mm = size_t(m->h.m);
+  const size_t wb = mm * N * sizeof(double), gb = 2 * mm * N * real_size(m);
+  if (overlaps(wbar_in, wb, wbar_out, wb) || overlaps(wbar_in, wb, grad_out, gb) ||
+      overlaps(grad_in, gb, wbar_out, wb) || overlaps(grad_in, gb, grad_out, gb) ||
+      overlaps(wbar_out, wb, grad_out, gb)) {
+    set_error("output buffers overlap the inputs or each other");
+    return HWE_EINVAL;
+  }
+  if ((s = set_dev(m)) != HWE_OK) return s;
+  return launch_step(m, wbar_in, grad_in, wbar_out, grad_out, dt, stream);
+}
+
+hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n, const double* lam_wbar_np1,
+                            const void* lam_grad_np1, double* lam_wbar_n, void* lam_grad_n, double dt, void* stream) {
+  hwe_status s = need_device(m);
+  if (s != HWE_OK) return s;
+  if ((s = check_dt(dt)) != HWE_OK) return s;
+  if (!wbar_n || !grad_n || !lam_wbar_np1 || !lam_grad_np1 || !lam_wbar_n || !lam_grad_n) {
+    set_error("null state pointer");
+    return HWE_EINVAL;
+  }
+  const size_t N = size_t(m->h.N), mm = size_t(m->h.m);
+  const size_t wb = mm * N * sizeof(double), gb = 2 * mm * N * real_size(m);
+  const void* ins[4] = {wbar_n, grad_n, lam_wbar_np1, lam_grad_np1};
+  const size_t insz[4] = {wb, gb, wb, gb};
+  for (int k = 0; k < 4; ++k)
+    if (overlaps(ins[k], insz[k], lam_wbar_n, wb) || overlaps(ins[k], insz[k], lam_grad_n, gb)) {
+      set_error("output buffers overlap the inputs");
+      return HWE_EINVAL;
+    }
+  if (overlaps(lam_wbar_n, wb, lam_grad_n, gb)) {
+    set_error("output buffers overlap each other");
+    return HWE_EINVAL;
+  }
+  if ((s = set_dev(m)) != HWE_OK) return s;
+  return launch_adjoint(m, wbar_n, grad_n, lam_wbar_np1, lam_grad_np1, lam_wbar_n, lam_grad_n, dt, stream);
+}
+
+hwe_status hwe_max_dt(hwe_mesh m, const double* wbar, double cfl, double* dt_dev, void* stream) {
+  hwe_status s = need_device(m);
+  if (s != HWE_OK) return s;
+  if (!wbar || !dt_dev || !(cfl > 0.0) || !std::isfinite(cfl)) {
+    set_error("null pointer or invalid cfl");
+    return HWE_EINVAL;
+  }
+  if ((s = set_dev(m)) != HWE_OK) return s;
+  return launch_max_dt(m, wbar, cfl, dt_dev, stream);
+}
+
+hwe_status hwe_check_state(hwe_mesh m, const double* wbar, int32_t* flags_dev, void* stream) {
+  hwe_status s = need_device(m);
+  if (s != HWE_OK) return s;
+  if (!wbar || !flags_dev) {
+    set_error("null pointer");
+    return HWE_EINVAL;
+  }
+  if ((s = set_dev(m)) != HWE_OK) return s;
+  return launch_check(m, wbar, flags_dev, stream);
+}
+
+hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, void* R_out, void* stream) {
+  hwe_status s = need_device(m);
+  if (s != HWE_OK) return s;
+  if (!wbar || !grad || !R_out) {
+    set_error("null pointer");
+    return HWE_EINVAL;
+  }
+  if ((s = set_dev(m)) != HWE_OK) return s;
+  return launch_recon(m, wbar, grad, R_out, stream);
+}
+
+hwe_status hwe_profile_begin(hwe_mesh m, int32_t n_steps) {
+  hwe_status s = need_device(m);
+  if (s != HWE_OK) return s;
+  if (n_steps <= 0 || n_steps > (1 << 20)) {
+    set_error("n_steps out of range");
+    return HWE_EINVAL;
+  }
+  if ((s = set_dev(m)) != HWE_OK) return s;
+  return profile_begin(m, n_steps);
+}
+
+hwe_status hwe_profile_end(hwe_mesh m, double* ms_sum, int32_t* n_steps_done) {
+  hwe_status s = need_device(m);
+  if (s != HWE_OK) return s;
+  if (!ms_sum || !n_steps_done) {
+    set_error("null pointer");
+    return HWE_EINVAL;
+  }
+  if ((s = set_dev(m)) != HWE_OK) return s;
+  int n = 0;
+  s = profile_end(m, ms_sum, &n);
+  *n_steps_done = n;
+  return s;
+}
+
+hwe_status hwe_debug_host_array(hwe_mesh m, int32_t which, double* out) {
+  if (!m || !out) {
+    set_error("null argument");
+    return HWE_EINVAL;
+  }
+  const HostMesh& h = m->h;
+  switch (which) {
+    case 0:
+      std::memcpy(out, h.p1.data(), h.p1.size() * sizeof(double));
+      return HWE_OK;
+    case 1:
+      std::memcpy(out, h.cen.data(), h.cen.size() * sizeof(double));
+      return HWE_OK;
+    case 2:
+      std::memcpy(out, h.area.data(), h.area.size() * sizeof(double));
+      return HWE_OK;
+    case 3:
+      std::memcpy(out, h.mom.data(), h.mom.size() * sizeof(double));
+      return HWE_OK;
+    case 4:
+      for (size_t k = 0; k < h.nbr.size(); ++k) out[k] = double(h.nbr[k]);
+      return HWE_OK;
+    default:
+      set_error("unknown array id");
+      return HWE_EINVAL;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Internal declarations of the hwe library (host precompute + device state).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hwe.h"
+
+namespace hwe {
+
+// Thread-local error message set by a failing C-ABI call.
+void set_error(const std::string& msg);
+
+// Number of double entries of the per-cell Step-1 map (5 coefficients x 11 inputs).
+constexpr int kP1 = 55;
+// Per-cell Step-2 data: (dx, dy, 1/(1 + dx^2 + dy^2)) for each of the three faces.
+constexpr int kP2 = 9;
+// Per-edge geometry: nx, ny, length, then the Gauss-point offsets (X, Y) from the
+// centroid of the edge's first cell (points 0, 1) and of its second cell (0, 1).
+constexpr int kEG = 11;
+
+// Everything precomputed on the host, in the internal (Morton) cell order.
+struct HostMesh {
+  int64_t N = 0, E = 0, NB = 0;
+  int m = 1;
+  std::vector<int64_t> perm;       // internal cell -> caller triangle
+  std::vector<double> cen;         // [2][N] centroid (cell's own frame)
+  std::vector<double> area;        // [N]
+  std::vector<double> mom;         // [3][N] central second moments Mxx, Mxy, Myy
+  std::vector<int32_t> nbr;        // [3][N] neighbour across face f; -(b+1) for boundary face b
+  std::vector<double> bnd_n;       // [2][NB] outward unit normal of boundary face b
+  std::vector<double> p1;          // [55][N] Step-1 map (row-major 5 x 11 per cell)
+  std::vector<double> p2;          // [9][N] Step-2 data
+  std::vector<int32_t> cell_edge;  // [3][N] (edge << 1) | (cell is the edge's second cell)
+  std::vector<double> nl;          // [6][N] outward normal times length: x of faces 0..2, then y
+  std::vector<double> inv_area;    // [N]
+  std::vector<int32_t> ecell;      // [2][E] first cell (lower caller index), second cell or -1
+  std::vector<double> egeo;        // [11][E]
+  double rmin = 0.0;               // smallest inradius
+};
+
+// Device copies (FP64 always, FP32 copies for the mixed path) and scratch.
+struct DevMesh {
+  int device = -1;
+  // connectivity
+  int32_t* nbr = nullptr;
+  int32_t* cell_edge = nullptr;
+  int32_t* ecell = nullptr;
+  // FP64 geometry / tables
+  double* bnd_n = nullptr;
+  double* area = nullptr;
+  double* mom = nullptr;
+  double* p1 = nullptr;
+  double* p2 = nullptr;
+  double* nl = nullptr;
+  double* inv_area = nullptr;
+  double* enl = nullptr;    // [3][E] edge normal and length (FP64 in both precisions)
+  double* egp = nullptr;    // [8][E] Gauss-point offsets (FP64 path)
+  // FP32 copies for the mixed path
+  float* p1f = nullptr;
+  float* p2f = nullptr;
+  float* nlf = nullptr;
+  float* egpf = nullptr;
+  float* momf = nullptr;
+  // scratch: reconstruction coefficients [6][m][N] (double or float by
+  // precision), edge flux [m][E] (double) and interface-value offset [m][E]
+  // (double or float)
+  void* R = nullptr;
+  void* F = nullptr;
+  void* G = nullptr;
+  // reductions
+  double* red = nullptr;   // [kRedBlocks]
+  int32_t* redi = nullptr; // [kRedBlocks]
+  // per-kernel event profiling (hwe_profile_begin / hwe_profile_end)
+  std::vector<void*> prof_ev;  // hipEvent_t, 4 per profiled step
+  int prof_cap = 0, prof_n = 0;
+  void* prof_stream = nullptr;
+};
+
+constexpr int kRedBlocks = 1024;
+
+}  // namespace hwe
+
+struct hwe_mesh_s {
+  hwe_opts opts;
+  hwe::HostMesh h;
+  hwe::DevMesh d;
+};
+
+namespace hwe {
+// Host precompute (hwe_mesh.cpp).  Returns HWE_OK or an error status with the
+// message set.
+hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* tris, int64_t n_tris,
+                           const hwe_opts& o, HostMesh& h);
+// Device upload / release (hwe_kernels.hip).
+hwe_status upload_mesh(hwe_mesh_s* M);
+void free_device(hwe_mesh_s* M);
+// Launchers (hwe_kernels.hip).  All asynchronous on stream.
+hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out,
+                       void* grad_out, double dt, void* stream);
+hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, void* R_out, void* stream);
+hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_n, const double* lw,
+                          const void* lg, double* lw_out, void* lg_out, double dt, void* stream);
+hwe_status launch_max_dt(hwe_mesh_s* M, const double* wbar, double cfl, double* dt_dev, void* stream);
+hwe_status launch_check(hwe_mesh_s* M, const double* wbar, int32_t* flags, void* stream);
+hwe_status profile_begin(hwe_mesh_s* M, int n_steps);
+hwe_status profile_end(hwe_mesh_s* M, double* ms_sum, int* n_done);
+}  // namespace hwe

@@ -1,0 +1,479 @@
+// HIP kernels of the explicit ADER-HWENO step for gfx950, and their launchers.
+// The per-item arithmetic lives in hwe_step_math.h.
+//
+// One step = three kernels on the caller's stream, none of which uses atomics:
+//   recon_kernel  : one work-item per cell.  Gathers the 4-cell stencil, applies
+//                   the precomputed least-squares maps (Steps 1-2), smoothness
+//                   indicators and nonlinear weights in FP64 (Steps 4-5) and
+//                   writes the final reconstruction R - Wbar (Step 6) as six
+//                   monomial coefficients per component.
+//   edge_kernel   : four work-items per edge: (side, Gauss point).  Each
+//                   evaluates R and its derivatives at its point, runs the
+//                   Lax-Wendroff procedure, the Taylor extrapolation at the
+//                   Lobatto nodes 0, dt/2, dt, and the time integral of the
+//                   normal flux; lanes are then combined with cross-lane
+//                   shuffles into the local Lax-Friedrichs edge flux F_e and the
+//                   edge integral of the interface value at t_n + dt.
+//   update_kernel : one work-item per cell gathers its three edges: eq. (flx)
+//                   accumulated in FP64, and the Green-Gauss derivative
+//                   averages, eq. (derave2d2), written in a form that is exactly
+//                   zero for a constant state.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+
+#include "hwe_internal.h"
+#include "hwe_math.h"
+#include "hwe_step_math.h"
+
+namespace hwe {
+namespace {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------- kernels
+// One work-item per (cell, component); the M lanes of a cell are adjacent, so
+// their table loads hit the same addresses.
+template <int EQ, class Real>
+__global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, const double* __restrict__ wbar,
+                                                        const Real* __restrict__ grad,
+                                                        const int32_t* __restrict__ nbr,
+                                                        const double* __restrict__ bnd_n,
+                                                        const Real* __restrict__ p1, const Real* __restrict__ p2,
+                                                        const double* __restrict__ area,
+                                                        const Real* __restrict__ mom, Real* __restrict__ R) {
+  constexpr int M = NComp<EQ>::m;
+  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int i = gid / M, q = gid - (gid / M) * M;
+  if (i >= N) return;
+  recon_point<EQ, Real>(i, q, N, NB, P, wbar, grad, nbr, bnd_n, p1, p2, area, mom, R);
+}
+
+template <class Real> __device__ __forceinline__ Real xor_shfl(Real v, int mask) { return __shfl_xor(v, mask); }
+
+// Four work-items per edge (side, Gauss point), adjacent in the wave.
+template <int EQ, class Real>
+__global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, double dt,
+                                                       const double* __restrict__ wbar,
+                                                       const Real* __restrict__ R,
+                                                       const int32_t* __restrict__ ecell,
+                                                       const double* __restrict__ enl,
+                                                       const Real* __restrict__ egp, double* __restrict__ F,
+                                                       Real* __restrict__ G) {
+  constexpr int M = NComp<EQ>::m;
+  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int e = gid >> 2, side = (gid >> 1) & 1, g = gid & 1;
+  const bool valid = e < E;
+  Real AH[M], AD[M], AT[M];
+  edge_lane<EQ, Real>(valid ? e : -1, side, g, E, N, P, dt, wbar, R, ecell, enl, egp, AH, AD, AT);
+  // Gauss points (weights 1/2 each): combine lanes g = 0, 1
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    AH[q] = Real(0.5) * (AH[q] + xor_shfl(AH[q], 1));
+    AD[q] = Real(0.5) * (AD[q] + xor_shfl(AD[q], 1));
+    AT[q] = Real(0.5) * (AT[q] + xor_shfl(AT[q], 1));
+  }
+  // the other side's sums
+  Real OH[M], OD[M], OT[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    OH[q] = xor_shfl(AH[q], 2);
+    OD[q] = xor_shfl(AD[q], 2);
+    OT[q] = xor_shfl(AT[q], 2);
+  }
+  if (!valid || side != 0) return;
+  if (g == 0)
+    edge_flux<EQ, Real>(e, E, N, P, wbar, ecell, enl, AH, AD, OH, OD, F);
+  else
+    edge_value<EQ, Real>(e, E, ecell, AT, OT, G);
+}
+
+template <int EQ, class Real>
+__global__ __launch_bounds__(kBlock) void update_kernel(int N, int E, double dt, const double* __restrict__ wbar,
+                                                         const int32_t* __restrict__ nbr,
+                                                         const int32_t* __restrict__ cell_edge,
+                                                         const Real* __restrict__ nl,
+                                                         const double* __restrict__ inv_area,
+                                                         const double* __restrict__ F, const Real* __restrict__ G,
+                                                         double* __restrict__ wout, Real* __restrict__ gout) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= N) return;
+  update_point<EQ, Real>(i, N, E, dt, wbar, nbr, cell_edge, nl, inv_area, F, G, wout, gout);
+}
+
+// ---------------------------------------------------------------- reductions
+template <int EQ>
+__global__ __launch_bounds__(kBlock) void max_speed_kernel(int N, Params P, const double* __restrict__ wbar,
+                                                            double* __restrict__ part) {
+  constexpr int M = NComp<EQ>::m;
+  __shared__ double sh[kBlock];
+  double mx = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    double W[M];
+    for (int q = 0; q < M; ++q) W[q] = wbar[q * N + i];
+    double s = max_speed<EQ>(P, W);
+    mx = s > mx ? s : mx;
+    if (s != s) mx = s;  // propagate NaN
+  }
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      double o = sh[threadIdx.x + w];
+      double a = sh[threadIdx.x];
+      sh[threadIdx.x] = (o > a || o != o) ? o : a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kBlock) void finish_dt_kernel(int nparts, const double* __restrict__ part, double num,
+                                                            double* __restrict__ dt) {
+  __shared__ double sh[kBlock];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) {
+    double o = part[i];
+    mx = (o > mx || o != o) ? o : mx;
+  }
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      double o = sh[threadIdx.x + w];
+      double a = sh[threadIdx.x];
+      sh[threadIdx.x] = (o > a || o != o) ? o : a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dt[0] = num / sh[0];
+}
+
+template <int EQ>
+__global__ __launch_bounds__(kBlock) void check_kernel(int N, Params P, const double* __restrict__ wbar,
+                                                        int32_t* __restrict__ part) {
+  constexpr int M = NComp<EQ>::m;
+  __shared__ int32_t sh[kBlock];
+  int32_t fl = 0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    double W[M];
+    for (int q = 0; q < M; ++q) {
+      W[q] = wbar[q * N + i];
+      if (!isfinite(W[q])) fl |= 1;
+    }
+    if constexpr (EQ == EQ_EUL) {
+      if (!(W[0] > 0.0)) fl |= 2;
+      double p = (P.gam - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+      if (!(p > 0.0)) fl |= 4;
+    }
+  }
+  sh[threadIdx.x] = fl;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] |= sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kBlock) void finish_or_kernel(int nparts, const int32_t* __restrict__ part,
+                                                            int32_t* __restrict__ out) {
+  __shared__ int32_t sh[kBlock];
+  int32_t fl = 0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) fl |= part[i];
+  sh[threadIdx.x] = fl;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] |= sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// ---------------------------------------------------------------- helpers
+hwe_status hip_fail(hipError_t err, const char* what) {
+  std::ostringstream s;
+  s << what << ": " << hipGetErrorString(err);
+  set_error(s.str());
+  return HWE_EHIP;
+}
+
+template <class T>
+hwe_status dev_copy(T** dst, const T* src, size_t n) {
+  hipError_t err = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(n, 1) * sizeof(T));
+  if (err != hipSuccess) return hip_fail(err, "hipMalloc");
+  if (n) {
+    err = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+    if (err != hipSuccess) return hip_fail(err, "hipMemcpy");
+  }
+  return HWE_OK;
+}
+template <class T>
+hwe_status dev_copy_f32(float** dst, const std::vector<T>& src) {
+  std::vector<float> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = float(src[i]);
+  return dev_copy(dst, tmp.data(), tmp.size());
+}
+hwe_status dev_alloc(void** dst, size_t bytes) {
+  hipError_t err = hipMalloc(dst, std::max<size_t>(bytes, 16));
+  if (err != hipSuccess) return hip_fail(err, "hipMalloc");
+  return HWE_OK;
+}
+
+unsigned grid_for(int64_t items) { return unsigned((items + kBlock - 1) / kBlock); }
+
+template <int EQ, class Real>
+hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, const Real* grad_in, double* wbar_out,
+                     Real* grad_out, double dt, hipStream_t st, const Real* p1, const Real* p2, const Real* nl,
+                     const Real* egp, const Real* mom) {
+  const HostMesh& h = M->h;
+  const DevMesh& d = M->d;
+  const int N = int(h.N), E = int(h.E), NB = int(h.NB);
+  Real* R = static_cast<Real*>(d.R);
+  double* F = static_cast<double*>(d.F);
+  Real* G = static_cast<Real*>(d.G);
+  constexpr int Mc = NComp<EQ>::m;
+  // optional per-kernel events (profiling mode only)
+  hipEvent_t* ev = nullptr;
+  if (d.prof_n < d.prof_cap) ev = reinterpret_cast<hipEvent_t*>(&M->d.prof_ev[4 * size_t(d.prof_n)]);
+  if (ev) hipEventRecord(ev[0], st);
+  hipLaunchKernelGGL((recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * Mc)), dim3(kBlock), 0, st, N, NB, P, wbar_in, grad_in,
+                     d.nbr, d.bnd_n, p1, p2, d.area, mom, R);
+  if (ev) hipEventRecord(ev[1], st);
+  hipLaunchKernelGGL((edge_kernel<EQ, Real>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, P, dt,
+                     wbar_in, R, d.ecell, d.enl, egp, F, G);
+  if (ev) hipEventRecord(ev[2], st);
+  hipLaunchKernelGGL((update_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, dt, wbar_in, d.nbr,
+                     d.cell_edge, nl, d.inv_area, F, G, wbar_out, grad_out);
+  if (ev) {
+    hipEventRecord(ev[3], st);
+    ++M->d.prof_n;
+  }
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return hip_fail(err, "kernel launch");
+  return HWE_OK;
+}
+
+template <int EQ, class Real>
+hwe_status recon_impl(hwe_mesh_s* M, const Params& P, const double* wbar, const Real* grad, Real* R, hipStream_t st,
+                      const Real* p1, const Real* p2, const Real* mom) {
+  const HostMesh& h = M->h;
+  const DevMesh& d = M->d;
+  const int N = int(h.N), NB = int(h.NB);
+  constexpr int Mc = NComp<EQ>::m;
+  hipLaunchKernelGGL((recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * Mc)), dim3(kBlock), 0, st, N, NB, P, wbar, grad, d.nbr,
+                     d.bnd_n, p1, p2, d.area, mom, R);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return hip_fail(err, "kernel launch");
+  return HWE_OK;
+}
+
+}  // namespace
+
+Params params_of(const hwe_opts& o) {
+  Params P;
+  P.ax = o.adv[0];
+  P.ay = o.adv[1];
+  P.gam = o.gas_gamma;
+  for (int l = 0; l < 4; ++l) P.lw[l] = o.lin_w[l];
+  P.eps = o.eps;
+  P.linear = o.linear_weights ? 1 : 0;
+  return P;
+}
+
+hwe_status upload_mesh(hwe_mesh_s* M) {
+  const HostMesh& h = M->h;
+  DevMesh& d = M->d;
+  d.device = M->opts.device;
+  hipError_t err = hipSetDevice(d.device);
+  if (err != hipSuccess) return hip_fail(err, "hipSetDevice");
+  hwe_status s;
+#define HWE_TRY(x)           \
+  do {                       \
+    s = (x);                 \
+    if (s != HWE_OK) return s; \
+  } while (0)
+  HWE_TRY(dev_copy(&d.nbr, h.nbr.data(), h.nbr.size()));
+  HWE_TRY(dev_copy(&d.cell_edge, h.cell_edge.data(), h.cell_edge.size()));
+  HWE_TRY(dev_copy(&d.ecell, h.ecell.data(), h.ecell.size()));
+  HWE_TRY(dev_copy(&d.bnd_n, h.bnd_n.data(), h.bnd_n.size()));
+  HWE_TRY(dev_copy(&d.area, h.area.data(), h.area.size()));
+  HWE_TRY(dev_copy(&d.inv_area, h.inv_area.data(), h.inv_area.size()));
+  const size_t N = size_t(h.N), E = size_t(h.E), m = size_t(h.m);
+  HWE_TRY(dev_copy(&d.enl, h.egeo.data(), 3 * E));
+  if (M->opts.prec == HWE_FP64) {
+    HWE_TRY(dev_copy(&d.mom, h.mom.data(), h.mom.size()));
+    HWE_TRY(dev_copy(&d.p1, h.p1.data(), h.p1.size()));
+    HWE_TRY(dev_copy(&d.p2, h.p2.data(), h.p2.size()));
+    HWE_TRY(dev_copy(&d.nl, h.nl.data(), h.nl.size()));
+    HWE_TRY(dev_copy(&d.egp, h.egeo.data() + 3 * E, 8 * E));
+  } else {
+    HWE_TRY(dev_copy_f32(&d.momf, h.mom));
+    HWE_TRY(dev_copy_f32(&d.p1f, h.p1));
+    HWE_TRY(dev_copy_f32(&d.p2f, h.p2));
+    HWE_TRY(dev_copy_f32(&d.nlf, h.nl));
+    HWE_TRY(dev_copy_f32(&d.egpf, std::vector<double>(h.egeo.begin() + 3 * E, h.egeo.end())));
+  }
+  const size_t rs = M->opts.prec == HWE_FP64 ? sizeof(double) : sizeof(float);
+  HWE_TRY(dev_alloc(&d.R, 6 * m * N * rs));
+  HWE_TRY(dev_alloc(&d.F, m * E * sizeof(double)));
+  HWE_TRY(dev_alloc(&d.G, m * E * rs));
+  HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.red), kRedBlocks * sizeof(double)));
+  HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.redi), kRedBlocks * sizeof(int32_t)));
+#undef HWE_TRY
+  return HWE_OK;
+}
+
+void free_device(hwe_mesh_s* M) {
+  DevMesh& d = M->d;
+  if (d.device < 0) return;
+  hipSetDevice(d.device);
+  hipDeviceSynchronize();
+  void* ptrs[] = {d.nbr, d.cell_edge, d.ecell, d.bnd_n, d.area, d.mom, d.p1,   d.p2, d.nl, d.inv_area, d.enl,
+                  d.egp, d.p1f,       d.p2f,   d.nlf,   d.egpf, d.momf, d.R,  d.F,  d.G,  d.red,      d.redi};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  for (void* e : d.prof_ev) hipEventDestroy(static_cast<hipEvent_t>(e));
+  d = DevMesh();
+}
+
+hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,
+                       double dt, void* stream) {
+  const Params P = params_of(M->opts);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevMesh& d = M->d;
+  if (M->opts.prec == HWE_FP64) {
+    auto gi = static_cast<const double*>(grad_in);
+    auto go = static_cast<double*>(grad_out);
+    switch (M->opts.eq) {
+      case HWE_ADVECTION:
+        return step_impl<EQ_ADV, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+      case HWE_BURGERS:
+        return step_impl<EQ_BUR, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+      default:
+        return step_impl<EQ_EUL, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+    }
+  }
+  auto gi = static_cast<const float*>(grad_in);
+  auto go = static_cast<float*>(grad_out);
+  switch (M->opts.eq) {
+    case HWE_ADVECTION:
+      return step_impl<EQ_ADV, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1f, d.p2f, d.nlf, d.egpf, d.momf);
+    case HWE_BURGERS:
+      return step_impl<EQ_BUR, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1f, d.p2f, d.nlf, d.egpf, d.momf);
+    default:
+      return step_impl<EQ_EUL, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1f, d.p2f, d.nlf, d.egpf, d.momf);
+  }
+}
+
+hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, void* R_out, void* stream) {
+  const Params P = params_of(M->opts);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevMesh& d = M->d;
+  if (M->opts.prec == HWE_FP64) {
+    auto g = static_cast<const double*>(grad);
+    auto R = static_cast<double*>(R_out);
+    switch (M->opts.eq) {
+      case HWE_ADVECTION: return recon_impl<EQ_ADV, double>(M, P, wbar, g, R, st, d.p1, d.p2, d.mom);
+      case HWE_BURGERS: return recon_impl<EQ_BUR, double>(M, P, wbar, g, R, st, d.p1, d.p2, d.mom);
+      default: return recon_impl<EQ_EUL, double>(M, P, wbar, g, R, st, d.p1, d.p2, d.mom);
+    }
+  }
+  auto g = static_cast<const float*>(grad);
+  auto R = static_cast<float*>(R_out);
+  switch (M->opts.eq) {
+    case HWE_ADVECTION: return recon_impl<EQ_ADV, float>(M, P, wbar, g, R, st, d.p1f, d.p2f, d.momf);
+    case HWE_BURGERS: return recon_impl<EQ_BUR, float>(M, P, wbar, g, R, st, d.p1f, d.p2f, d.momf);
+    default: return recon_impl<EQ_EUL, float>(M, P, wbar, g, R, st, d.p1f, d.p2f, d.momf);
+  }
+}
+
+hwe_status launch_max_dt(hwe_mesh_s* M, const double* wbar, double cfl, double* dt_dev, void* stream) {
+  const Params P = params_of(M->opts);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int N = int(M->h.N);
+  const int nb = std::min<int>(kRedBlocks, int(grid_for(N)));
+  switch (M->opts.eq) {
+    case HWE_ADVECTION:
+      hipLaunchKernelGGL(max_speed_kernel<EQ_ADV>, dim3(nb), dim3(kBlock), 0, st, N, P, wbar, M->d.red);
+      break;
+    case HWE_BURGERS:
+      hipLaunchKernelGGL(max_speed_kernel<EQ_BUR>, dim3(nb), dim3(kBlock), 0, st, N, P, wbar, M->d.red);
+      break;
+    default:
+      hipLaunchKernelGGL(max_speed_kernel<EQ_EUL>, dim3(nb), dim3(kBlock), 0, st, N, P, wbar, M->d.red);
+  }
+  hipLaunchKernelGGL(finish_dt_kernel, dim3(1), dim3(kBlock), 0, st, nb, M->d.red, cfl * M->h.rmin, dt_dev);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return hip_fail(err, "kernel launch");
+  return HWE_OK;
+}
+
+hwe_status launch_check(hwe_mesh_s* M, const double* wbar, int32_t* flags, void* stream) {
+  const Params P = params_of(M->opts);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int N = int(M->h.N);
+  const int nb = std::min<int>(kRedBlocks, int(grid_for(N)));
+  switch (M->opts.eq) {
+    case HWE_ADVECTION:
+      hipLaunchKernelGGL(check_kernel<EQ_ADV>, dim3(nb), dim3(kBlock), 0, st, N, P, wbar, M->d.redi);
+      break;
+    case HWE_BURGERS:
+      hipLaunchKernelGGL(check_kernel<EQ_BUR>, dim3(nb), dim3(kBlock), 0, st, N, P, wbar, M->d.redi);
+      break;
+    default:
+      hipLaunchKernelGGL(check_kernel<EQ_EUL>, dim3(nb), dim3(kBlock), 0, st, N, P, wbar, M->d.redi);
+  }
+  hipLaunchKernelGGL(finish_or_kernel, dim3(1), dim3(kBlock), 0, st, nb, M->d.redi, flags);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return hip_fail(err, "kernel launch");
+  return HWE_OK;
+}
+
+hwe_status profile_begin(hwe_mesh_s* M, int n_steps) {
+  DevMesh& d = M->d;
+  for (void* e : d.prof_ev) hipEventDestroy(static_cast<hipEvent_t>(e));
+  d.prof_ev.assign(4 * size_t(n_steps), nullptr);
+  for (auto& e : d.prof_ev) {
+    hipEvent_t h;
+    hipError_t err = hipEventCreate(&h);
+    if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
+    e = h;
+  }
+  d.prof_cap = n_steps;
+  d.prof_n = 0;
+  return HWE_OK;
+}
+
+hwe_status profile_end(hwe_mesh_s* M, double* ms_sum, int* n_done) {
+  DevMesh& d = M->d;
+  ms_sum[0] = ms_sum[1] = ms_sum[2] = 0.0;
+  for (int k = 0; k < d.prof_n; ++k) {
+    hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(&d.prof_ev[4 * size_t(k)]);
+    hipError_t err = hipEventSynchronize(ev[3]);
+    if (err != hipSuccess) return hip_fail(err, "hipEventSynchronize");
+    for (int j = 0; j < 3; ++j) {
+      float ms = 0.f;
+      err = hipEventElapsedTime(&ms, ev[j], ev[j + 1]);
+      if (err != hipSuccess) return hip_fail(err, "hipEventElapsedTime");
+      ms_sum[j] += ms;
+    }
+  }
+  *n_done = d.prof_n;
+  for (void* e : d.prof_ev) hipEventDestroy(static_cast<hipEvent_t>(e));
+  d.prof_ev.clear();
+  d.prof_cap = d.prof_n = 0;
+  return HWE_OK;
+}
+
+hwe_status launch_adjoint(hwe_mesh_s*, const double*, const void*, const double*, const void*, double*, void*, double,
+                          void*) {
+  set_error("hwe_step_adjoint: not available in this build");
+  return HWE_EINVAL;
+}
+
+}  // namespace hwe

@@ -1,0 +1,259 @@
+// Point-wise math of the step shared by the forward and adjoint kernels:
+// flux functions, spectral radii and the Lax-Wendroff procedure.
+//
+// Lax-Wendroff (Sec. 2.1).  The time derivatives at a Gauss point follow from
+// the conservation law W_t = -(f(W))_x - (g(W))_y applied to the quadratic
+// reconstruction.  Instead of forming f' and f'' explicitly, the fluxes are
+// evaluated on truncated Taylor polynomials ("jets") of the reconstruction about
+// the point:
+//  * a spatial jet holds the coefficients (c, x, y, xx, xy, yy) of
+//    c + x X + y Y + xx X^2 + xy XY + yy Y^2; pushing it through f and g gives
+//    W_t = -(f.x + g.y), W_tx = -(2 f.xx + g.xy), W_ty = -(f.xy + 2 g.yy),
+//    which are the paper's first three Lax-Wendroff formulas;
+//  * a time extension (t, xt, yt) with W.t = W_t, W.xt = W_tx, W.yt = W_ty gives
+//    W_tt = -(f.xt + g.yt) = -(f''[W_t, W_x] + f' W_tx + g''[W_t, W_y] + g' W_ty).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hwe {
+
+enum { EQ_ADV = 0, EQ_BUR = 1, EQ_EUL = 2 };
+template <int EQ> struct NComp {
+  static constexpr int m = EQ == EQ_EUL ? 4 : 1;
+};
+
+struct Params {
+  double ax, ay;   // advection velocity
+  double gam;      // ratio of specific heats
+  double lw[4];    // linear weights gamma_1..4
+  double eps;      // epsilon of the nonlinear weights
+  int linear;      // 1: omega = gamma
+};
+
+template <class T> struct SJ {  // spatial jet
+  T c, x, y, xx, xy, yy;
+};
+template <class T> struct TJ {  // time extension of a spatial jet
+  T t, xt, yt;
+};
+
+template <class T> __host__ __device__ __forceinline__ SJ<T> sj_mul(const SJ<T>& a, const SJ<T>& b) {
+  SJ<T> r;
+  r.c = a.c * b.c;
+  r.x = a.c * b.x + a.x * b.c;
+  r.y = a.c * b.y + a.y * b.c;
+  r.xx = a.c * b.xx + a.x * b.x + a.xx * b.c;
+  r.xy = a.c * b.xy + a.x * b.y + a.y * b.x + a.xy * b.c;
+  r.yy = a.c * b.yy + a.y * b.y + a.yy * b.c;
+  return r;
+}
+template <class T> __host__ __device__ __forceinline__ SJ<T> sj_recip(const SJ<T>& a) {
+  SJ<T> r;
+  T r1 = T(1) / a.c, r2 = r1 * r1, r3 = r2 * r1;
+  r.c = r1;
+  r.x = -a.x * r2;
+  r.y = -a.y * r2;
+  r.xx = a.x * a.x * r3 - a.xx * r2;
+  r.xy = T(2) * a.x * a.y * r3 - a.xy * r2;
+  r.yy = a.y * a.y * r3 - a.yy * r2;
+  return r;
+}
+template <class T> __host__ __device__ __forceinline__ SJ<T> sj_add(const SJ<T>& a, const SJ<T>& b) {
+  return SJ<T>{a.c + b.c, a.x + b.x, a.y + b.y, a.xx + b.xx, a.xy + b.xy, a.yy + b.yy};
+}
+template <class T> __host__ __device__ __forceinline__ SJ<T> sj_sub(const SJ<T>& a, const SJ<T>& b) {
+  return SJ<T>{a.c - b.c, a.x - b.x, a.y - b.y, a.xx - b.xx, a.xy - b.xy, a.yy - b.yy};
+}
+template <class T> __host__ __device__ __forceinline__ SJ<T> sj_scale(T s, const SJ<T>& a) {
+  return SJ<T>{s * a.c, s * a.x, s * a.y, s * a.xx, s * a.xy, s * a.yy};
+}
+// time extension of a product / reciprocal (a, b spatial parts, at, bt time parts)
+template <class T>
+__host__ __device__ __forceinline__ TJ<T> tj_mul(const SJ<T>& a, const TJ<T>& at, const SJ<T>& b, const TJ<T>& bt) {
+  TJ<T> r;
+  r.t = a.c * bt.t + at.t * b.c;
+  r.xt = a.c * bt.xt + a.x * bt.t + at.t * b.x + at.xt * b.c;
+  r.yt = a.c * bt.yt + a.y * bt.t + at.t * b.y + at.yt * b.c;
+  return r;
+}
+template <class T>
+__host__ __device__ __forceinline__ TJ<T> tj_recip(const SJ<T>& a, const TJ<T>& at, const SJ<T>& r) {
+  T r2 = r.c * r.c, r3 = r2 * r.c;
+  TJ<T> o;
+  o.t = -at.t * r2;
+  o.xt = T(2) * a.x * at.t * r3 - at.xt * r2;
+  o.yt = T(2) * a.y * at.t * r3 - at.yt * r2;
+  return o;
+}
+template <class T> __host__ __device__ __forceinline__ TJ<T> tj_add(const TJ<T>& a, const TJ<T>& b) {
+  return TJ<T>{a.t + b.t, a.xt + b.xt, a.yt + b.yt};
+}
+template <class T> __host__ __device__ __forceinline__ TJ<T> tj_sub(const TJ<T>& a, const TJ<T>& b) {
+  return TJ<T>{a.t - b.t, a.xt - b.xt, a.yt - b.yt};
+}
+template <class T> __host__ __device__ __forceinline__ TJ<T> tj_scale(T s, const TJ<T>& a) {
+  return TJ<T>{s * a.t, s * a.xt, s * a.yt};
+}
+
+// Lax-Wendroff at one point.  D[j][q], j = W, Wx, Wy, Wxx, Wxy, Wyy.
+// Outputs W_t and W_tt per component.
+template <int EQ, class T>
+__host__ __device__ __forceinline__ void lax_wendroff(const Params& P, const T (&D)[6][NComp<EQ>::m],
+                                                     T (&Wt)[NComp<EQ>::m], T (&Wtt)[NComp<EQ>::m]) {
+  if constexpr (EQ == EQ_ADV) {
+    const T ax = T(P.ax), ay = T(P.ay);
+    T wt = -(ax * D[1][0] + ay * D[2][0]);
+    T wtx = -(ax * D[3][0] + ay * D[4][0]);
+    T wty = -(ax * D[4][0] + ay * D[5][0]);
+    Wt[0] = wt;
+    Wtt[0] = -(ax * wtx + ay * wty);
+  } else if constexpr (EQ == EQ_BUR) {
+    SJ<T> J{D[0][0], D[1][0], D[2][0], T(0.5) * D[3][0], D[4][0], T(0.5) * D[5][0]};
+    SJ<T> s = sj_scale(T(0.5), sj_mul(J, J));
+    TJ<T> Jt;
+    Jt.t = -(s.x + s.y);
+    Jt.xt = -(T(2) * s.xx + s.xy);
+    Jt.yt = -(s.xy + T(2) * s.yy);
+    TJ<T> st = tj_scale(T(0.5), tj_mul(J, Jt, J, Jt));
+    Wt[0] = Jt.t;
+    Wtt[0] = -(st.xt + st.yt);
+  } else {
+    const T gm1 = T(P.gam - 1.0);
+    SJ<T> J[4];
+    for (int q = 0; q < 4; ++q) J[q] = SJ<T>{D[0][q], D[1][q], D[2][q], T(0.5) * D[3][q], D[4][q], T(0.5) * D[5][q]};
+    const SJ<T>& rho = J[0];
+    const SJ<T>& mx = J[1];
+    const SJ<T>& my = J[2];
+    const SJ<T>& En = J[3];
+    SJ<T> r = sj_recip(rho);
+    SJ<T> u = sj_mul(mx, r), v = sj_mul(my, r);
+    SJ<T> mxu = sj_mul(mx, u), myv = sj_mul(my, v), muv = sj_mul(mx, v);
+    SJ<T> ke = sj_scale(T(0.5), sj_add(mxu, myv));
+    SJ<T> p = sj_scale(gm1, sj_sub(En, ke));
+    SJ<T> H = sj_add(En, p);
+    SJ<T> uH = sj_mul(u, H), vH = sj_mul(v, H);
+    SJ<T> f1 = sj_add(mxu, p), g2 = sj_add(myv, p);
+    // f = (mx, f1, muv, uH), g = (my, muv, g2, vH)
+    TJ<T> Jt[4];
+    Jt[0] = TJ<T>{-(mx.x + my.y), -(T(2) * mx.xx + my.xy), -(mx.xy + T(2) * my.yy)};
+    Jt[1] = TJ<T>{-(f1.x + muv.y), -(T(2) * f1.xx + muv.xy), -(f1.xy + T(2) * muv.yy)};
+    Jt[2] = TJ<T>{-(muv.x + g2.y), -(T(2) * muv.xx + g2.xy), -(muv.xy + T(2) * g2.yy)};
+    Jt[3] = TJ<T>{-(uH.x + vH.y), -(T(2) * uH.xx + vH.xy), -(uH.xy + T(2) * vH.yy)};
+    TJ<T> rt = tj_recip(rho, Jt[0], r);
+    TJ<T> ut = tj_mul(mx, Jt[1], r, rt), vt = tj_mul(my, Jt[2], r, rt);
+    TJ<T> mxut = tj_mul(mx, Jt[1], u, ut), myvt = tj_mul(my, Jt[2], v, vt), muvt = tj_mul(mx, Jt[1], v, vt);
+    TJ<T> ket = tj_scale(T(0.5), tj_add(mxut, myvt));
+    TJ<T> pt = tj_scale(gm1, tj_sub(Jt[3], ket));
+    TJ<T> Ht = tj_add(Jt[3], pt);
+    TJ<T> uHt = tj_mul(u, ut, H, Ht), vHt = tj_mul(v, vt, H, Ht);
+    for (int q = 0; q < 4; ++q) Wt[q] = Jt[q].t;
+    Wtt[0] = -(Jt[1].xt + Jt[2].yt);
+    Wtt[1] = -((mxut.xt + pt.xt) + muvt.yt);
+    Wtt[2] = -(muvt.xt + (myvt.yt + pt.yt));
+    Wtt[3] = -(uHt.xt + vHt.yt);
+  }
+}
+
+// Normal flux H(W) = f(W) nx + g(W) ny.
+template <int EQ, class T>
+__host__ __device__ __forceinline__ void normal_flux(const Params& P, const T (&W)[NComp<EQ>::m], T nx, T ny,
+                                                    T (&H)[NComp<EQ>::m]) {
+  if constexpr (EQ == EQ_ADV) {
+    H[0] = (T(P.ax) * nx + T(P.ay) * ny) * W[0];
+  } else if constexpr (EQ == EQ_BUR) {
+    H[0] = T(0.5) * W[0] * W[0] * (nx + ny);
+  } else {
+    T r = T(1) / W[0];
+    T u = W[1] * r, v = W[2] * r;
+    T un = u * nx + v * ny;
+    T p = T(P.gam - 1.0) * (W[3] - T(0.5) * (W[1] * u + W[2] * v));
+    H[0] = W[0] * un;
+    H[1] = W[1] * un + p * nx;
+    H[2] = W[2] * un + p * ny;
+    H[3] = (W[3] + p) * un;
+  }
+}
+
+// Offset form of the normal flux: dH = H(Wb + d) - H(Wb), written so that it
+// is formed from the offset d without cancellation (exactly 0 for d = 0).
+// For Euler with u = mx/rho etc. at Wb and primes at Wb + d:
+//   du = (dmx - u drho)/rho',  dke = (dmx u + mx' du + dmy v + my' dv)/2,
+//   dp = (gamma-1)(dE - dke),  dun = du nx + dv ny,
+//   dH = (drho un + rho' dun, dmx un + mx' dun + dp nx, dmy un + my' dun + dp ny,
+//         (dE + dp) un + (E' + p') dun).
+template <int EQ, class T> struct FluxBase {
+  T w[NComp<EQ>::m];
+  T u, v, p;
+};
+template <int EQ, class T>
+__host__ __device__ __forceinline__ FluxBase<EQ, T> flux_base(const Params& P, const double (&W)[NComp<EQ>::m]) {
+  FluxBase<EQ, T> b;
+  for (int q = 0; q < NComp<EQ>::m; ++q) b.w[q] = T(W[q]);
+  b.u = b.v = b.p = T(0);
+  if constexpr (EQ == EQ_EUL) {
+    const double r = 1.0 / W[0];
+    const double u = W[1] * r, v = W[2] * r;
+    b.u = T(u);
+    b.v = T(v);
+    b.p = T((P.gam - 1.0) * (W[3] - 0.5 * (W[1] * u + W[2] * v)));
+  }
+  return b;
+}
+template <int EQ, class T>
+__host__ __device__ __forceinline__ void normal_flux_delta(const Params& P, const FluxBase<EQ, T>& b,
+                                                          const T (&d)[NComp<EQ>::m], T nx, T ny,
+                                                          T (&dH)[NComp<EQ>::m]) {
+  if constexpr (EQ == EQ_ADV) {
+    dH[0] = (T(P.ax) * nx + T(P.ay) * ny) * d[0];
+  } else if constexpr (EQ == EQ_BUR) {
+    dH[0] = T(0.5) * (T(2) * b.w[0] + d[0]) * d[0] * (nx + ny);
+  } else {
+    const T rho1 = b.w[0] + d[0];
+    const T mx1 = b.w[1] + d[1], my1 = b.w[2] + d[2];
+    const T ir = T(1) / rho1;
+    const T du = (d[1] - b.u * d[0]) * ir;
+    const T dv = (d[2] - b.v * d[0]) * ir;
+    const T dke = T(0.5) * (d[1] * b.u + mx1 * du + d[2] * b.v + my1 * dv);
+    const T dp = T(P.gam - 1.0) * (d[3] - dke);
+    const T un = b.u * nx + b.v * ny;
+    const T dun = du * nx + dv * ny;
+    dH[0] = d[0] * un + rho1 * dun;
+    dH[1] = d[1] * un + mx1 * dun + dp * nx;
+    dH[2] = d[2] * un + my1 * dun + dp * ny;
+    dH[3] = (d[3] + dp) * un + ((b.w[3] + d[3]) + (b.p + dp)) * dun;
+  }
+}
+
+// Largest |eigenvalue| of d(F.n)/dW at a cell average (flux viscosity alpha).
+template <int EQ>
+__host__ __device__ __forceinline__ double spectral_radius(const Params& P, const double (&W)[NComp<EQ>::m], double nx,
+                                                          double ny) {
+  if constexpr (EQ == EQ_ADV) {
+    return fabs(P.ax * nx + P.ay * ny);
+  } else if constexpr (EQ == EQ_BUR) {
+    return fabs(W[0] * (nx + ny));
+  } else {
+    double r = 1.0 / W[0];
+    double u = W[1] * r, v = W[2] * r;
+    double p = (P.gam - 1.0) * (W[3] - 0.5 * (W[1] * u + W[2] * v));
+    return fabs(u * nx + v * ny) + sqrt(P.gam * p * r);
+  }
+}
+
+// Largest signal speed over all directions at a cell average (time-step rule).
+template <int EQ>
+__host__ __device__ __forceinline__ double max_speed(const Params& P, const double (&W)[NComp<EQ>::m]) {
+  if constexpr (EQ == EQ_ADV) {
+    return sqrt(P.ax * P.ax + P.ay * P.ay);
+  } else if constexpr (EQ == EQ_BUR) {
+    return 1.4142135623730951 * fabs(W[0]);
+  } else {
+    double r = 1.0 / W[0];
+    double u = W[1] * r, v = W[2] * r;
+    double p = (P.gam - 1.0) * (W[3] - 0.5 * (W[1] * u + W[2] * v));
+    return sqrt(u * u + v * v) + sqrt(P.gam * p * r);
+  }
+}
+
+}  // namespace hwe

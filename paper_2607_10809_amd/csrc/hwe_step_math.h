@@ -1,0 +1,280 @@
+// Per-item arithmetic of the three step kernels (one cell-component, one
+// edge lane, one cell), written as functions of plain pointers so that the
+// kernels in hwe_kernels.hip are thin index maps.
+//
+// Layouts (internal cell order, N cells, E edges, M components):
+//   wbar [M][N] double, grad [2][M][N] Real (W_x then W_y averages),
+//   R [6][M][N] Real: R - Wbar_K = a0 + a1 X + a2 Y + a3 X^2 + a4 XY + a5 Y^2
+//     about the centroid of K, F [M][E] double, G [M][E] Real.
+#pragma once
+
+#include "hwe_math.h"
+
+namespace hwe {
+
+// ------------------------------------------------------------------ Steps 1-6
+// Reconstruction of component q of cell i (Sec. 2.2).
+template <int EQ, class Real>
+__host__ __device__ __forceinline__ void recon_point(int i, int q, int N, int NB, const Params& P,
+                                                    const double* __restrict__ wbar, const Real* __restrict__ grad,
+                                                    const int32_t* __restrict__ nbr, const double* __restrict__ bnd_n,
+                                                    const Real* __restrict__ p1, const Real* __restrict__ p2,
+                                                    const double* __restrict__ area, const Real* __restrict__ mom,
+                                                    Real* __restrict__ R) {
+  constexpr int M = NComp<EQ>::m;
+  const double W0 = wbar[q * N + i];
+  double Wsum = W0, dW[3];
+  Real V[4], Y[4];
+  V[0] = grad[q * N + i];
+  Y[0] = grad[(M + q) * N + i];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int nb = nbr[f * N + i];
+    if (nb >= 0) {
+      const double w = wbar[q * N + nb];
+      dW[f] = w - W0;
+      Wsum += w;
+      V[f + 1] = grad[q * N + nb];
+      Y[f + 1] = grad[(M + q) * N + nb];
+    } else {
+      // transmissive ghost: K0 mirrored across the face, gradient reflected
+      const int b = -nb - 1;
+      const Real nx = Real(bnd_n[b]), ny = Real(bnd_n[NB + b]);
+      dW[f] = 0.0;
+      Wsum += W0;
+      const Real vn = V[0] * nx + Y[0] * ny;
+      V[f + 1] = V[0] - Real(2) * nx * vn;
+      Y[f + 1] = Y[0] - Real(2) * ny * vn;
+    }
+  }
+  // Step 1: c = P1 (dW1..3, V0..3, Y0..3); W differences formed in FP64
+  const Real d0 = Real(dW[0]), d1 = Real(dW[1]), d2 = Real(dW[2]);
+  const size_t sN = size_t(N);
+  Real c[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const Real* t = p1 + size_t(j * 11) * sN + i;
+    Real s = t[0] * d0 + t[sN] * d1 + t[2 * sN] * d2;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) s += t[(3 + l) * sN] * V[l] + t[(7 + l) * sN] * Y[l];
+    c[j] = s;
+  }
+  // Step 2: linear candidates on {K0, K_l}
+  Real bl[3], cl[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const Real dx = p2[(3 * f) * sN + i], dy = p2[(3 * f + 1) * sN + i], iv = p2[(3 * f + 2) * sN + i];
+    const Real t = (Real(dW[f]) - dx * V[f + 1] - dy * Y[f + 1]) * iv;
+    bl[f] = V[f + 1] + dx * t;
+    cl[f] = Y[f + 1] + dy * t;
+  }
+  // Steps 4-5 in FP64: smoothness indicators at the centroid, nonlinear weights
+  const double g1 = P.lw[0];
+  double w[4];
+  if (P.linear) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) w[l] = P.lw[l];
+  } else {
+    const double A0 = area[i];
+    const double c1 = c[0], c2 = c[1], c3 = c[2], c4 = c[3], c5 = c[4];
+    double beta[4];
+    beta[0] = A0 * (c1 * c1 + c2 * c2) + A0 * A0 * (4.0 * c3 * c3 + c4 * c4 + 4.0 * c5 * c5);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const double b = bl[f], cc = cl[f];
+      beta[f + 1] = A0 * (b * b + cc * cc);
+    }
+    const double wave = Wsum * 0.25 + 1e-30;
+    const double w2 = wave * wave;
+    const double ts = fabs(beta[0] - beta[1]) + fabs(beta[0] - beta[2]) + fabs(beta[0] - beta[3]);
+    const double kappa = ts * ts / 9.0;
+    double ssum = 0.0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const double D = w2 * w2 * P.eps + w2 * beta[l];
+      const double frac = kappa == 0.0 ? 0.0 : kappa / D;
+      w[l] = P.lw[l] * (1.0 + frac);
+      ssum += w[l];
+    }
+    const double inv = 1.0 / ssum;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) w[l] *= inv;
+  }
+  // Step 6: R = (w1/g1) p1 + sum_l (w_l - w1 g_l/g1) p_l, minus Wbar_0
+  const Real k1 = Real(w[0] / g1);
+  Real R1 = k1 * c[0], R2 = k1 * c[1];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const Real kl = Real(w[f + 1] - w[0] * P.lw[f + 1] / g1);
+    R1 += kl * bl[f];
+    R2 += kl * cl[f];
+  }
+  const Real R3 = k1 * c[2], R4 = k1 * c[3], R5 = k1 * c[4];
+  const Real a0 = -(R3 * mom[i] + R4 * mom[sN + i] + R5 * mom[2 * sN + i]);
+  R[(0 * M + q) * sN + i] = a0;
+  R[(1 * M + q) * sN + i] = R1;
+  R[(2 * M + q) * sN + i] = R2;
+  R[(3 * M + q) * sN + i] = R3;
+  R[(4 * M + q) * sN + i] = R4;
+  R[(5 * M + q) * sN + i] = R5;
+}
+
+// ------------------------------------------------------------------ edge lane
+// Contribution of one side (0: the edge's first cell, 1: its second) at one
+// Gauss point, as offsets from that cell's average Wbar: time integrals over
+// the Lobatto nodes of the normal-flux offset dH = H(W) - H(Wbar) (AH) and of
+// d = W - Wbar (AD), and d at t_n + dt (AT).  e < 0 or an absent second side
+// gives zeros.  enl: [3][E] double (nx, ny, |e|); egp: [8][E] Gauss-point
+// offsets from the centroids (side 0 points 0, 1; side 1 points 0, 1).
+template <int EQ, class Real>
+__host__ __device__ __forceinline__ void edge_lane(int e, int side, int g, int E, int N, const Params& P, double dt,
+                                                  const double* __restrict__ wbar, const Real* __restrict__ R,
+                                                  const int32_t* __restrict__ ecell, const double* __restrict__ enl,
+                                                  const Real* __restrict__ egp, Real (&AH)[NComp<EQ>::m],
+                                                  Real (&AD)[NComp<EQ>::m], Real (&AT)[NComp<EQ>::m]) {
+  constexpr int M = NComp<EQ>::m;
+#pragma unroll
+  for (int q = 0; q < M; ++q) AH[q] = AD[q] = AT[q] = Real(0);
+  if (e < 0) return;
+  const int cell = ecell[side * E + e];
+  if (cell < 0) return;
+  const size_t sN = size_t(N);
+  const Real nx = Real(enl[e]), ny = Real(enl[E + e]);
+  const Real X = egp[(4 * side + 2 * g) * E + e];
+  const Real Y = egp[(4 * side + 2 * g + 1) * E + e];
+  double Wbd[M];
+  Real D[6][M], dl[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    const Real a0 = R[(0 * M + q) * sN + cell], a1 = R[(1 * M + q) * sN + cell], a2 = R[(2 * M + q) * sN + cell];
+    const Real a3 = R[(3 * M + q) * sN + cell], a4 = R[(4 * M + q) * sN + cell], a5 = R[(5 * M + q) * sN + cell];
+    Wbd[q] = wbar[q * sN + cell];
+    dl[q] = a0 + a1 * X + a2 * Y + a3 * X * X + a4 * X * Y + a5 * Y * Y;  // W - Wbar at the point
+    D[0][q] = Real(Wbd[q]) + dl[q];
+    D[1][q] = a1 + Real(2) * a3 * X + a4 * Y;
+    D[2][q] = a2 + a4 * X + Real(2) * a5 * Y;
+    D[3][q] = Real(2) * a3;
+    D[4][q] = a4;
+    D[5][q] = Real(2) * a5;
+  }
+  Real Wt[M], Wtt[M];
+  lax_wendroff<EQ, Real>(P, D, Wt, Wtt);
+  const FluxBase<EQ, Real> base = flux_base<EQ, Real>(P, Wbd);
+  // Lobatto nodes 0, dt/2, dt with weights 1/6, 4/6, 1/6
+  const Real taus[3] = {Real(0), Real(0.5 * dt), Real(dt)};
+  const Real wts[3] = {Real(1.0 / 6.0), Real(4.0 / 6.0), Real(1.0 / 6.0)};
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const Real tau = taus[s], h2 = Real(0.5) * tau * tau;
+    Real dls[M], dH[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) dls[q] = dl[q] + tau * Wt[q] + h2 * Wtt[q];
+    normal_flux_delta<EQ, Real>(P, base, dls, nx, ny, dH);
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      AH[q] += wts[s] * dH[q];
+      AD[q] += wts[s] * dls[q];
+    }
+    if (s == 2)
+#pragma unroll
+      for (int q = 0; q < M; ++q) AT[q] = dls[q];
+  }
+}
+
+// Local Lax-Friedrichs edge flux in FP64 from the Gauss-averaged side sums
+// (A: first cell, O: second cell):
+//   F_e = |e| (1/2)(H(W_int) + H(W_ext) - alpha (W_ext - W_int))
+//       = |e| (1/2)(H(Wbar_0) + H(Wbar_1) + AH + OH - alpha (Wbar_1 - Wbar_0 + OD - AD)),
+// alpha = max of the spectral radii at the two cell averages (first cell on ties).
+// Boundary edges (no second cell): W_ext = W_int, F_e = |e| (H(Wbar_0) + AH).
+template <int EQ, class Real>
+__host__ __device__ __forceinline__ void edge_flux(int e, int E, int N, const Params& P,
+                                                  const double* __restrict__ wbar, const int32_t* __restrict__ ecell,
+                                                  const double* __restrict__ enl, const Real (&AH)[NComp<EQ>::m],
+                                                  const Real (&AD)[NComp<EQ>::m], const Real (&OH)[NComp<EQ>::m],
+                                                  const Real (&OD)[NComp<EQ>::m], double* __restrict__ F) {
+  constexpr int M = NComp<EQ>::m;
+  const int c0 = ecell[e], c1 = ecell[E + e];
+  const double nx = enl[e], ny = enl[E + e], len = enl[2 * E + e];
+  const size_t sN = size_t(N), sE = size_t(E);
+  double Wl[M], Hl[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) Wl[q] = wbar[q * sN + c0];
+  normal_flux<EQ, double>(P, Wl, nx, ny, Hl);
+  if (c1 < 0) {
+#pragma unroll
+    for (int q = 0; q < M; ++q) F[q * sE + e] = len * (Hl[q] + double(AH[q]));
+    return;
+  }
+  double Wr[M], Hr[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) Wr[q] = wbar[q * sN + c1];
+  normal_flux<EQ, double>(P, Wr, nx, ny, Hr);
+  const double la = spectral_radius<EQ>(P, Wl, nx, ny);
+  const double lb = spectral_radius<EQ>(P, Wr, nx, ny);
+  const double alpha = la >= lb ? la : lb;
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    const double jump = (Wr[q] - Wl[q]) + double(OD[q] - AD[q]);
+    F[q * sE + e] = len * 0.5 * ((Hl[q] + Hr[q]) + double(AH[q] + OH[q]) - alpha * jump);
+  }
+}
+
+// Gauss average of the interface value of eq. (timeflux) at t_n + dt, as an
+// offset from the mean of the two cell averages (boundary: from the one cell).
+template <int EQ, class Real>
+__host__ __device__ __forceinline__ void edge_value(int e, int E, const int32_t* __restrict__ ecell,
+                                                   const Real (&AT)[NComp<EQ>::m], const Real (&OT)[NComp<EQ>::m],
+                                                   Real* __restrict__ G) {
+  constexpr int M = NComp<EQ>::m;
+  const bool bnd = ecell[E + e] < 0;
+#pragma unroll
+  for (int q = 0; q < M; ++q) G[q * size_t(E) + e] = bnd ? AT[q] : Real(0.5) * (AT[q] + OT[q]);
+}
+
+// ------------------------------------------------------------------ update
+// eq. (flx) with FP64 accumulation, and eq. (derave2d2):  using sum_e n_e|e| = 0
+// over the closed cell, |K| Vbar = sum_e n_e|e| (Wface_e - Wbar_K + G_e) where
+// Wface_e = mean of the two cell averages, so a constant state gives exactly 0.
+template <int EQ, class Real>
+__host__ __device__ __forceinline__ void update_point(int i, int N, int E, double dt, const double* __restrict__ wbar,
+                                                     const int32_t* __restrict__ nbr,
+                                                     const int32_t* __restrict__ cell_edge,
+                                                     const Real* __restrict__ nl, const double* __restrict__ inv_area,
+                                                     const double* __restrict__ F, const Real* __restrict__ G,
+                                                     double* __restrict__ wout, Real* __restrict__ gout) {
+  constexpr int M = NComp<EQ>::m;
+  const size_t sN = size_t(N), sE = size_t(E);
+  double W0[M], fs[M], vs[M], ys[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    W0[q] = wbar[q * sN + i];
+    fs[q] = vs[q] = ys[q] = 0.0;
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int ce = cell_edge[f * sN + i];
+    const int e = ce >> 1;
+    const bool second = (ce & 1) != 0;
+    const int nb = nbr[f * sN + i];
+    const double nlx = nl[f * sN + i], nly = nl[(3 + f) * sN + i];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const double Fe = F[q * sE + e];
+      fs[q] += second ? -Fe : Fe;
+      const double d = nb >= 0 ? 0.5 * (wbar[q * sN + nb] - W0[q]) : 0.0;
+      const double gq = double(G[q * sE + e]) + d;
+      vs[q] += nlx * gq;
+      ys[q] += nly * gq;
+    }
+  }
+  const double ia = inv_area[i];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    wout[q * sN + i] = W0[q] - dt * ia * fs[q];
+    gout[q * sN + i] = Real(ia * vs[q]);
+    gout[(M + q) * sN + i] = Real(ia * ys[q]);
+  }
+}
+
+}  // namespace hwe

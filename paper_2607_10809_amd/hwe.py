@@ -1,0 +1,195 @@
+"""Python binding of the hwe C ABI with torch tensors for device memory and streams.
+
+Functions with the C names (``hwe_mesh_init``, ``hwe_step``, ``hwe_step_adjoint``)
+forward their arguments to the library unchanged; :class:`Mesh` adds buffer
+management and the caller <-> internal (Morton) cell order maps.  Every step of
+the method runs in the HIP library; nothing here computes any part of it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BCS, EQUATIONS, PRECISIONS, HweOpts, check, load_library
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_opts(eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp64", adv=(1.0, 1.0),
+              gas_gamma=1.4, lin_w=(0.94, 0.02, 0.02, 0.02), eps=1e-8, linear_weights=False, device=0) -> HweOpts:
+    L = load_library()
+    o = HweOpts()
+    check(L.hwe_opts_default(C.byref(o)))
+    o.eq = EQUATIONS[eq] if isinstance(eq, str) else int(eq)
+    o.bc = BCS[bc] if isinstance(bc, str) else int(bc)
+    o.prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.linear_weights = 1 if linear_weights else 0
+    o.box[:] = [float(v) for v in box]
+    o.adv[:] = [float(v) for v in adv]
+    o.gas_gamma = float(gas_gamma)
+    o.lin_w[:] = [float(v) for v in lin_w]
+    o.eps = float(eps)
+    o.device = int(device)
+    return o
+
+
+def hwe_mesh_init(nodes, tris, opts: HweOpts) -> C.c_void_p:
+    L = load_library()
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    h = C.c_void_p()
+    check(L.hwe_mesh_init(nodes.ctypes.data_as(C.POINTER(C.c_double)), nodes.shape[0],
+                          tris.ctypes.data_as(C.POINTER(C.c_int32)), tris.shape[0], C.byref(opts), C.byref(h)))
+    return h
+
+
+def hwe_step(handle, wbar_in, grad_in, wbar_out, grad_out, dt, stream=None):
+    check(load_library().hwe_step(handle, _ptr(wbar_in), _ptr(grad_in), _ptr(wbar_out), _ptr(grad_out),
+                                  float(dt), _stream(stream)))
+
+
+def hwe_step_adjoint(handle, wbar_n, grad_n, lam_wbar_np1, lam_grad_np1, lam_wbar_n, lam_grad_n, dt, stream=None):
+    check(load_library().hwe_step_adjoint(handle, _ptr(wbar_n), _ptr(grad_n), _ptr(lam_wbar_np1),
+                                          _ptr(lam_grad_np1), _ptr(lam_wbar_n), _ptr(lam_grad_n), float(dt),
+                                          _stream(stream)))
+
+
+class Mesh:
+    """A triangular mesh on one GPU with the scheme's options.
+
+    State tensors (internal cell order): ``wbar`` float64 (m, N) and ``grad``
+    (2, m, N) of float64 (``precision='fp64'``) or float32 (``'mixed'``).
+    """
+
+    def __init__(self, nodes, tris, eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp64",
+                 device=0, **kw):
+        self.opts = make_opts(eq, bc, box, precision, device=device, **kw)
+        self.precision = precision
+        self._L = load_library()
+        self._h = hwe_mesh_init(nodes, tris, self.opts)
+        N, E, m = C.c_int64(), C.c_int64(), C.c_int32()
+        check(self._L.hwe_mesh_info(self._h, C.byref(N), C.byref(E), C.byref(m)))
+        self.N, self.E, self.m = N.value, E.value, m.value
+        perm = np.empty(self.N, dtype=np.int64)
+        check(self._L.hwe_mesh_cell_perm(self._h, perm.ctypes.data_as(C.POINTER(C.c_int64))))
+        self.perm = perm                       # internal i -> caller perm[i]
+        self.device = torch.device("cuda", device) if device >= 0 else None
+        self.gdtype = torch.float64 if precision == "fp64" else torch.float32
+
+    @classmethod
+    def from_workload(cls, wl, precision="fp64", device=0, **kw):
+        bc = "periodic" if wl.mesh.periodic else "transmissive"
+        eq = {0: "advection", 1: "burgers", 2: "euler"}[wl.eq]
+        return cls(wl.mesh.nodes, wl.mesh.tris, eq=eq, bc=bc, box=wl.mesh.box, precision=precision,
+                   device=device, adv=wl.adv, **kw)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.hwe_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ state maps
+    def to_device(self, state):
+        """Caller-order numpy state [3][m][N] -> (wbar, grad) tensors in internal order."""
+        s = np.asarray(state, dtype=np.float64)[:, :, self.perm]
+        wbar = torch.from_numpy(np.ascontiguousarray(s[0])).to(self.device)
+        grad = torch.from_numpy(np.ascontiguousarray(s[1:])).to(self.device, dtype=self.gdtype)
+        return wbar, grad
+
+    def to_host(self, wbar, grad):
+        """(wbar, grad) tensors in internal order -> caller-order numpy [3][m][N] float64."""
+        out = np.empty((3, self.m, self.N))
+        out[0][:, self.perm] = wbar.detach().double().cpu().numpy()
+        out[1:][:, :, self.perm] = grad.detach().double().cpu().numpy()
+        return out
+
+    def empty_state(self):
+        return (torch.empty((self.m, self.N), dtype=torch.float64, device=self.device),
+                torch.empty((2, self.m, self.N), dtype=self.gdtype, device=self.device))
+
+    def _check_state(self, wbar, grad):
+        if wbar.dtype != torch.float64 or wbar.shape != (self.m, self.N) or not wbar.is_contiguous():
+            raise ValueError("wbar must be a contiguous float64 tensor of shape (m, N)")
+        if grad.dtype != self.gdtype or grad.shape != (2, self.m, self.N) or not grad.is_contiguous():
+            raise ValueError(f"grad must be a contiguous {self.gdtype} tensor of shape (2, m, N)")
+        if wbar.device != self.device or grad.device != self.device:
+            raise ValueError("state tensors must live on the mesh's device")
+
+    # ------------------------------------------------------------ the step
+    def step(self, wbar, grad, dt, out=None, stream=None):
+        self._check_state(wbar, grad)
+        wo, go = out if out is not None else self.empty_state()
+        self._check_state(wo, go)
+        hwe_step(self._h, wbar, grad, wo, go, dt, stream)
+        return wo, go
+
+    def run(self, wbar, grad, dt, nsteps, stream=None):
+        """nsteps steps of size dt with two ping-pong buffers; returns the final state."""
+        a = (wbar, grad)
+        if nsteps <= 0:
+            return a
+        b = self.empty_state()
+        c = self.empty_state() if nsteps > 1 else None
+        for k in range(nsteps):
+            dst = b if k % 2 == 0 else c
+            hwe_step(self._h, a[0], a[1], dst[0], dst[1], dt, stream)
+            a = dst
+        return a
+
+    def adjoint(self, wbar, grad, lam_wbar, lam_grad, dt, out=None, stream=None):
+        self._check_state(wbar, grad)
+        self._check_state(lam_wbar, lam_grad)
+        lw, lg = out if out is not None else self.empty_state()
+        hwe_step_adjoint(self._h, wbar, grad, lam_wbar, lam_grad, lw, lg, dt, stream)
+        return lw, lg
+
+    def max_dt(self, wbar, cfl, stream=None):
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        check(self._L.hwe_max_dt(self._h, _ptr(wbar), float(cfl), _ptr(out), _stream(stream)))
+        return float(out.item())
+
+    def check_state(self, wbar, stream=None):
+        out = torch.empty(1, dtype=torch.int32, device=self.device)
+        check(self._L.hwe_check_state(self._h, _ptr(wbar), _ptr(out), _stream(stream)))
+        return int(out.item())
+
+    def debug_recon(self, wbar, grad, stream=None):
+        R = torch.empty((6, self.m, self.N), dtype=self.gdtype, device=self.device)
+        check(self._L.hwe_debug_recon(self._h, _ptr(wbar), _ptr(grad), _ptr(R), _stream(stream)))
+        return R
+
+    def profile_begin(self, n_steps):
+        check(self._L.hwe_profile_begin(self._h, int(n_steps)))
+
+    def profile_end(self):
+        """Summed per-kernel milliseconds (recon, edge, update) and the step count."""
+        ms = (C.c_double * 3)()
+        n = C.c_int32()
+        check(self._L.hwe_profile_end(self._h, ms, C.byref(n)))
+        return [ms[0], ms[1], ms[2]], n.value
+
+    def host_array(self, which):
+        sizes = {0: (55, self.N), 1: (2, self.N), 2: (self.N,), 3: (3, self.N), 4: (3, self.N)}
+        out = np.empty(sizes[which])
+        check(self._L.hwe_debug_host_array(self._h, int(which), out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out

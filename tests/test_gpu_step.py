@@ -1,0 +1,333 @@
+"""GPU parity of the HIP step against the CPU oracle (through the C ABI).
+
+Bars: FP64 within 1e-12 relative max-norm on smooth cases and 1e-10 relative L1
+with shocks; the mixed path (FP32 bulk, FP64 cell averages / weights) within
+2e-5 relative max-norm on the cell averages of W.  Workloads are the seeded
+synthetic inputs of ``workloads`` at the sizes of the benchmark configurations
+(51,200 / 204,800 / 980,000 triangles), with smaller meshes where the oracle
+must run many steps.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_util import gpu_run, gpu_run_to, rel_l1, rel_max  # noqa: E402
+
+from oracle import OracleMesh  # noqa: E402
+from workloads import (advection_workload, burgers_workload, riemann_workload, split_square_mesh,  # noqa: E402
+                       vortex_workload)
+
+pytestmark = pytest.mark.gpu
+
+FP64_SMOOTH = 1e-12
+FP64_SHOCK_L1 = 1e-10
+MIXED = 2e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_10809_amd import _lib
+    _lib.load_library()
+
+
+def _mesh(wl, precision="fp64", **kw):
+    from paper_2607_10809_amd.hwe import Mesh
+    return Mesh.from_workload(wl, precision=precision, **kw)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ C1
+def test_c1_linear_advection_full_run():
+    wl = advection_workload(n=20)                      # 800 triangles, T = 0.5, CFL 0.3
+    om = OracleMesh.from_workload(wl)
+    dt = om.max_dt(wl.state0, wl.cfl)
+    ref = om.run_to(wl.state0, wl.T, dt)
+    got = gpu_run_to(_mesh(wl), wl.state0, wl.T, dt)
+    err = rel_max(got, ref)
+    ex = wl.exact_state(wl.T)
+    area = om.geometry()["area"]
+    _say("C1 rel_max", err, "L1 vs exact gpu/oracle", rel_l1(got[:1], ex[:1], area), rel_l1(ref[:1], ex[:1], area))
+    assert err <= FP64_SMOOTH
+    gm = gpu_run_to(_mesh(wl, "mixed"), wl.state0, wl.T, dt)
+    assert rel_max(gm[:1], ref[:1]) <= MIXED
+
+
+# ------------------------------------------------------------------ C2
+def test_c2_burgers_smooth_fp64_and_mixed():
+    wl = burgers_workload(n=160, T=0.5 / np.pi)        # 51,200 jittered triangles
+    om = OracleMesh.from_workload(wl)
+    dt = om.max_dt(wl.state0, wl.cfl)
+    ref = om.run_to(wl.state0, wl.T, dt)
+    got = gpu_run_to(_mesh(wl), wl.state0, wl.T, dt)
+    err = rel_max(got, ref)
+    gm = gpu_run_to(_mesh(wl, "mixed"), wl.state0, wl.T, dt)
+    errm = rel_max(gm[:1], ref[:1])
+    _say("C2 smooth rel_max fp64", err, "mixed wbar", errm)
+    assert err <= FP64_SMOOTH
+    assert errm <= MIXED
+
+
+@pytest.mark.parametrize("T", [0.5, 1.5])
+def test_c2_burgers_shocked(T):
+    wl = burgers_workload(n=160, T=T)
+    om = OracleMesh.from_workload(wl)
+    dt = om.max_dt(wl.state0, wl.cfl)
+    ref = om.run_to(wl.state0, T, dt)
+    got = gpu_run_to(_mesh(wl), wl.state0, T, dt)
+    area = om.geometry()["area"]
+    e1 = rel_l1(got, ref, area)
+    gm = gpu_run_to(_mesh(wl, "mixed"), wl.state0, T, dt)
+    em = rel_l1(gm[:1], ref[:1], area)
+    _say(f"C2 T={T} rel_L1 fp64", e1, "rel_max", rel_max(got, ref), "mixed wbar L1", em,
+         "max", rel_max(gm[:1], ref[:1]))
+    assert e1 <= FP64_SHOCK_L1
+    assert em <= MIXED
+
+
+# ------------------------------------------------------------------ C3
+@pytest.fixture(scope="module")
+def c3():
+    wl = vortex_workload()                              # 204,800 jittered triangles
+    om = OracleMesh.from_workload(wl)
+    dt = om.max_dt(wl.state0, wl.cfl)
+    return wl, om, dt
+
+
+def test_c3_vortex_prefix_fp64_and_mixed(c3):
+    wl, om, dt = c3
+    ref = om.run(wl.state0, dt, 20)
+    got = gpu_run(_mesh(wl), wl.state0, dt, 20)
+    gm = gpu_run(_mesh(wl, "mixed"), wl.state0, dt, 20)
+    err, errm = rel_max(got, ref), rel_max(gm[:1], ref[:1])
+    _say("C3 20-step rel_max fp64", err, "mixed wbar", errm)
+    assert err <= FP64_SMOOTH
+    assert errm <= MIXED
+
+
+def test_c3_vortex_late_state_sampled_cells(c3):
+    """After 1000 GPU steps, one more GPU step matches the oracle's step on sampled cells."""
+    import torch
+    wl, om, dt = c3
+    mesh = _mesh(wl)
+    w, g = mesh.to_device(wl.state0)
+    w, g = mesh.run(w, g, dt, 1000)
+    s_k = mesh.to_host(w, g)
+    w1, g1 = mesh.step(w, g, dt)
+    torch.cuda.synchronize()
+    s_k1 = mesh.to_host(w1, g1)
+    rng = np.random.default_rng(0)
+    cells = rng.choice(om.N, 4096, replace=False)
+    ref = om.step_cells(s_k, cells, dt)
+    err = float((np.abs(s_k1[:, :, cells] - ref).max(axis=-1) / np.abs(s_k1).max(axis=-1)).max())
+    _say("C3 step 1000 sampled rel_max", err)
+    assert err <= FP64_SMOOTH
+
+
+def test_vortex_full_run_to_T2_small_mesh():
+    wl = vortex_workload(n=40)
+    om = OracleMesh.from_workload(wl)
+    dt = om.max_dt(wl.state0, wl.cfl)
+    ref = om.run_to(wl.state0, wl.T, dt)
+    got = gpu_run_to(_mesh(wl), wl.state0, wl.T, dt)
+    gm = gpu_run_to(_mesh(wl, "mixed"), wl.state0, wl.T, dt)
+    err, errm = rel_max(got, ref), rel_max(gm[:1], ref[:1])
+    _say("vortex n=40 T=2 rel_max fp64", err, "mixed wbar", errm)
+    assert err <= FP64_SMOOTH
+    assert errm <= MIXED
+
+
+def test_c3_mixed_against_fp64_at_T2(c3):
+    wl, om, dt = c3
+    got = gpu_run_to(_mesh(wl), wl.state0, wl.T, dt)
+    gm = gpu_run_to(_mesh(wl, "mixed"), wl.state0, wl.T, dt)
+    ex = wl.exact_state(wl.T)
+    area = om.geometry()["area"]
+    errm = rel_max(gm[:1], got[:1])
+    _say("C3 T=2 mixed vs fp64 wbar rel_max", errm, "h*grad rel_max", rel_max(gm[1:], got[1:]),
+         "density L1 vs exact fp64/mixed", rel_l1(got[0, :1], ex[0, :1], area), rel_l1(gm[0, :1], ex[0, :1], area))
+    assert errm <= MIXED
+
+
+# ------------------------------------------------------------------ C4
+def test_c4_riemann_prefix_full_size():
+    wl = riemann_workload()                             # 980,000 triangles, transmissive
+    om = OracleMesh.from_workload(wl)
+    dt = om.max_dt(wl.state0, wl.cfl)
+    ref = om.run(wl.state0, dt, 10)
+    got = gpu_run(_mesh(wl), wl.state0, dt, 10)
+    gm = gpu_run(_mesh(wl, "mixed"), wl.state0, dt, 10)
+    area = om.geometry()["area"]
+    e1, em = rel_l1(got, ref, area), rel_l1(gm[:1], ref[:1], area)
+    _say("C4 10-step rel_L1 fp64", e1, "rel_max", rel_max(got, ref), "mixed wbar L1", em)
+    assert e1 <= FP64_SHOCK_L1
+    assert em <= MIXED
+
+
+def test_riemann_prefix_and_late_one_step_small_mesh():
+    """Four-quadrant Riemann problem, 20,000 triangles.
+
+    Its slip lines are unstable and the nonlinear weights amplify any round-off
+    difference by about 1.6x per step, so two correct implementations part ways
+    after a few tens of steps.  Parity is therefore checked on a 15-step prefix
+    and, at a late shocked state, on one application of the step map.
+    """
+    import torch
+    wl = riemann_workload(n=100)
+    om = OracleMesh.from_workload(wl)
+    dt = om.max_dt(wl.state0, wl.cfl)
+    area = om.geometry()["area"]
+    ref = om.run(wl.state0, dt, 15)
+    got = gpu_run(_mesh(wl), wl.state0, dt, 15)
+    e1 = rel_l1(got, ref, area)
+    _say("Riemann n=100 15-step rel_L1", e1, "rel_max", rel_max(got, ref))
+    assert e1 <= FP64_SHOCK_L1
+    mesh = _mesh(wl)
+    w, g = mesh.to_device(wl.state0)
+    w, g = mesh.run(w, g, dt, 250)
+    s_k = mesh.to_host(w, g)
+    assert mesh.check_state(w) == 0
+    w1, g1 = mesh.step(w, g, dt)
+    torch.cuda.synchronize()
+    err = rel_max(mesh.to_host(w1, g1), om.step(s_k, dt))
+    _say("Riemann n=100 one step from step 250 rel_max", err)
+    assert err <= FP64_SMOOTH
+
+
+def test_c4_riemann_late_state_sampled_cells():
+    import torch
+    wl = riemann_workload()
+    om = OracleMesh.from_workload(wl)
+    dt = om.max_dt(wl.state0, wl.cfl)
+    for prec, tol in (("fp64", FP64_SMOOTH), ("mixed", MIXED)):
+        mesh = _mesh(wl, prec)
+        w, g = mesh.to_device(wl.state0)
+        w, g = mesh.run(w, g, dt, 300)
+        assert mesh.check_state(w) == 0
+        s_k = mesh.to_host(w, g)
+        w1, g1 = mesh.step(w, g, dt)
+        torch.cuda.synchronize()
+        s_k1 = mesh.to_host(w1, g1)
+        cells = np.random.default_rng(2).choice(om.N, 4096, replace=False)
+        ref = om.step_cells(s_k, cells, dt)
+        nb = 1 if prec == "mixed" else 3
+        err = float((np.abs(s_k1[:nb, :, cells] - ref[:nb]).max(axis=-1) / np.abs(s_k1[:nb]).max(axis=-1)).max())
+        _say(f"C4 {prec} one step from step 300, sampled rel_max", err)
+        assert err <= tol
+
+
+# ------------------------------------------------------------------ invariants / determinism
+def test_free_stream_mass_and_determinism(c3):
+    import torch
+    wl, om, dt = c3
+    box = (0.0, 2.0, 0.0, 2.0)
+    from paper_2607_10809_amd.hwe import Mesh
+    mesh = split_square_mesh(30, box, jitter=0.3, seed=9)
+    for prec in ("fp64", "mixed"):
+        m = Mesh(mesh.nodes, mesh.tris, eq="euler", bc="periodic", box=box, precision=prec)
+        s = np.zeros((3, 4, m.N))
+        s[0] = np.array([1.3, 0.5, -0.7, 3.1])[:, None]
+        out = gpu_run(m, s, 0.002, 50)
+        assert np.abs(out[0] - s[0]).max() <= 1e-13 * 3.1
+        assert np.abs(out[1:]).max() <= (1e-11 if prec == "fp64" else 1e-5)
+    area = om.geometry()["area"]
+    for prec in ("fp64", "mixed"):
+        mesh3 = _mesh(wl, prec)
+        w, g = mesh3.to_device(wl.state0)
+        a = mesh3.run(w, g, dt, 200)
+        b = mesh3.run(w, g, dt, 200)
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])      # bitwise reproducible
+        s = mesh3.to_host(*a)
+        m0 = (wl.state0[0] * area).sum(axis=1)
+        m1 = (s[0] * area).sum(axis=1)
+        drift = np.abs(m1 - m0) / (np.abs(wl.state0[0]) * area).sum(axis=1)
+        _say(prec, "mass drift over 200 steps", drift)
+        assert drift.max() <= 1e-13
+
+
+def test_reconstruction_kernel_against_oracle_points(c3):
+    import torch
+    wl, om, dt = c3
+    mesh = _mesh(wl)
+    w, g = mesh.to_device(wl.state0)
+    R = mesh.debug_recon(w, g)
+    torch.cuda.synchronize()
+    R = R.cpu().numpy()
+    cen = mesh.host_array(1)
+    V = om.cell_vertices()
+    rng = np.random.default_rng(1)
+    worst = 0.0
+    for i in rng.choice(mesh.N, 200, replace=False):
+        k = mesh.perm[i]
+        pts = np.array([V[k].mean(0), 0.5 * (V[k][0] + V[k][1]), V[k][2]])
+        D = om.eval_recon(wl.state0, k, pts)             # (3, m, 6)
+        X = pts[:, 0] - cen[0, i]
+        Y = pts[:, 1] - cen[1, i]
+        a = R[:, :, i]                                    # (6, m)
+        val = wl.state0[0, :, k][None, :] + a[0] + np.outer(X, a[1]) + np.outer(Y, a[2]) \
+            + np.outer(X * X, a[3]) + np.outer(X * Y, a[4]) + np.outer(Y * Y, a[5])
+        dx = a[1] + np.outer(2 * X, a[3]) + np.outer(Y, a[4])
+        worst = max(worst, float(np.abs(val - D[:, :, 0]).max() / np.abs(D[:, :, 0]).max()),
+                    float(np.abs(dx - D[:, :, 1]).max() / max(np.abs(D[:, :, 1]).max(), 1e-3)))
+    _say("recon kernel worst rel", worst)
+    assert worst <= 1e-12
+
+
+def test_max_dt_and_state_flags(c3):
+    import torch
+    wl, om, dt = c3
+    mesh = _mesh(wl)
+    w, g = mesh.to_device(wl.state0)
+    assert np.isclose(mesh.max_dt(w, 0.3), dt, rtol=1e-13)
+    assert mesh.check_state(w) == 0
+    w2 = w.clone()
+    w2[0, 5] = float("nan")
+    assert mesh.check_state(w2) & 1
+    w3 = w.clone()
+    w3[0, 7] = -1.0
+    assert mesh.check_state(w3) & 2
+    w4 = w.clone()
+    w4[3, 9] = 0.0
+    assert mesh.check_state(w4) & 4
+    torch.cuda.synchronize()
+
+
+def test_tiny_and_ragged_meshes():
+    # 18 triangles (< one wavefront), and 2*37^2 = 2738 (ragged tail of every launch)
+    for n in (3, 37):
+        wl = vortex_workload(n=n)
+        om = OracleMesh.from_workload(wl)
+        dt = om.max_dt(wl.state0, wl.cfl)
+        ref = om.run(wl.state0, dt, 5)
+        got = gpu_run(_mesh(wl), wl.state0, dt, 5)
+        assert rel_max(got, ref) <= FP64_SMOOTH
+    wl = riemann_workload(n=3)
+    om = OracleMesh.from_workload(wl)
+    dt = om.max_dt(wl.state0, wl.cfl)
+    ref = om.run(wl.state0, dt, 5)
+    got = gpu_run(_mesh(wl), wl.state0, dt, 5)
+    assert rel_max(got, ref) <= FP64_SMOOTH
+
+
+def test_bad_arguments_raise():
+    import torch
+    from paper_2607_10809_amd._lib import HweError
+    wl = vortex_workload(n=4)
+    mesh = _mesh(wl)
+    w, g = mesh.to_device(wl.state0)
+    with pytest.raises(HweError):
+        mesh.step(w, g, -1.0)
+    with pytest.raises(HweError):
+        mesh.step(w, g, float("nan"))
+    with pytest.raises(HweError):                 # output aliases the input
+        mesh.step(w, g, 0.01, out=(w, g))
+    torch.cuda.synchronize()
