@@ -72,12 +72,16 @@ typedef struct {
   double eps;             /* epsilon of eq. (nonlinearweight): 1e-8 */
   int32_t device;         /* HIP device ordinal; -1 = host precompute only (no
                              device memory; hwe_step etc. return HWE_ENODEV) */
-  int32_t reserved;       /* must be 0 */
+  int32_t positivity;     /* 1 (Euler only): positivity-preserving scaling of the
+                             reconstruction about the cell average (the scale
+                             limiter cited in Sec. 3): density, then pressure, kept
+                             >= min(1e-13, average density, average pressure) at
+                             the cell's six edge Gauss points.  0: off */
 } hwe_opts;
 
 /* Fill *o with the paper's defaults: linear weights 0.94/0.02/0.02/0.02
  * (Step 3), eps = 1e-8 (Step 5), gas_gamma = 1.4, adv = (1, 1), periodic unit
- * box, FP64, device 0. */
+ * box, FP64, no limiter, device 0. */
 hwe_status hwe_opts_default(hwe_opts* o);
 
 /* Build a mesh handle (host FP64 precompute + one upload).
@@ -122,7 +126,8 @@ hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, doub
  * Same layouts and precision as hwe_step; outputs must not overlap inputs.
  * Non-smooth points: d|x| = sign(x) dx with sign(0) = 0; the max of the two
  * spectral radii in the flux viscosity takes the edge's first cell (the one
- * with the lower caller index) on ties. */
+ * with the lower caller index) on ties.  Returns HWE_EINVAL for meshes built
+ * with opts.positivity = 1 (the limiter is not differentiated). */
 hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n,
                             const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n,
                             void* lam_grad_n, double dt, void* stream);

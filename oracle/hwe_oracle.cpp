@@ -103,6 +103,13 @@ template <class T> HD<T> recip(const HD<T>& x) {
 }
 template <class T> HD<T> operator/(const HD<T>& x, const HD<T>& y) { return x * recip(y); }
 
+// ---------------------------------------------------------------- rules
+// 2-point Gauss-Legendre on each edge; 3-point Gauss-Lobatto in time
+const double kGaussS[2] = {0.5 - 0.28867513459481288225, 0.5 + 0.28867513459481288225};  // 1/2 -+ sqrt(3)/6
+const double kGaussW[2] = {0.5, 0.5};
+const double kTimeL[3] = {0.0, 0.5, 1.0};
+const double kTimeW[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+
 // ---------------------------------------------------------------- options
 struct Opts {
   int eq;           // 0 advection, 1 Burgers, 2 Euler
@@ -113,6 +120,7 @@ struct Opts {
   double lin_w[4];  // linear weights gamma_1..gamma_4
   double eps;       // epsilon of the nonlinear weights
   int linear_only;  // 1: use the linear weights (omega = gamma), for exactness pins
+  int positivity;   // 1: scaling limiter on the reconstruction (Euler)
 };
 
 inline int ncomp(int eq) { return eq == 2 ? 4 : 1; }
@@ -270,6 +278,8 @@ struct Recon {
   T p[4][4][6];     // [candidate l=1..4][component][coefficient]
   T beta[4][4];     // [component][l]
   T omega[4][4];    // [component][l]
+  T wbar[4];        // cell averages of K0
+  T theta[4];       // scaling of the reconstruction about the average (1 = none)
   double cx, cy;    // expansion point (centroid of K0)
 };
 
@@ -330,6 +340,10 @@ bool reconstruct(const Mesh& M, const T* s, int64_t k, Recon<T>& R) {
   const double x0 = M.cx[k], y0 = M.cy[k];
   R.cx = x0;
   R.cy = y0;
+  for (int q = 0; q < m; ++q) {
+    R.wbar[q] = st[0].W[q];
+    R.theta[q] = T(1.0);
+  }
   const double A0 = M.area[k];
   // scaled monomials xi = X / h, eta = Y / h keep the KKT matrices O(1)
   const double h = std::sqrt(A0);
@@ -445,6 +459,7 @@ bool reconstruct(const Mesh& M, const T* s, int64_t k, Recon<T>& R) {
     }
     for (int l = 0; l < 4; ++l) R.omega[q][l] = wb[l] / ssum;
   }
+  if (o.positivity && o.eq == 2) positivity_scaling(M, k, R);
   return true;
 }
 
@@ -472,6 +487,75 @@ void eval_recon(const Opts& o, const Recon<T>& R, int q, double x, double y, T D
     for (int l = 1; l < 4; ++l) r += w[l] * pv[l][j];
     D[j] = r;
   }
+  // scaling limiter: R -> Wbar + theta (R - Wbar)
+  D[0] = R.wbar[q] + R.theta[q] * (D[0] - R.wbar[q]);
+  for (int j = 1; j < 6; ++j) D[j] = R.theta[q] * D[j];
+}
+
+// Positivity-preserving scaling of the reconstruction (the scale limiter of
+// Zhang and Shu cited in Sec. 3): with eps = min(1e-13, rho_bar, p_bar),
+// first the density part is scaled about its average so that density >= eps at
+// the six edge Gauss points of the cell, then the whole state is scaled by the
+// smallest t in [0, 1] with p(Wbar + t (W - Wbar)) = eps over the points where
+// the pressure would fall below eps.
+template <class T>
+void positivity_scaling(const Mesh& M, int64_t k, Recon<T>& R) {
+  const Opts& o = M.o;
+  const Tri& t = M.tri[k];
+  const double gm1 = o.gas_gamma - 1.0;
+  double xs[6], ys[6];
+  for (int f = 0; f < 3; ++f) {
+    int f1 = (f + 1) % 3;
+    for (int G = 0; G < 2; ++G) {
+      xs[2 * f + G] = t.x[f] + kGaussS[G] * (t.x[f1] - t.x[f]);
+      ys[2 * f + G] = t.y[f] + kGaussS[G] * (t.y[f1] - t.y[f]);
+    }
+  }
+  auto pressure = [&](const T* W) { return T(gm1) * (W[3] - T(0.5) * (W[1] * W[1] + W[2] * W[2]) / W[0]); };
+  const T* Wb = R.wbar;
+  const double pbar = val(pressure(Wb));
+  const double eps = std::min(1e-13, std::min(val(Wb[0]), pbar));
+  // density
+  T rmin = T(1e300);
+  for (int i = 0; i < 6; ++i) {
+    T D[6];
+    eval_recon(o, R, 0, xs[i], ys[i], D);
+    if (val(D[0]) < val(rmin)) rmin = D[0];
+  }
+  if (val(rmin) < eps) R.theta[0] = (Wb[0] - T(eps)) / (Wb[0] - rmin);
+  // pressure
+  T th = T(1.0);
+  for (int i = 0; i < 6; ++i) {
+    T W[4];
+    for (int q = 0; q < 4; ++q) {
+      T D[6];
+      eval_recon(o, R, q, xs[i], ys[i], D);
+      W[q] = D[0];
+    }
+    if (!(val(pressure(W)) < eps)) continue;
+    // g(t) = 2 rho(t) (E(t) - eps/(gamma-1)) - |m(t)|^2, g(0) > 0 > g(1)
+    T dr = W[0] - Wb[0], d1 = W[1] - Wb[1], d2 = W[2] - Wb[2], dE = W[3] - Wb[3];
+    T Ep = Wb[3] - T(eps / gm1);
+    T a = T(2.0) * dr * dE - (d1 * d1 + d2 * d2);
+    T b = T(2.0) * (Ep * dr + Wb[0] * dE) - T(2.0) * (Wb[1] * d1 + Wb[2] * d2);
+    T c = T(2.0) * Wb[0] * Ep - (Wb[1] * Wb[1] + Wb[2] * Wb[2]);
+    T root;
+    if (val(a) == 0.0) {
+      root = T(0.0) - c / b;
+    } else {
+      T disc = b * b - T(4.0) * a * c;
+      if (val(disc) < 0.0) disc = T(0.0);
+      T sq = sqrtv(disc);
+      T qq = val(b) >= 0.0 ? T(-0.5) * (b + sq) : T(-0.5) * (b - sq);
+      T r1 = qq / a, r2 = c / qq;
+      double v1 = val(r1), v2 = val(r2);
+      bool ok1 = v1 >= 0.0 && v1 <= 1.0, ok2 = v2 >= 0.0 && v2 <= 1.0;
+      root = ok1 && ok2 ? (v1 <= v2 ? r1 : r2) : (ok1 ? r1 : r2);
+    }
+    if (val(root) < val(th)) th = root;
+  }
+  if (val(th) < 1.0)
+    for (int q = 0; q < 4; ++q) R.theta[q] = R.theta[q] * th;
 }
 
 // ---------------------------------------------------------------- Lax-Wendroff
@@ -510,10 +594,6 @@ void lax_wendroff(const Opts& o, int m, const T D[6][4], T Wt[4], T Wtx[4], T Wt
 }
 
 // ---------------------------------------------------------------- the step
-const double kGaussS[2] = {0.5 - 0.28867513459481288225, 0.5 + 0.28867513459481288225};  // 1/2 -+ sqrt(3)/6
-const double kGaussW[2] = {0.5, 0.5};
-const double kTimeL[3] = {0.0, 0.5, 1.0};
-const double kTimeW[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
 
 // One cell's new state from the reconstructions (eqs. (flx), (fx), (flux),
 // (tay), (tayext), (derave2d2), (timeflux), (taylor2dtime)).
@@ -764,6 +844,7 @@ struct or_opts {
   double lin_w[4];
   double eps;
   int linear_only;
+  int positivity;
 };
 
 void* or_mesh_new(const double* nodes, int64_t nn, const int32_t* tris, int64_t nt, const or_opts* o,
@@ -778,6 +859,7 @@ void* or_mesh_new(const double* nodes, int64_t nn, const int32_t* tris, int64_t 
   for (int i = 0; i < 4; ++i) M->o.lin_w[i] = o->lin_w[i];
   M->o.eps = o->eps;
   M->o.linear_only = o->linear_only;
+  M->o.positivity = o->positivity;
   int st = build_mesh(*M, nodes, nn, tris, nt);
   if (status) *status = st;
   if (st != 0) {
@@ -888,6 +970,15 @@ int or_recon_cell(void* h, const double* s, int64_t k, double* p, double* beta, 
     }
   centroid[0] = R.cx;
   centroid[1] = R.cy;
+  return 0;
+}
+
+// Scaling factors theta[m] of the limiter for cell k (1 where inactive).
+int or_recon_theta(void* h, const double* s, int64_t k, double* theta) {
+  Mesh* M = static_cast<Mesh*>(h);
+  Recon<double> R;
+  if (!reconstruct(*M, s, k, R)) return -3;
+  for (int q = 0; q < M->m; ++q) theta[q] = R.theta[q];
   return 0;
 }
 

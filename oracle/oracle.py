@@ -12,13 +12,13 @@ _SRC = os.path.join(_HERE, "hwe_oracle.cpp")
 _LIB = os.path.join(_HERE, "libhwe_oracle.so")
 
 OPTS_DEFAULT = dict(adv=(1.0, 1.0), gas_gamma=1.4, lin_w=(0.94, 0.02, 0.02, 0.02), eps=1e-8,
-                    linear_only=0)
+                    linear_only=0, positivity=0)
 
 
 class _Opts(C.Structure):
     _fields_ = [("eq", C.c_int), ("bc", C.c_int), ("box", C.c_double * 4), ("adv", C.c_double * 2),
                 ("gas_gamma", C.c_double), ("lin_w", C.c_double * 4), ("eps", C.c_double),
-                ("linear_only", C.c_int)]
+                ("linear_only", C.c_int), ("positivity", C.c_int)]
 
 
 def build_oracle(force: bool = True) -> str:
@@ -54,6 +54,7 @@ def _load():
         L.or_jvp.argtypes = [C.c_void_p, dp, dp, C.c_double, C.c_int64, C.c_int]
         L.or_recon_cell.argtypes = [C.c_void_p, dp, C.c_int64, dp, dp, dp, dp]
         L.or_eval_recon.argtypes = [C.c_void_p, dp, C.c_int64, dp, C.c_int64, dp]
+        L.or_recon_theta.argtypes = [C.c_void_p, dp, C.c_int64, dp]
         L.or_lax_wendroff.argtypes = [C.POINTER(_Opts), dp, C.c_int64, dp]
         L.or_llf.argtypes = [C.POINTER(_Opts), dp, dp, C.c_double, C.c_double, C.c_double, dp]
         L.or_spectral_radius.restype = C.c_double
@@ -80,6 +81,7 @@ def _opts(eq, bc=0, box=(0.0, 1.0, 0.0, 1.0), **kw):
     s.lin_w[:] = [float(v) for v in o["lin_w"]]
     s.eps = float(o["eps"])
     s.linear_only = int(o["linear_only"])
+    s.positivity = int(o["positivity"])
     return s
 
 
@@ -191,6 +193,13 @@ class OracleMesh:
         if st:
             raise RuntimeError("oracle recon failed")
         return dict(p=p, beta=beta, omega=omega, centroid=cen)
+
+    def recon_theta(self, s, k):
+        s = self._check_state(s)
+        th = np.empty(self.m)
+        if _lib.or_recon_theta(self._h, _p(s), int(k), _p(th)):
+            raise RuntimeError("oracle recon failed")
+        return th
 
     def eval_recon(self, s, k, xy):
         s = self._check_state(s)

@@ -95,7 +95,7 @@ hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tr
   *out = nullptr;
   const hwe_opts& o = *opts;
   if (o.eq < HWE_ADVECTION || o.eq > HWE_EULER || o.bc < 0 || o.bc > 1 || o.prec < 0 || o.prec > 1 ||
-      o.reserved != 0) {
+      o.positivity < 0 || o.positivity > 1 || (o.positivity && o.eq != HWE_EULER)) {
     set_error("invalid option value");
     return HWE_EINVAL;
   }
@@ -204,6 +204,10 @@ hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n
     }
   if (overlaps(lam_wbar_n, wb, lam_grad_n, gb)) {
     set_error("output buffers overlap each other");
+    return HWE_EINVAL;
+  }
+  if (m->opts.positivity) {
+    set_error("hwe_step_adjoint: the positivity limiter is not differentiated");
     return HWE_EINVAL;
   }
   if ((s = set_dev(m)) != HWE_OK) return s;

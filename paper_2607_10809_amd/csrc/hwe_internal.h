@@ -35,6 +35,8 @@ struct HostMesh {
   std::vector<int32_t> cell_edge;  // [3][N] (edge << 1) | (cell is the edge's second cell)
   std::vector<double> nl;          // [6][N] outward normal times length: x of faces 0..2, then y
   std::vector<double> inv_area;    // [N]
+  std::vector<double> gpc;         // [12][N] offsets (X, Y) from the centroid of the
+                                   // 2 Gauss points of faces 0..2: row 4f+2g (X), 4f+2g+1 (Y)
   std::vector<int32_t> ecell;      // [2][E] first cell (lower caller index), second cell or -1
   std::vector<double> egeo;        // [11][E]
   double rmin = 0.0;               // smallest inradius
@@ -55,6 +57,7 @@ struct DevMesh {
   double* p2 = nullptr;
   double* nl = nullptr;
   double* inv_area = nullptr;
+  double* gpc = nullptr;    // [12][N] (limiter only)
   double* enl = nullptr;    // [3][E] edge normal and length (FP64 in both precisions)
   double* egp = nullptr;    // [8][E] Gauss-point offsets (FP64 path)
   // FP32 copies for the mixed path

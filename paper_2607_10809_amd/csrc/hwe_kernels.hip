@@ -45,12 +45,47 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
                                                         const double* __restrict__ bnd_n,
                                                         const Real* __restrict__ p1, const Real* __restrict__ p2,
                                                         const double* __restrict__ area,
-                                                        const Real* __restrict__ mom, Real* __restrict__ R) {
+                                                        const Real* __restrict__ mom,
+                                                        const double* __restrict__ gpc, Real* __restrict__ R) {
   constexpr int M = NComp<EQ>::m;
   const int gid = blockIdx.x * kBlock + threadIdx.x;
   const int i = gid / M, q = gid - (gid / M) * M;
-  if (i >= N) return;
-  recon_point<EQ, Real>(i, q, N, NB, P, wbar, grad, nbr, bnd_n, p1, p2, area, mom, R);
+  if constexpr (EQ == EQ_EUL) {
+    // all four component lanes of a cell stay active for the limiter's shuffles
+    const bool valid = i < N;
+    const int ic = valid ? i : N - 1;
+    Real a[6];
+    recon_coeffs<EQ, Real>(ic, q, N, NB, P, wbar, grad, nbr, bnd_n, p1, p2, area, mom, a);
+    if (P.positivity) {
+      const int lane0 = (threadIdx.x & 63) & ~3;
+      Real all[4][6];
+      double Wb[4];
+      const double w0 = wbar[q * size_t(N) + ic];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) all[c][j] = __shfl(a[j], lane0 + c);
+        Wb[c] = __shfl(w0, lane0 + c);
+      }
+      double px[6], py[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        px[k] = gpc[(2 * k) * size_t(N) + ic];
+        py[k] = gpc[(2 * k + 1) * size_t(N) + ic];
+      }
+      double th[4];
+      positivity_theta<Real>(P.gam, Wb, all, px, py, th);
+      const Real tq = Real(th[q]);
+#pragma unroll
+      for (int j = 0; j < 6; ++j) a[j] *= tq;
+    }
+    if (valid) store_coeffs<EQ, Real>(i, q, N, a, R);
+  } else {
+    if (i >= N) return;
+    Real a[6];
+    recon_coeffs<EQ, Real>(i, q, N, NB, P, wbar, grad, nbr, bnd_n, p1, p2, area, mom, a);
+    store_coeffs<EQ, Real>(i, q, N, a, R);
+  }
 }
 
 template <class Real> __device__ __forceinline__ Real xor_shfl(Real v, int mask) { return __shfl_xor(v, mask); }
@@ -242,7 +277,7 @@ hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, cons
   if (d.prof_n < d.prof_cap) ev = reinterpret_cast<hipEvent_t*>(&M->d.prof_ev[4 * size_t(d.prof_n)]);
   if (ev) hipEventRecord(ev[0], st);
   hipLaunchKernelGGL((recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * Mc)), dim3(kBlock), 0, st, N, NB, P, wbar_in, grad_in,
-                     d.nbr, d.bnd_n, p1, p2, d.area, mom, R);
+                     d.nbr, d.bnd_n, p1, p2, d.area, mom, d.gpc, R);
   if (ev) hipEventRecord(ev[1], st);
   hipLaunchKernelGGL((edge_kernel<EQ, Real>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, P, dt,
                      wbar_in, R, d.ecell, d.enl, egp, F, G);
@@ -266,7 +301,7 @@ hwe_status recon_impl(hwe_mesh_s* M, const Params& P, const double* wbar, const 
   const int N = int(h.N), NB = int(h.NB);
   constexpr int Mc = NComp<EQ>::m;
   hipLaunchKernelGGL((recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * Mc)), dim3(kBlock), 0, st, N, NB, P, wbar, grad, d.nbr,
-                     d.bnd_n, p1, p2, d.area, mom, R);
+                     d.bnd_n, p1, p2, d.area, mom, d.gpc, R);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return hip_fail(err, "kernel launch");
   return HWE_OK;
@@ -276,6 +311,7 @@ hwe_status recon_impl(hwe_mesh_s* M, const Params& P, const double* wbar, const 
 
 Params params_of(const hwe_opts& o) {
   Params P;
+  P.positivity = o.positivity ? 1 : 0;
   P.ax = o.adv[0];
   P.ay = o.adv[1];
   P.gam = o.gas_gamma;
@@ -303,6 +339,7 @@ hwe_status upload_mesh(hwe_mesh_s* M) {
   HWE_TRY(dev_copy(&d.bnd_n, h.bnd_n.data(), h.bnd_n.size()));
   HWE_TRY(dev_copy(&d.area, h.area.data(), h.area.size()));
   HWE_TRY(dev_copy(&d.inv_area, h.inv_area.data(), h.inv_area.size()));
+  if (M->opts.positivity) HWE_TRY(dev_copy(&d.gpc, h.gpc.data(), h.gpc.size()));
   const size_t N = size_t(h.N), E = size_t(h.E), m = size_t(h.m);
   HWE_TRY(dev_copy(&d.enl, h.egeo.data(), 3 * E));
   if (M->opts.prec == HWE_FP64) {
@@ -333,7 +370,7 @@ void free_device(hwe_mesh_s* M) {
   if (d.device < 0) return;
   hipSetDevice(d.device);
   hipDeviceSynchronize();
-  void* ptrs[] = {d.nbr, d.cell_edge, d.ecell, d.bnd_n, d.area, d.mom, d.p1,   d.p2, d.nl, d.inv_area, d.enl,
+  void* ptrs[] = {d.nbr, d.cell_edge, d.ecell, d.bnd_n, d.area, d.mom, d.p1, d.p2, d.nl, d.inv_area, d.gpc, d.enl,
                   d.egp, d.p1f,       d.p2f,   d.nlf,   d.egpf, d.momf, d.R,  d.F,  d.G,  d.red,      d.redi};
   for (void* p : ptrs)
     if (p) hipFree(p);

@@ -29,6 +29,7 @@ struct Params {
   double lw[4];    // linear weights gamma_1..4
   double eps;      // epsilon of the nonlinear weights
   int linear;      // 1: omega = gamma
+  int positivity;  // 1: scaling limiter on the Euler reconstruction
 };
 
 template <class T> struct SJ {  // spatial jet

@@ -14,13 +14,14 @@ namespace hwe {
 
 // ------------------------------------------------------------------ Steps 1-6
 // Reconstruction of component q of cell i (Sec. 2.2).
+// Writes the six coefficients a0..a5 of R - Wbar (monomials about the centroid).
 template <int EQ, class Real>
-__host__ __device__ __forceinline__ void recon_point(int i, int q, int N, int NB, const Params& P,
-                                                    const double* __restrict__ wbar, const Real* __restrict__ grad,
-                                                    const int32_t* __restrict__ nbr, const double* __restrict__ bnd_n,
-                                                    const Real* __restrict__ p1, const Real* __restrict__ p2,
-                                                    const double* __restrict__ area, const Real* __restrict__ mom,
-                                                    Real* __restrict__ R) {
+__host__ __device__ __forceinline__ void recon_coeffs(int i, int q, int N, int NB, const Params& P,
+                                                     const double* __restrict__ wbar, const Real* __restrict__ grad,
+                                                     const int32_t* __restrict__ nbr, const double* __restrict__ bnd_n,
+                                                     const Real* __restrict__ p1, const Real* __restrict__ p2,
+                                                     const double* __restrict__ area, const Real* __restrict__ mom,
+                                                     Real (&a)[6]) {
   constexpr int M = NComp<EQ>::m;
   const double W0 = wbar[q * N + i];
   double Wsum = W0, dW[3];
@@ -110,13 +111,77 @@ __host__ __device__ __forceinline__ void recon_point(int i, int q, int N, int NB
     R2 += kl * cl[f];
   }
   const Real R3 = k1 * c[2], R4 = k1 * c[3], R5 = k1 * c[4];
-  const Real a0 = -(R3 * mom[i] + R4 * mom[sN + i] + R5 * mom[2 * sN + i]);
-  R[(0 * M + q) * sN + i] = a0;
-  R[(1 * M + q) * sN + i] = R1;
-  R[(2 * M + q) * sN + i] = R2;
-  R[(3 * M + q) * sN + i] = R3;
-  R[(4 * M + q) * sN + i] = R4;
-  R[(5 * M + q) * sN + i] = R5;
+  a[0] = -(R3 * mom[i] + R4 * mom[sN + i] + R5 * mom[2 * sN + i]);
+  a[1] = R1;
+  a[2] = R2;
+  a[3] = R3;
+  a[4] = R4;
+  a[5] = R5;
+}
+
+template <int EQ, class Real>
+__host__ __device__ __forceinline__ void store_coeffs(int i, int q, int N, const Real (&a)[6], Real* __restrict__ R) {
+  constexpr int M = NComp<EQ>::m;
+  const size_t sN = size_t(N);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) R[(j * M + q) * sN + i] = a[j];
+}
+
+// Positivity-preserving scaling of the Euler reconstruction of one cell (the
+// scale limiter of Zhang and Shu cited in Sec. 3), in FP64.  a[q][0..5]: the
+// coefficients of R - Wbar per component, px/py: the six edge Gauss points of
+// the cell relative to its centroid.  With eps = min(1e-13, rho_bar, p_bar):
+// theta_rho scales the density part so that rho >= eps at the points; then t
+// is the smallest root in [0, 1] of p(Wbar + t (W - Wbar)) = eps over the
+// points where p < eps, solved through
+//   g(t) = 2 rho(t) (E(t) - eps/(gamma-1)) - |m(t)|^2 = A t^2 + B t + C.
+// Results: theta[0] = theta_rho t, theta[1..3] = t (1 where inactive).
+template <class Real>
+__host__ __device__ __forceinline__ void positivity_theta(double gam, const double (&Wb)[4], const Real (&a)[4][6],
+                                                         const double (&px)[6], const double (&py)[6],
+                                                         double (&theta)[4]) {
+  const double gm1 = gam - 1.0;
+  const double pbar = gm1 * (Wb[3] - 0.5 * (Wb[1] * Wb[1] + Wb[2] * Wb[2]) / Wb[0]);
+  const double eps = fmin(1e-13, fmin(Wb[0], pbar));
+  double d[6][4];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double X = px[k], Y = py[k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      d[k][q] = double(a[q][0]) + double(a[q][1]) * X + double(a[q][2]) * Y + double(a[q][3]) * X * X +
+                double(a[q][4]) * X * Y + double(a[q][5]) * Y * Y;
+  }
+  double rmin = 1e300;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) rmin = fmin(rmin, Wb[0] + d[k][0]);
+  const double th_rho = rmin < eps ? (Wb[0] - eps) / (Wb[0] - rmin) : 1.0;
+  double t = 1.0;
+  const double Ep = Wb[3] - eps / gm1;
+  const double C = 2.0 * Wb[0] * Ep - (Wb[1] * Wb[1] + Wb[2] * Wb[2]);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double dr = th_rho * d[k][0], d1 = d[k][1], d2 = d[k][2], dE = d[k][3];
+    const double r = Wb[0] + dr, m1 = Wb[1] + d1, m2 = Wb[2] + d2, En = Wb[3] + dE;
+    const double p = gm1 * (En - 0.5 * (m1 * m1 + m2 * m2) / r);
+    if (!(p < eps)) continue;
+    const double A = 2.0 * dr * dE - (d1 * d1 + d2 * d2);
+    const double B = 2.0 * (Ep * dr + Wb[0] * dE) - 2.0 * (Wb[1] * d1 + Wb[2] * d2);
+    double root;
+    if (A == 0.0) {
+      root = -C / B;
+    } else {
+      const double disc = fmax(B * B - 4.0 * A * C, 0.0);
+      const double sq = sqrt(disc);
+      const double qq = B >= 0.0 ? -0.5 * (B + sq) : -0.5 * (B - sq);
+      const double r1 = qq / A, r2 = C / qq;
+      const bool ok1 = r1 >= 0.0 && r1 <= 1.0, ok2 = r2 >= 0.0 && r2 <= 1.0;
+      root = (ok1 && ok2) ? (r1 <= r2 ? r1 : r2) : (ok1 ? r1 : r2);
+    }
+    t = root < t ? root : t;
+  }
+  theta[0] = th_rho * t;
+  theta[1] = theta[2] = theta[3] = t;
 }
 
 // ------------------------------------------------------------------ edge lane

@@ -26,7 +26,8 @@ def _stream(stream=None):
 
 
 def make_opts(eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp64", adv=(1.0, 1.0),
-              gas_gamma=1.4, lin_w=(0.94, 0.02, 0.02, 0.02), eps=1e-8, linear_weights=False, device=0) -> HweOpts:
+              gas_gamma=1.4, lin_w=(0.94, 0.02, 0.02, 0.02), eps=1e-8, linear_weights=False, device=0,
+              positivity=False) -> HweOpts:
     L = load_library()
     o = HweOpts()
     check(L.hwe_opts_default(C.byref(o)))
@@ -40,6 +41,7 @@ def make_opts(eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp
     o.lin_w[:] = [float(v) for v in lin_w]
     o.eps = float(eps)
     o.device = int(device)
+    o.positivity = 1 if positivity else 0
     return o
 
 
@@ -155,6 +157,25 @@ class Mesh:
             hwe_step(self._h, a[0], a[1], dst[0], dst[1], dt, stream)
             a = dst
         return a
+
+    def run_to(self, wbar, grad, T, cfl, every=50, stream=None):
+        """Advance to time T with dt = cfl * min inradius / max signal speed,
+        recomputed on the device from the current state every ``every`` steps
+        (the last step is clipped to end at T).  Returns (wbar, grad, steps)."""
+        bufs = [(wbar, grad), self.empty_state(), self.empty_state()]
+        cur, t, steps = 0, 0.0, 0
+        while T - t > 1e-14 * T:
+            dt = self.max_dt(bufs[cur][0], cfl, stream)
+            for _ in range(every):
+                h = min(dt, T - t)
+                if h <= 1e-14 * T:
+                    break
+                nxt = 1 if cur != 1 else 2
+                hwe_step(self._h, bufs[cur][0], bufs[cur][1], bufs[nxt][0], bufs[nxt][1], h, stream)
+                cur = nxt
+                t += h
+                steps += 1
+        return bufs[cur][0], bufs[cur][1], steps
 
     def adjoint(self, wbar, grad, lam_wbar, lam_grad, dt, out=None, stream=None):
         self._check_state(wbar, grad)
