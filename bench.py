@@ -81,6 +81,54 @@ def gpu_leg(wl, steps, warmup, precision):
     return dict(mesh=mesh, dt=dt, ms=ms, wall=t_wall, flags=flags, kernel_ms=[k / nk for k in kms])
 
 
+def adjoint_leg(wl, nsteps=200, ckpt=20, precision="fp64"):
+    """C5: misfit gradient through a checkpointed rollout; backward/forward time."""
+    import torch
+    from paper_2607_10809_amd.autograd import rollout
+    from paper_2607_10809_amd.hwe import Mesh
+    from workloads import cell_average_states, make_vortex, perturbed_vortex_target_center
+    mesh = Mesh.from_workload(wl, precision=precision)
+    w0, g0 = mesh.to_device(wl.state0)
+    dt = mesh.max_dt(w0, wl.cfl)
+    tw, tg = mesh.to_device(cell_average_states(wl.mesh, make_vortex(center=perturbed_vortex_target_center())))
+    tgt = mesh.run(tw, tg, dt, nsteps)[0][0].clone()
+    stream = torch.cuda.current_stream()
+
+    def once():
+        w = w0.clone().requires_grad_(True)
+        g = g0.clone().requires_grad_(True)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        wT, gT = rollout(mesh, w, g, dt, nsteps, ckpt)
+        e[1].record(stream)
+        loss = 0.5 * ((wT[0] - tgt) ** 2).sum()
+        loss.backward()
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+
+    once()
+    f, b = once()
+    # per-step kernel time: adjoint step vs forward step on the same state
+    la, lg = mesh.empty_state()
+    la.normal_()
+    lg.normal_()
+    out = mesh.empty_state()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    for _ in range(100):
+        mesh.step(w0, g0, dt, out=out)
+    ev[1].record(stream)
+    for _ in range(100):
+        mesh.adjoint(w0, g0, la, lg, dt, out=out)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    fs, as_ = ev[0].elapsed_time(ev[1]) / 100, ev[1].elapsed_time(ev[2]) / 100
+    return {"forward_ms": f, "backward_ms": b, "ratio": b / f, "steps": nsteps, "ckpt": ckpt,
+            "step_us": fs * 1e3, "adjoint_step_us": as_ * 1e3, "per_step_ratio": as_ / fs}
+
+
 def cpu_leg(wl, budget_s=12.0):
     from oracle import OracleMesh
     om = OracleMesh.from_workload(wl)
@@ -125,6 +173,11 @@ def main():
     log(f"FP64: {f64['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {f64['kernel_ms']}")
     mix = gpu_leg(wl, args.steps, args.warmup, "mixed")
     log(f"mixed: {mix['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {mix['kernel_ms']}")
+    adj = adjoint_leg(wl)
+    log(f"adjoint (FP64, 200 steps, checkpoint 20): forward {adj['forward_ms']:.1f} ms, backward "
+        f"{adj['backward_ms']:.1f} ms, ratio {adj['ratio']:.2f}; per step {adj['adjoint_step_us']:.1f} us vs "
+        f"{adj['step_us']:.1f} us")
+    adjm = adjoint_leg(wl, precision="mixed")
     E, m = f64["mesh"].E, f64["mesh"].m
     value = N * args.steps / (f64["ms"] * 1e-3)
     value_mixed = N * args.steps / (mix["ms"] * 1e-3)
@@ -161,7 +214,9 @@ def main():
                    "dt": f64["dt"], "parallelism": "1 GPU"},
         "mixed": {"value": value_mixed, "ms_per_step": mix["ms"] / args.steps, "dtype": "f32 bulk + f64 averages/weights",
                   "speedup_vs_fp64": value_mixed / value},
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": adj["ratio"],
+        "adjoint": {"fp64": adj, "mixed": adjm,
+                    "workload": "misfit 0.5|rho(T)-rho_target|^2, 200 steps, checkpoint every 20, same mesh"},
         "step_alg_bytes": {"fp64": int(step_bytes), "mixed": int(sum(kbm.values()))},
         "step_GBps": {"fp64": round(step_bytes / (f64["ms"] / args.steps * 1e-3) / 1e9, 1),
                       "mixed": round(sum(kbm.values()) / (mix["ms"] / args.steps * 1e-3) / 1e9, 1)},

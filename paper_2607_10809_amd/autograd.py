@@ -1,0 +1,60 @@
+"""Differentiable multi-step rollout of the HIP step with step checkpointing.
+
+``rollout(mesh, wbar0, grad0, dt, n_steps, ckpt)`` runs ``n_steps`` explicit
+steps (hwe_step) and returns the final state; its backward pass applies the
+hand-written adjoint (hwe_step_adjoint) in reverse.  Only every ``ckpt``-th
+state is kept during the forward pass; the backward pass recomputes each
+segment of ``ckpt`` steps from its checkpoint, then walks it backwards.
+The time step is a constant (not differentiated).
+"""
+from __future__ import annotations
+
+import torch
+
+
+class Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, wbar0, grad0, mesh, dt, n_steps, ckpt):
+        if ckpt <= 0:
+            raise ValueError("ckpt must be positive")
+        if mesh.opts.positivity:
+            raise ValueError("the positivity limiter is not differentiated; build the mesh without it")
+        checkpoints = [(wbar0.detach().clone(), grad0.detach().clone())]
+        cur = (checkpoints[0][0], checkpoints[0][1])
+        bufs = [mesh.empty_state(), mesh.empty_state()]
+        for k in range(n_steps):
+            nxt = bufs[k % 2]
+            mesh.step(cur[0], cur[1], dt, out=nxt)
+            cur = nxt
+            if (k + 1) % ckpt == 0 and k + 1 < n_steps:
+                checkpoints.append((cur[0].clone(), cur[1].clone()))
+        ctx.mesh, ctx.dt, ctx.n_steps, ctx.ckpt = mesh, dt, n_steps, ckpt
+        ctx.checkpoints = checkpoints
+        return cur[0].clone(), cur[1].clone()
+
+    @staticmethod
+    def backward(ctx, lw, lg):
+        mesh, dt, n, ckpt = ctx.mesh, ctx.dt, ctx.n_steps, ctx.ckpt
+        lam = (lw.contiguous().to(torch.float64), lg.contiguous().to(mesh.gdtype))
+        nseg = len(ctx.checkpoints)
+        out = [mesh.empty_state(), mesh.empty_state()]
+        flip = 0
+        for s in reversed(range(nseg)):
+            start = s * ckpt
+            length = min(ckpt, n - start)
+            # recompute the states of the segment
+            states = [ctx.checkpoints[s]]
+            for k in range(length - 1):
+                states.append(mesh.step(states[-1][0], states[-1][1], dt))
+            for k in reversed(range(length)):
+                dst = out[flip]
+                flip ^= 1
+                mesh.adjoint(states[k][0], states[k][1], lam[0], lam[1], dt, out=dst)
+                lam = dst
+            ctx.checkpoints[s] = None
+        return lam[0].clone(), lam[1].clone(), None, None, None, None
+
+
+def rollout(mesh, wbar0, grad0, dt, n_steps, ckpt=20):
+    """Final state after n_steps steps; differentiable with respect to (wbar0, grad0)."""
+    return Rollout.apply(wbar0, grad0, mesh, float(dt), int(n_steps), int(ckpt))

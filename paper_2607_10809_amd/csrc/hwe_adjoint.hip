@@ -1,0 +1,292 @@
+// Adjoint (vector-Jacobian product) of one explicit step, for gfx950.
+//
+//   hwe_step_adjoint(state_n, lam_{n+1}) = J(state_n)^T lam_{n+1}
+//
+// Three launches on the caller's stream, none with atomics:
+//   1. the forward reconstruction kernel (R of every cell at state_n);
+//   2. adj_cell_kernel, four work-items per cell.  Work-items 0-2 take the
+//      cell's faces: from the cell's and the neighbour's lam_{n+1} they form the
+//      adjoints of the edge flux F_e and of the interface-value integral G_e,
+//      then reverse the cell's own side of the edge (Lax-Wendroff, Taylor
+//      extrapolation, offset-form normal flux at both Gauss points) and the
+//      flux base terms.  The four work-items sum their results with cross-lane
+//      shuffles; work-item q then reverses the reconstruction of component q
+//      (Steps 1-6, including the nonlinear-weight derivatives) into four
+//      stencil "slots" (the cell itself and its three neighbours).
+//   3. adj_gather_kernel, one work-item per cell: its own slot, the slots its
+//      neighbours wrote for it, the Green-Gauss terms of the derivative
+//      averages and the derivative of the flux viscosity alpha (only on the
+//      cell whose spectral radius the max selected).
+#include <hip/hip_runtime.h>
+
+#include "hwe_adjoint_math.h"
+#include "hwe_internal.h"
+
+namespace hwe {
+
+hwe_status hip_fail(hipError_t err, const char* what);
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <class T> __device__ __forceinline__ T xshfl(T v, int mask) { return __shfl_xor(v, mask); }
+
+template <int EQ, class Real>
+__global__ __launch_bounds__(kBlock) void adj_cell_kernel(
+    int N, int E, int NB, Params P, double dt, const double* __restrict__ wbar, const Real* __restrict__ grad,
+    const double* __restrict__ lw, const Real* __restrict__ lg, const Real* __restrict__ R,
+    const int32_t* __restrict__ nbr, const int32_t* __restrict__ cell_edge, const int32_t* __restrict__ ecell,
+    const double* __restrict__ enl, const Real* __restrict__ egp, const double* __restrict__ inv_area,
+    const Real* __restrict__ nl, const double* __restrict__ bnd_n, const Real* __restrict__ p1,
+    const Real* __restrict__ p2, const double* __restrict__ area, const Real* __restrict__ mom,
+    double* __restrict__ slots, double* __restrict__ sface) {
+  constexpr int M = NComp<EQ>::m;
+  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int i = gid >> 2, lane = gid & 3;
+  const bool valid = i < N;
+  const int ic = valid ? i : N - 1;
+  const size_t sN = size_t(N), sE = size_t(E);
+  Real la[6][M];
+  double lWf[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    lWf[q] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) la[j][q] = Real(0);
+  }
+  if (lane < 3) {
+    const int f = lane;
+    const int ce = cell_edge[f * sN + ic];
+    const int e = ce >> 1, side = ce & 1;
+    const int c0 = ecell[e], c1 = ecell[sE + e];
+    const int nb = side ? c0 : c1;
+    const double nx = enl[e], ny = enl[sE + e], len = enl[2 * sE + e];
+    const double sigma = side ? -1.0 : 1.0;
+    const double iaK = inv_area[ic];
+    const double nlx = double(nl[f * sN + ic]), nly = double(nl[(3 + f) * sN + ic]);
+    double WK[M], Wn[M], lF[M], lG[M];
+    const double ian = nb >= 0 ? inv_area[nb] : 0.0;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      WK[q] = wbar[q * sN + ic];
+      Wn[q] = nb >= 0 ? wbar[q * sN + nb] : WK[q];
+      const double lwK = lw[q * sN + ic];
+      const double lgxK = double(lg[q * sN + ic]), lgyK = double(lg[(M + q) * sN + ic]);
+      if (nb >= 0) {
+        lF[q] = -dt * sigma * (iaK * lwK - ian * lw[q * sN + nb]);
+        lG[q] = nlx * (iaK * lgxK - ian * double(lg[q * sN + nb])) + nly * (iaK * lgyK - ian * double(lg[(M + q) * sN + nb]));
+      } else {
+        lF[q] = -dt * iaK * lwK;
+        lG[q] = iaK * (nlx * lgxK + nly * lgyK);
+      }
+    }
+    double alpha = 0.0;
+    if (nb >= 0) {
+      const double la0 = side ? spectral_radius<EQ>(P, Wn, nx, ny) : spectral_radius<EQ>(P, WK, nx, ny);
+      const double la1 = side ? spectral_radius<EQ>(P, WK, nx, ny) : spectral_radius<EQ>(P, Wn, nx, ny);
+      alpha = la0 >= la1 ? la0 : la1;
+    }
+    // flux base terms:  d/dWbar_K of |e| 1/2 (H(Wbar_K) + sigma alpha Wbar_K) . lF
+    if (nb >= 0) {
+      normal_flux_jt<EQ>(P, WK, nx, ny, lF, 0.5 * len, lWf);
+#pragma unroll
+      for (int q = 0; q < M; ++q) lWf[q] += 0.5 * len * sigma * alpha * lF[q];
+    } else {
+      normal_flux_jt<EQ>(P, WK, nx, ny, lF, len, lWf);
+    }
+    // seeds of each Gauss-point lane (Gauss weights 1/2)
+    Real sAH[M], sAD[M], sAT[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      if (nb >= 0) {
+        sAH[q] = Real(0.25 * len * lF[q]);
+        sAD[q] = Real(0.25 * len * sigma * alpha * lF[q]);
+        sAT[q] = Real(0.25 * lG[q]);
+      } else {
+        sAH[q] = Real(0.5 * len * lF[q]);
+        sAD[q] = Real(0);
+        sAT[q] = Real(0.5 * lG[q]);
+      }
+    }
+    Real a[6][M];
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+#pragma unroll
+      for (int q = 0; q < M; ++q) a[j][q] = R[(j * M + q) * sN + ic];
+    double s = 0.0;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const Real X = egp[(4 * side + 2 * g) * sE + e];
+      const Real Y = egp[(4 * side + 2 * g + 1) * sE + e];
+      Real ADg[M];
+      edge_lane_rev<EQ, Real>(P, dt, a, WK, X, Y, Real(nx), Real(ny), sAH, sAD, sAT, la, lWf, ADg);
+#pragma unroll
+      for (int q = 0; q < M; ++q) s += 0.5 * lF[q] * double(ADg[q]);
+    }
+    if (valid) sface[f * sN + ic] = s;
+  }
+  // sum over the cell's lanes
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    lWf[q] += xshfl(lWf[q], 1);
+    lWf[q] += xshfl(lWf[q], 2);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      la[j][q] += xshfl(la[j][q], 1);
+      la[j][q] += xshfl(la[j][q], 2);
+    }
+  }
+  if (lane < M && valid) {
+    const int q = lane;
+    Real laq[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) laq[j] = la[j][0];
+    if constexpr (M == 4) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) laq[j] = q == 0 ? la[j][0] : (q == 1 ? la[j][1] : (q == 2 ? la[j][2] : la[j][3]));
+    }
+    double lwq = lWf[0];
+    if constexpr (M == 4) lwq = q == 0 ? lWf[0] : (q == 1 ? lWf[1] : (q == 2 ? lWf[2] : lWf[3]));
+    double slot[4][3];
+    recon_rev<EQ, Real>(i, q, N, NB, P, wbar, grad, nbr, bnd_n, p1, p2, area, mom, laq, slot);
+    slot[0][0] += lwq;
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+      for (int fl = 0; fl < 3; ++fl) slots[((sl * 3 + fl) * M + q) * sN + i] = slot[sl][fl];
+  }
+}
+
+template <int EQ, class Real>
+__global__ __launch_bounds__(kBlock) void adj_gather_kernel(
+    int N, int E, Params P, double dt, const double* __restrict__ wbar, const double* __restrict__ lw,
+    const Real* __restrict__ lg, const int32_t* __restrict__ nbr, const int32_t* __restrict__ nbr_back,
+    const int32_t* __restrict__ cell_edge, const int32_t* __restrict__ ecell, const double* __restrict__ enl,
+    const double* __restrict__ inv_area, const Real* __restrict__ nl, const double* __restrict__ slots,
+    const double* __restrict__ sface, double* __restrict__ lw_out, Real* __restrict__ lg_out) {
+  constexpr int M = NComp<EQ>::m;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= N) return;
+  const size_t sN = size_t(N), sE = size_t(E);
+  const double iaK = inv_area[i];
+  double aW[M], aV[M], aY[M], WK[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    WK[q] = wbar[q * sN + i];
+    aW[q] = lw[q * sN + i] + slots[((0 * 3 + 0) * M + q) * sN + i];
+    aV[q] = slots[((0 * 3 + 1) * M + q) * sN + i];
+    aY[q] = slots[((0 * 3 + 2) * M + q) * sN + i];
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int nb = nbr[f * sN + i];
+    if (nb < 0) continue;
+    const int bk = nbr_back[f * sN + i];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      aW[q] += slots[(((1 + bk) * 3 + 0) * M + q) * sN + nb];
+      aV[q] += slots[(((1 + bk) * 3 + 1) * M + q) * sN + nb];
+      aY[q] += slots[(((1 + bk) * 3 + 2) * M + q) * sN + nb];
+    }
+    // Green-Gauss: |K| Vbar_K includes n|e| (Wbar_nb - Wbar_K)/2 (and the neighbour's the mirror term)
+    const double nlx = double(nl[f * sN + i]), nly = double(nl[(3 + f) * sN + i]);
+    const double ian = inv_area[nb];
+#pragma unroll
+    for (int q = 0; q < M; ++q)
+      aW[q] += -0.5 * (nlx * (iaK * double(lg[q * sN + i]) + ian * double(lg[q * sN + nb])) +
+                       nly * (iaK * double(lg[(M + q) * sN + i]) + ian * double(lg[(M + q) * sN + nb])));
+    // flux viscosity: alpha = max(lambda(Wbar_0), lambda(Wbar_1)), first cell on ties
+    const int ce = cell_edge[f * sN + i];
+    const int e = ce >> 1, side = ce & 1;
+    const int c0 = ecell[e], c1 = ecell[sE + e];
+    const double nx = enl[e], ny = enl[sE + e], len = enl[2 * sE + e];
+    double W0[M], W1[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      W0[q] = wbar[q * sN + c0];
+      W1[q] = wbar[q * sN + c1];
+    }
+    const double l0 = spectral_radius<EQ>(P, W0, nx, ny), l1 = spectral_radius<EQ>(P, W1, nx, ny);
+    const bool mine = (l0 >= l1) ? (side == 0) : (side == 1);
+    if (!mine) continue;
+    const double ia0 = inv_area[c0], ia1 = inv_area[c1];
+    double jb = 0.0;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const double lFq = -dt * (ia0 * lw[q * sN + c0] - ia1 * lw[q * sN + c1]);
+      jb += lFq * (W1[q] - W0[q]);
+    }
+    const double sown = sface[f * sN + i], soth = sface[bk * sN + nb];
+    const double s0 = side == 0 ? sown : soth, s1 = side == 0 ? soth : sown;
+    jb += s1 - s0;
+    spectral_radius_grad<EQ>(P, WK, nx, ny, -0.5 * len * jb, aW);
+  }
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    lw_out[q * sN + i] = aW[q];
+    lg_out[q * sN + i] = Real(aV[q]);
+    lg_out[(M + q) * sN + i] = Real(aY[q]);
+  }
+}
+
+unsigned grid_for(int64_t items) { return unsigned((items + kBlock - 1) / kBlock); }
+
+template <int EQ, class Real>
+hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, const Real* grad, const double* lw,
+                        const Real* lg, double* lw_out, Real* lg_out, double dt, hipStream_t st, const Real* p1,
+                        const Real* p2, const Real* nl, const Real* egp, const Real* mom) {
+  const HostMesh& h = M->h;
+  const DevMesh& d = M->d;
+  const int N = int(h.N), E = int(h.E), NB = int(h.NB);
+  const Real* R = static_cast<const Real*>(d.R);
+  hipLaunchKernelGGL((adj_cell_kernel<EQ, Real>), dim3(grid_for(4 * int64_t(N))), dim3(kBlock), 0, st, N, E, NB, P,
+                     dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.ecell, d.enl, egp, d.inv_area, nl, d.bnd_n, p1,
+                     p2, d.area, mom, d.slots, d.sface);
+  hipLaunchKernelGGL((adj_gather_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg,
+                     d.nbr, d.nbr_back, d.cell_edge, d.ecell, d.enl, d.inv_area, nl, d.slots, d.sface, lw_out,
+                     lg_out);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return hip_fail(err, "kernel launch");
+  return HWE_OK;
+}
+
+}  // namespace
+
+hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_n, const double* lw, const void* lg,
+                          double* lw_out, void* lg_out, double dt, void* stream) {
+  hwe_status s = launch_recon(M, wbar_n, grad_n, M->d.R, stream);
+  if (s != HWE_OK) return s;
+  const Params P = params_of(M->opts);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevMesh& d = M->d;
+  if (M->opts.prec == HWE_FP64) {
+    auto g = static_cast<const double*>(grad_n);
+    auto l = static_cast<const double*>(lg);
+    auto o = static_cast<double*>(lg_out);
+    switch (M->opts.eq) {
+      case HWE_ADVECTION:
+        return adjoint_impl<EQ_ADV, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+      case HWE_BURGERS:
+        return adjoint_impl<EQ_BUR, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+      default:
+        return adjoint_impl<EQ_EUL, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+    }
+  }
+  auto g = static_cast<const float*>(grad_n);
+  auto l = static_cast<const float*>(lg);
+  auto o = static_cast<float*>(lg_out);
+  switch (M->opts.eq) {
+    case HWE_ADVECTION:
+      return adjoint_impl<EQ_ADV, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1f, d.p2f, d.nlf, d.egpf,
+                                         d.momf);
+    case HWE_BURGERS:
+      return adjoint_impl<EQ_BUR, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1f, d.p2f, d.nlf, d.egpf,
+                                         d.momf);
+    default:
+      return adjoint_impl<EQ_EUL, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1f, d.p2f, d.nlf, d.egpf,
+                                         d.momf);
+  }
+}
+
+}  // namespace hwe

@@ -29,6 +29,7 @@ struct HostMesh {
   std::vector<double> area;        // [N]
   std::vector<double> mom;         // [3][N] central second moments Mxx, Mxy, Myy
   std::vector<int32_t> nbr;        // [3][N] neighbour across face f; -(b+1) for boundary face b
+  std::vector<int32_t> nbr_back;   // [3][N] the neighbour's face index that points back (-1 on boundary)
   std::vector<double> bnd_n;       // [2][NB] outward unit normal of boundary face b
   std::vector<double> p1;          // [55][N] Step-1 map (row-major 5 x 11 per cell)
   std::vector<double> p2;          // [9][N] Step-2 data
@@ -49,6 +50,7 @@ struct DevMesh {
   int32_t* nbr = nullptr;
   int32_t* cell_edge = nullptr;
   int32_t* ecell = nullptr;
+  int32_t* nbr_back = nullptr;
   // FP64 geometry / tables
   double* bnd_n = nullptr;
   double* area = nullptr;
@@ -72,6 +74,9 @@ struct DevMesh {
   void* R = nullptr;
   void* F = nullptr;
   void* G = nullptr;
+  // adjoint scratch: stencil-slot adjoints [4][3][m][N] and per-face scalars [3][N]
+  double* slots = nullptr;
+  double* sface = nullptr;
   // reductions
   double* red = nullptr;   // [kRedBlocks]
   int32_t* redi = nullptr; // [kRedBlocks]
@@ -108,5 +113,8 @@ hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_
 hwe_status launch_max_dt(hwe_mesh_s* M, const double* wbar, double cfl, double* dt_dev, void* stream);
 hwe_status launch_check(hwe_mesh_s* M, const double* wbar, int32_t* flags, void* stream);
 hwe_status profile_begin(hwe_mesh_s* M, int n_steps);
+// Equation parameters of a handle, as passed to the kernels.
+struct Params;
+Params params_of(const hwe_opts& o);
 hwe_status profile_end(hwe_mesh_s* M, double* ms_sum, int* n_done);
 }  // namespace hwe

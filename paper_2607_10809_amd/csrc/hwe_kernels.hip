@@ -230,12 +230,16 @@ __global__ __launch_bounds__(kBlock) void finish_or_kernel(int nparts, const int
 }
 
 // ---------------------------------------------------------------- helpers
+}  // namespace
+
 hwe_status hip_fail(hipError_t err, const char* what) {
   std::ostringstream s;
   s << what << ": " << hipGetErrorString(err);
   set_error(s.str());
   return HWE_EHIP;
 }
+
+namespace {
 
 template <class T>
 hwe_status dev_copy(T** dst, const T* src, size_t n) {
@@ -336,6 +340,7 @@ hwe_status upload_mesh(hwe_mesh_s* M) {
   HWE_TRY(dev_copy(&d.nbr, h.nbr.data(), h.nbr.size()));
   HWE_TRY(dev_copy(&d.cell_edge, h.cell_edge.data(), h.cell_edge.size()));
   HWE_TRY(dev_copy(&d.ecell, h.ecell.data(), h.ecell.size()));
+  HWE_TRY(dev_copy(&d.nbr_back, h.nbr_back.data(), h.nbr_back.size()));
   HWE_TRY(dev_copy(&d.bnd_n, h.bnd_n.data(), h.bnd_n.size()));
   HWE_TRY(dev_copy(&d.area, h.area.data(), h.area.size()));
   HWE_TRY(dev_copy(&d.inv_area, h.inv_area.data(), h.inv_area.size()));
@@ -359,6 +364,8 @@ hwe_status upload_mesh(hwe_mesh_s* M) {
   HWE_TRY(dev_alloc(&d.R, 6 * m * N * rs));
   HWE_TRY(dev_alloc(&d.F, m * E * sizeof(double)));
   HWE_TRY(dev_alloc(&d.G, m * E * rs));
+  HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.slots), 12 * m * N * sizeof(double)));
+  HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.sface), 3 * N * sizeof(double)));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.red), kRedBlocks * sizeof(double)));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.redi), kRedBlocks * sizeof(int32_t)));
 #undef HWE_TRY
@@ -370,8 +377,9 @@ void free_device(hwe_mesh_s* M) {
   if (d.device < 0) return;
   hipSetDevice(d.device);
   hipDeviceSynchronize();
-  void* ptrs[] = {d.nbr, d.cell_edge, d.ecell, d.bnd_n, d.area, d.mom, d.p1, d.p2, d.nl, d.inv_area, d.gpc, d.enl,
-                  d.egp, d.p1f,       d.p2f,   d.nlf,   d.egpf, d.momf, d.R,  d.F,  d.G,  d.red,      d.redi};
+  void* ptrs[] = {d.nbr, d.cell_edge, d.ecell, d.nbr_back, d.bnd_n, d.area, d.mom, d.p1, d.p2, d.nl, d.inv_area,
+                  d.gpc, d.enl, d.egp, d.p1f, d.p2f, d.nlf, d.egpf, d.momf, d.R, d.F, d.G, d.slots, d.sface,
+                  d.red, d.redi};
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (void* e : d.prof_ev) hipEventDestroy(static_cast<hipEvent_t>(e));
@@ -507,10 +515,6 @@ hwe_status profile_end(hwe_mesh_s* M, double* ms_sum, int* n_done) {
   return HWE_OK;
 }
 
-hwe_status launch_adjoint(hwe_mesh_s*, const double*, const void*, const double*, const void*, double*, void*, double,
-                          void*) {
-  set_error("hwe_step_adjoint: not available in this build");
-  return HWE_EINVAL;
-}
+
 
 }  // namespace hwe

@@ -423,6 +423,7 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
   h.area.assign(N, 0);
   h.mom.assign(3 * N, 0);
   h.nbr.assign(3 * N, 0);
+  h.nbr_back.assign(3 * N, -1);
   h.bnd_n.assign(2 * std::max<int64_t>(h.NB, 1), 0);
   h.p1.assign(size_t(kP1) * N, 0);
   h.p2.assign(size_t(kP2) * N, 0);
@@ -467,6 +468,7 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
       if (s >= 0) {
         int64_t kn = s / 3;
         h.nbr[f * N + i] = int32_t(inv[kn]);
+        h.nbr_back[f * N + i] = int32_t(s % 3);
         gn = G[kn];
         cx = gn.cx + shift[6 * k + 2 * f];
         cy = gn.cy + shift[6 * k + 2 * f + 1];
