@@ -153,6 +153,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--n", type=int, default=320, help="squares per side (default: 320 -> 204,800 triangles)")
+    ap.add_argument("--forward-only", action="store_true", help="skip the adjoint leg (for counter runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 20 device copies of 256 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; run with --gpus 1", file=sys.stderr)
@@ -161,6 +164,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": a.numel() * 8, "launches": 20}), flush=True)
+        return
     from paper_2607_10809_amd import _lib
     _lib.load_library()
     from workloads import vortex_workload
@@ -173,11 +184,13 @@ def main():
     log(f"FP64: {f64['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {f64['kernel_ms']}")
     mix = gpu_leg(wl, args.steps, args.warmup, "mixed")
     log(f"mixed: {mix['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {mix['kernel_ms']}")
-    adj = adjoint_leg(wl)
-    log(f"adjoint (FP64, 200 steps, checkpoint 20): forward {adj['forward_ms']:.1f} ms, backward "
-        f"{adj['backward_ms']:.1f} ms, ratio {adj['ratio']:.2f}; per step {adj['adjoint_step_us']:.1f} us vs "
-        f"{adj['step_us']:.1f} us")
-    adjm = adjoint_leg(wl, precision="mixed")
+    adj = adjm = None
+    if not args.forward_only:
+        adj = adjoint_leg(wl)
+        log(f"adjoint (FP64, 200 steps, checkpoint 20): forward {adj['forward_ms']:.1f} ms, backward "
+            f"{adj['backward_ms']:.1f} ms, ratio {adj['ratio']:.2f}; per step {adj['adjoint_step_us']:.1f} us vs "
+            f"{adj['step_us']:.1f} us")
+        adjm = adjoint_leg(wl, precision="mixed")
     E, m = f64["mesh"].E, f64["mesh"].m
     value = N * args.steps / (f64["ms"] * 1e-3)
     value_mixed = N * args.steps / (mix["ms"] * 1e-3)
@@ -214,7 +227,7 @@ def main():
                    "dt": f64["dt"], "parallelism": "1 GPU"},
         "mixed": {"value": value_mixed, "ms_per_step": mix["ms"] / args.steps, "dtype": "f32 bulk + f64 averages/weights",
                   "speedup_vs_fp64": value_mixed / value},
-        "adjoint_forward_ratio": adj["ratio"],
+        "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": {"fp64": adj, "mixed": adjm,
                     "workload": "misfit 0.5|rho(T)-rho_target|^2, 200 steps, checkpoint every 20, same mesh"},
         "step_alg_bytes": {"fp64": int(step_bytes), "mixed": int(sum(kbm.values()))},
