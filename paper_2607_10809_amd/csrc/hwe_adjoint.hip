@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void adj_cell_kernel(
     const Real* __restrict__ p2, const double* __restrict__ area, const Real* __restrict__ mom,
     double* __restrict__ slots, double* __restrict__ sface) {
   constexpr int M = NComp<EQ>::m;
-  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int gid = xcd_block_id() * kBlock + threadIdx.x;
   const int i = gid >> 2, lane = gid & 3;
   const bool valid = i < N;
   const int ic = valid ? i : N - 1;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void adj_gather_kernel(
     const double* __restrict__ inv_area, const Real* __restrict__ nl, const double* __restrict__ slots,
     const double* __restrict__ sface, double* __restrict__ lw_out, Real* __restrict__ lg_out) {
   constexpr int M = NComp<EQ>::m;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = xcd_block_id() * kBlock + threadIdx.x;
   if (i >= N) return;
   const size_t sN = size_t(N), sE = size_t(E);
   const double iaK = inv_area[i];

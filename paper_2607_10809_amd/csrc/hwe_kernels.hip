@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
                                                         const Real* __restrict__ mom,
                                                         const double* __restrict__ gpc, Real* __restrict__ R) {
   constexpr int M = NComp<EQ>::m;
-  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int gid = xcd_block_id() * kBlock + threadIdx.x;
   const int i = gid / M, q = gid - (gid / M) * M;
   if constexpr (EQ == EQ_EUL) {
     // all four component lanes of a cell stay active for the limiter's shuffles
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, do
                                                        const Real* __restrict__ egp, double* __restrict__ F,
                                                        Real* __restrict__ G) {
   constexpr int M = NComp<EQ>::m;
-  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int gid = xcd_block_id() * kBlock + threadIdx.x;
   const int e = gid >> 2, side = (gid >> 1) & 1, g = gid & 1;
   const bool valid = e < E;
   Real AH[M], AD[M], AT[M];
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(int N, int E, double dt,
                                                          const double* __restrict__ inv_area,
                                                          const double* __restrict__ F, const Real* __restrict__ G,
                                                          double* __restrict__ wout, Real* __restrict__ gout) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = xcd_block_id() * kBlock + threadIdx.x;
   if (i >= N) return;
   update_point<EQ, Real>(i, N, E, dt, wbar, nbr, cell_edge, nl, inv_area, F, G, wout, gout);
 }

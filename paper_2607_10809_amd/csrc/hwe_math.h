@@ -19,6 +19,17 @@
 namespace hwe {
 
 enum { EQ_ADV = 0, EQ_BUR = 1, EQ_EUL = 2 };
+
+// Workgroups of a launch are dispatched round-robin over the eight XCDs of an
+// MI355X, each with its own L2.  Renumber them so that XCD x runs a contiguous
+// range of logical blocks: cells and edges that are close in the Morton order
+// (and share neighbours, tables and reconstructions) then meet in one L2.
+__device__ __forceinline__ int xcd_block_id() {
+  const int nb = int(gridDim.x), b = int(blockIdx.x);
+  const int x = b & 7, k = b >> 3;
+  const int base = nb >> 3, rem = nb & 7;
+  return x * base + (x < rem ? x : rem) + k;
+}
 template <int EQ> struct NComp {
   static constexpr int m = EQ == EQ_EUL ? 4 : 1;
 };
