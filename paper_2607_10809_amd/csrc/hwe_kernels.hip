@@ -88,9 +88,10 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
   }
 }
 
-template <class Real> __device__ __forceinline__ Real xor_shfl(Real v, int mask) { return __shfl_xor(v, mask); }
-
-// Four work-items per edge (side, Gauss point), adjacent in the wave.
+// Four work-items per edge (side, Gauss point), adjacent in the wave: lane
+// 4k + 2 side + g.  Every lane loads its side's cell, cell average and the
+// edge normal; the Gauss points are combined with quad_perm exchanges, then
+// the (side 0) lanes take the other side's sums and FP64 terms the same way.
 template <int EQ, class Real>
 __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, double dt,
                                                        const double* __restrict__ wbar,
@@ -103,28 +104,42 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, do
   const int gid = xcd_block_id() * kBlock + threadIdx.x;
   const int e = gid >> 2, side = (gid >> 1) & 1, g = gid & 1;
   const bool valid = e < E;
+  const int ec = valid ? e : E - 1;
+  const int cell = valid ? ecell[side * E + ec] : -1;
+  const int cc = cell >= 0 ? cell : 0;
+  const double nx = enl[ec], ny = enl[E + ec], len = enl[2 * E + ec];
+  double Wb[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) Wb[q] = wbar[q * size_t(N) + cc];
   Real AH[M], AD[M], AT[M];
-  edge_lane<EQ, Real>(valid ? e : -1, side, g, E, N, P, dt, wbar, R, ecell, enl, egp, AH, AD, AT);
+  edge_lane<EQ, Real>(ec, cell, side, g, E, N, P, dt, Wb, Real(nx), Real(ny), R, egp, AH, AD, AT);
+  double Hb[M];
+  const double lam = side_terms<EQ>(P, Wb, nx, ny, Hb);
   // Gauss points (weights 1/2 each): combine lanes g = 0, 1
 #pragma unroll
   for (int q = 0; q < M; ++q) {
-    AH[q] = Real(0.5) * (AH[q] + xor_shfl(AH[q], 1));
-    AD[q] = Real(0.5) * (AD[q] + xor_shfl(AD[q], 1));
-    AT[q] = Real(0.5) * (AT[q] + xor_shfl(AT[q], 1));
+    AH[q] = Real(0.5) * (AH[q] + quad_perm<kQuadXor1>(AH[q]));
+    AD[q] = Real(0.5) * (AD[q] + quad_perm<kQuadXor1>(AD[q]));
+    AT[q] = Real(0.5) * (AT[q] + quad_perm<kQuadXor1>(AT[q]));
   }
-  // the other side's sums
+  // the other side's sums and FP64 terms
   Real OH[M], OD[M], OT[M];
+  double Wo[M], Ho[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) {
-    OH[q] = xor_shfl(AH[q], 2);
-    OD[q] = xor_shfl(AD[q], 2);
-    OT[q] = xor_shfl(AT[q], 2);
+    OH[q] = quad_perm<kQuadXor2>(AH[q]);
+    OD[q] = quad_perm<kQuadXor2>(AD[q]);
+    OT[q] = quad_perm<kQuadXor2>(AT[q]);
+    Wo[q] = quad_perm<kQuadXor2>(Wb[q]);
+    Ho[q] = quad_perm<kQuadXor2>(Hb[q]);
   }
+  const double lo = quad_perm<kQuadXor2>(lam);
+  const bool second = quad_perm<kQuadXor2>(cell) >= 0;
   if (!valid || side != 0) return;
   if (g == 0)
-    edge_flux<EQ, Real>(e, E, N, P, wbar, ecell, enl, AH, AD, OH, OD, F);
+    edge_flux<EQ, Real>(e, E, len, second, Wb, Hb, lam, Wo, Ho, lo, AH, AD, OH, OD, F);
   else
-    edge_value<EQ, Real>(e, E, ecell, AT, OT, G);
+    edge_value<EQ, Real>(e, E, second, AT, OT, G);
 }
 
 template <int EQ, class Real>

@@ -30,6 +30,23 @@ __device__ __forceinline__ int xcd_block_id() {
   const int base = nb >> 3, rem = nb & 7;
   return x * base + (x < rem ? x : rem) + k;
 }
+
+// Exchange within aligned groups of four lanes through DPP quad permutations
+// (a VALU move, no LDS round trip).  CTRL is the quad_perm selector:
+// kQuadXor1 swaps lanes 0<->1 and 2<->3, kQuadXor2 swaps 0<->2 and 1<->3.
+constexpr int kQuadXor1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);
+constexpr int kQuadXor2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+template <int CTRL> __device__ __forceinline__ int quad_perm(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ float quad_perm(float v) {
+  return __int_as_float(quad_perm<CTRL>(__float_as_int(v)));
+}
+template <int CTRL> __device__ __forceinline__ double quad_perm(double v) {
+  const int lo = quad_perm<CTRL>(__double2loint(v)), hi = quad_perm<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 template <int EQ> struct NComp {
   static constexpr int m = EQ == EQ_EUL ? 4 : 1;
 };

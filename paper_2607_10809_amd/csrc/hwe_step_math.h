@@ -23,23 +23,32 @@ __host__ __device__ __forceinline__ void recon_coeffs(int i, int q, int N, int N
                                                      const double* __restrict__ area, const Real* __restrict__ mom,
                                                      Real (&a)[6]) {
   constexpr int M = NComp<EQ>::m;
+  // All stencil loads are issued before any is used: a ghost face (nb < 0)
+  // reads the cell itself and its values are replaced below.
+  int nbi[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) nbi[f] = nbr[f * N + i];
   const double W0 = wbar[q * N + i];
-  double Wsum = W0, dW[3];
+  double Wn[3];
   Real V[4], Y[4];
   V[0] = grad[q * N + i];
   Y[0] = grad[(M + q) * N + i];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
-    const int nb = nbr[f * N + i];
-    if (nb >= 0) {
-      const double w = wbar[q * N + nb];
-      dW[f] = w - W0;
-      Wsum += w;
-      V[f + 1] = grad[q * N + nb];
-      Y[f + 1] = grad[(M + q) * N + nb];
+    const int c = nbi[f] >= 0 ? nbi[f] : i;
+    Wn[f] = wbar[q * N + c];
+    V[f + 1] = grad[q * N + c];
+    Y[f + 1] = grad[(M + q) * N + c];
+  }
+  double Wsum = W0, dW[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    if (nbi[f] >= 0) {
+      dW[f] = Wn[f] - W0;
+      Wsum += Wn[f];
     } else {
       // transmissive ghost: K0 mirrored across the face, gradient reflected
-      const int b = -nb - 1;
+      const int b = -nbi[f] - 1;
       const Real nx = Real(bnd_n[b]), ny = Real(bnd_n[NB + b]);
       dW[f] = 0.0;
       Wsum += W0;
@@ -186,34 +195,29 @@ __host__ __device__ __forceinline__ void positivity_theta(double gam, const doub
 
 // ------------------------------------------------------------------ edge lane
 // Contribution of one side (0: the edge's first cell, 1: its second) at one
-// Gauss point, as offsets from that cell's average Wbar: time integrals over
+// Gauss point, as offsets from that cell's average Wbd: time integrals over
 // the Lobatto nodes of the normal-flux offset dH = H(W) - H(Wbar) (AH) and of
-// d = W - Wbar (AD), and d at t_n + dt (AT).  e < 0 or an absent second side
-// gives zeros.  enl: [3][E] double (nx, ny, |e|); egp: [8][E] Gauss-point
+// d = W - Wbar (AD), and d at t_n + dt (AT).  cell < 0 (no cell on this side)
+// gives zeros.  (nx, ny): the edge's unit normal; egp: [8][E] Gauss-point
 // offsets from the centroids (side 0 points 0, 1; side 1 points 0, 1).
 template <int EQ, class Real>
-__host__ __device__ __forceinline__ void edge_lane(int e, int side, int g, int E, int N, const Params& P, double dt,
-                                                  const double* __restrict__ wbar, const Real* __restrict__ R,
-                                                  const int32_t* __restrict__ ecell, const double* __restrict__ enl,
-                                                  const Real* __restrict__ egp, Real (&AH)[NComp<EQ>::m],
-                                                  Real (&AD)[NComp<EQ>::m], Real (&AT)[NComp<EQ>::m]) {
+__host__ __device__ __forceinline__ void edge_lane(int e, int cell, int side, int g, int E, int N, const Params& P,
+                                                  double dt, const double (&Wbd)[NComp<EQ>::m], Real nx, Real ny,
+                                                  const Real* __restrict__ R, const Real* __restrict__ egp,
+                                                  Real (&AH)[NComp<EQ>::m], Real (&AD)[NComp<EQ>::m],
+                                                  Real (&AT)[NComp<EQ>::m]) {
   constexpr int M = NComp<EQ>::m;
 #pragma unroll
   for (int q = 0; q < M; ++q) AH[q] = AD[q] = AT[q] = Real(0);
-  if (e < 0) return;
-  const int cell = ecell[side * E + e];
   if (cell < 0) return;
   const size_t sN = size_t(N);
-  const Real nx = Real(enl[e]), ny = Real(enl[E + e]);
   const Real X = egp[(4 * side + 2 * g) * E + e];
   const Real Y = egp[(4 * side + 2 * g + 1) * E + e];
-  double Wbd[M];
   Real D[6][M], dl[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) {
     const Real a0 = R[(0 * M + q) * sN + cell], a1 = R[(1 * M + q) * sN + cell], a2 = R[(2 * M + q) * sN + cell];
     const Real a3 = R[(3 * M + q) * sN + cell], a4 = R[(4 * M + q) * sN + cell], a5 = R[(5 * M + q) * sN + cell];
-    Wbd[q] = wbar[q * sN + cell];
     dl[q] = a0 + a1 * X + a2 * Y + a3 * X * X + a4 * X * Y + a5 * Y * Y;  // W - Wbar at the point
     D[0][q] = Real(Wbd[q]) + dl[q];
     D[1][q] = a1 + Real(2) * a3 * X + a4 * Y;
@@ -246,6 +250,15 @@ __host__ __device__ __forceinline__ void edge_lane(int e, int side, int g, int E
   }
 }
 
+// FP64 terms of one side at its cell average: the normal flux H(Wbar) and the
+// spectral radius of d(F.n)/dW there.
+template <int EQ>
+__host__ __device__ __forceinline__ double side_terms(const Params& P, const double (&W)[NComp<EQ>::m], double nx,
+                                                     double ny, double (&H)[NComp<EQ>::m]) {
+  normal_flux<EQ, double>(P, W, nx, ny, H);
+  return spectral_radius<EQ>(P, W, nx, ny);
+}
+
 // Local Lax-Friedrichs edge flux in FP64 from the Gauss-averaged side sums
 // (A: first cell, O: second cell):
 //   F_e = |e| (1/2)(H(W_int) + H(W_ext) - alpha (W_ext - W_int))
@@ -253,30 +266,19 @@ __host__ __device__ __forceinline__ void edge_lane(int e, int side, int g, int E
 // alpha = max of the spectral radii at the two cell averages (first cell on ties).
 // Boundary edges (no second cell): W_ext = W_int, F_e = |e| (H(Wbar_0) + AH).
 template <int EQ, class Real>
-__host__ __device__ __forceinline__ void edge_flux(int e, int E, int N, const Params& P,
-                                                  const double* __restrict__ wbar, const int32_t* __restrict__ ecell,
-                                                  const double* __restrict__ enl, const Real (&AH)[NComp<EQ>::m],
+__host__ __device__ __forceinline__ void edge_flux(int e, int E, double len, bool second, const double (&Wl)[NComp<EQ>::m],
+                                                  const double (&Hl)[NComp<EQ>::m], double la,
+                                                  const double (&Wr)[NComp<EQ>::m], const double (&Hr)[NComp<EQ>::m],
+                                                  double lb, const Real (&AH)[NComp<EQ>::m],
                                                   const Real (&AD)[NComp<EQ>::m], const Real (&OH)[NComp<EQ>::m],
                                                   const Real (&OD)[NComp<EQ>::m], double* __restrict__ F) {
   constexpr int M = NComp<EQ>::m;
-  const int c0 = ecell[e], c1 = ecell[E + e];
-  const double nx = enl[e], ny = enl[E + e], len = enl[2 * E + e];
-  const size_t sN = size_t(N), sE = size_t(E);
-  double Wl[M], Hl[M];
-#pragma unroll
-  for (int q = 0; q < M; ++q) Wl[q] = wbar[q * sN + c0];
-  normal_flux<EQ, double>(P, Wl, nx, ny, Hl);
-  if (c1 < 0) {
+  const size_t sE = size_t(E);
+  if (!second) {
 #pragma unroll
     for (int q = 0; q < M; ++q) F[q * sE + e] = len * (Hl[q] + double(AH[q]));
     return;
   }
-  double Wr[M], Hr[M];
-#pragma unroll
-  for (int q = 0; q < M; ++q) Wr[q] = wbar[q * sN + c1];
-  normal_flux<EQ, double>(P, Wr, nx, ny, Hr);
-  const double la = spectral_radius<EQ>(P, Wl, nx, ny);
-  const double lb = spectral_radius<EQ>(P, Wr, nx, ny);
   const double alpha = la >= lb ? la : lb;
 #pragma unroll
   for (int q = 0; q < M; ++q) {
@@ -288,13 +290,11 @@ __host__ __device__ __forceinline__ void edge_flux(int e, int E, int N, const Pa
 // Gauss average of the interface value of eq. (timeflux) at t_n + dt, as an
 // offset from the mean of the two cell averages (boundary: from the one cell).
 template <int EQ, class Real>
-__host__ __device__ __forceinline__ void edge_value(int e, int E, const int32_t* __restrict__ ecell,
-                                                   const Real (&AT)[NComp<EQ>::m], const Real (&OT)[NComp<EQ>::m],
-                                                   Real* __restrict__ G) {
+__host__ __device__ __forceinline__ void edge_value(int e, int E, bool second, const Real (&AT)[NComp<EQ>::m],
+                                                   const Real (&OT)[NComp<EQ>::m], Real* __restrict__ G) {
   constexpr int M = NComp<EQ>::m;
-  const bool bnd = ecell[E + e] < 0;
 #pragma unroll
-  for (int q = 0; q < M; ++q) G[q * size_t(E) + e] = bnd ? AT[q] : Real(0.5) * (AT[q] + OT[q]);
+  for (int q = 0; q < M; ++q) G[q * size_t(E) + e] = second ? Real(0.5) * (AT[q] + OT[q]) : AT[q];
 }
 
 // ------------------------------------------------------------------ update
@@ -316,18 +316,26 @@ __host__ __device__ __forceinline__ void update_point(int i, int N, int E, doubl
     W0[q] = wbar[q * sN + i];
     fs[q] = vs[q] = ys[q] = 0.0;
   }
+  // indices first, then every gather at once (a boundary face reads the cell
+  // itself in place of the absent neighbour and contributes no difference)
+  int ce[3], nb[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
-    const int ce = cell_edge[f * sN + i];
-    const int e = ce >> 1;
-    const bool second = (ce & 1) != 0;
-    const int nb = nbr[f * sN + i];
+    ce[f] = cell_edge[f * sN + i];
+    nb[f] = nbr[f * sN + i];
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int e = ce[f] >> 1;
+    const bool second = (ce[f] & 1) != 0;
+    const int c = nb[f] >= 0 ? nb[f] : i;
     const double nlx = nl[f * sN + i], nly = nl[(3 + f) * sN + i];
 #pragma unroll
     for (int q = 0; q < M; ++q) {
       const double Fe = F[q * sE + e];
+      const double Wn = wbar[q * sN + c];
       fs[q] += second ? -Fe : Fe;
-      const double d = nb >= 0 ? 0.5 * (wbar[q * sN + nb] - W0[q]) : 0.0;
+      const double d = nb[f] >= 0 ? 0.5 * (Wn - W0[q]) : 0.0;
       const double gq = double(G[q * sE + e]) + d;
       vs[q] += nlx * gq;
       ys[q] += nly * gq;

@@ -204,18 +204,27 @@ def test_riemann_prefix_and_late_one_step_small_mesh():
     assert err <= FP64_SMOOTH
 
 
+# The limited C4 runs use CFL 0.2 with the time step recomputed every 50 steps.
+# At CFL 0.3 the run is marginal: one FP64 trajectory lost positivity in one
+# cell at t ~ 0.046, and the oracle, stepped from the same state, gives the same
+# negative pressure (agreement 7e-14), so this is the method (the scaling limiter
+# bounds the point values, not the updated averages), not the kernels.
+C4_LIMITED_CFL = 0.2
+
+
 def test_c4_riemann_limited_late_state_sampled_cells():
     """Without the scaling limiter this problem loses positivity within ~300 steps
-    at 980,000 triangles; with it, one step from step 2000 matches the oracle."""
+    at 980,000 triangles; with it, one step from the state at t = 0.1 matches
+    the oracle."""
     import torch
     wl = riemann_workload()
     om = OracleMesh.from_workload(wl, positivity=1)
-    dt = om.max_dt(wl.state0, wl.cfl)
     for prec, tol in (("fp64", FP64_SMOOTH), ("mixed", MIXED)):
         mesh = _mesh(wl, prec, positivity=True)
         w, g = mesh.to_device(wl.state0)
-        w, g = mesh.run(w, g, dt, 2000)
+        w, g, n = mesh.run_to(w, g, 0.1, C4_LIMITED_CFL, every=50)
         assert mesh.check_state(w) == 0
+        dt = mesh.max_dt(w, C4_LIMITED_CFL)
         s_k = mesh.to_host(w, g)
         w1, g1 = mesh.step(w, g, dt)
         torch.cuda.synchronize()
@@ -224,7 +233,7 @@ def test_c4_riemann_limited_late_state_sampled_cells():
         ref = om.step_cells(s_k, cells, dt)
         nb = 1 if prec == "mixed" else 3
         err = float((np.abs(s_k1[:nb, :, cells] - ref[:nb]).max(axis=-1) / np.abs(s_k1[:nb]).max(axis=-1)).max())
-        _say(f"C4 limited {prec} one step from step 2000, sampled rel_max", err)
+        _say(f"C4 limited {prec} one step from t = 0.1 ({n} steps), sampled rel_max", err)
         assert err <= tol
 
 
@@ -249,14 +258,14 @@ def test_riemann_limiter_active_one_step_parity():
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_c4_riemann_limited_run_to_T(prec):
     """The 980,000-triangle Riemann problem to T = 0.3 with the limiter and the
-    CFL time step (0.3) recomputed from the current state every 50 steps: the
-    state stays admissible.  (With the time step frozen at its initial value the
-    CFL number drifts to ~0.4 and the run breaks down at t ~ 0.04.)"""
+    CFL time step recomputed from the current state every 50 steps: the state
+    stays admissible.  (With the time step frozen at its initial value the CFL
+    number drifts to ~0.4 and the run breaks down at t ~ 0.04.)"""
     import torch
     wl = riemann_workload()
     mesh = _mesh(wl, prec, positivity=True)
     w, g = mesh.to_device(wl.state0)
-    w, g, n = mesh.run_to(w, g, wl.T, wl.cfl, every=50)
+    w, g, n = mesh.run_to(w, g, wl.T, C4_LIMITED_CFL, every=50)
     flags = mesh.check_state(w)
     torch.cuda.synchronize()
     s = mesh.to_host(w, g)
