@@ -38,8 +38,8 @@ __global__ __launch_bounds__(kBlock) void adj_cell_kernel(
     const double* __restrict__ lw, const Real* __restrict__ lg, const Real* __restrict__ R,
     const int32_t* __restrict__ nbr, const int32_t* __restrict__ cell_edge, const int32_t* __restrict__ ecell,
     const double* __restrict__ enl, const Real* __restrict__ egp, const double* __restrict__ inv_area,
-    const Real* __restrict__ nl, const double* __restrict__ bnd_n, const Real* __restrict__ p1,
-    const Real* __restrict__ p2, const double* __restrict__ area, const Real* __restrict__ mom,
+    const Real* __restrict__ nl, const double* __restrict__ bnd_n, const Real* __restrict__ tbl,
+    const double* __restrict__ area,
     double* __restrict__ slots, double* __restrict__ sface) {
   constexpr int M = NComp<EQ>::m;
   const int gid = xcd_block_id() * kBlock + threadIdx.x;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void adj_cell_kernel(
     double lwq = lWf[0];
     if constexpr (M == 4) lwq = q == 0 ? lWf[0] : (q == 1 ? lWf[1] : (q == 2 ? lWf[2] : lWf[3]));
     double slot[4][3];
-    recon_rev<EQ, Real>(i, q, N, NB, P, wbar, grad, nbr, bnd_n, p1, p2, area, mom, laq, slot);
+    recon_rev<EQ, Real>(i, q, N, NB, P, wbar, grad, nbr, bnd_n, tbl + tbl_col(i), area, laq, slot);
     slot[0][0] += lwq;
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl)
@@ -234,15 +234,15 @@ unsigned grid_for(int64_t items) { return unsigned((items + kBlock - 1) / kBlock
 
 template <int EQ, class Real>
 hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, const Real* grad, const double* lw,
-                        const Real* lg, double* lw_out, Real* lg_out, double dt, hipStream_t st, const Real* p1,
-                        const Real* p2, const Real* nl, const Real* egp, const Real* mom) {
+                        const Real* lg, double* lw_out, Real* lg_out, double dt, hipStream_t st, const Real* tbl,
+                        const Real* nl, const Real* egp) {
   const HostMesh& h = M->h;
   const DevMesh& d = M->d;
   const int N = int(h.N), E = int(h.E), NB = int(h.NB);
   const Real* R = static_cast<const Real*>(d.R);
   hipLaunchKernelGGL((adj_cell_kernel<EQ, Real>), dim3(grid_for(4 * int64_t(N))), dim3(kBlock), 0, st, N, E, NB, P,
-                     dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.ecell, d.enl, egp, d.inv_area, nl, d.bnd_n, p1,
-                     p2, d.area, mom, d.slots, d.sface);
+                     dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.ecell, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl,
+                     d.area, d.slots, d.sface);
   hipLaunchKernelGGL((adj_gather_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg,
                      d.nbr, d.nbr_back, d.cell_edge, d.ecell, d.enl, d.inv_area, nl, d.slots, d.sface, lw_out,
                      lg_out);
@@ -266,11 +266,11 @@ hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_
     auto o = static_cast<double*>(lg_out);
     switch (M->opts.eq) {
       case HWE_ADVECTION:
-        return adjoint_impl<EQ_ADV, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+        return adjoint_impl<EQ_ADV, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tbl, d.nl, d.egp);
       case HWE_BURGERS:
-        return adjoint_impl<EQ_BUR, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+        return adjoint_impl<EQ_BUR, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tbl, d.nl, d.egp);
       default:
-        return adjoint_impl<EQ_EUL, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+        return adjoint_impl<EQ_EUL, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tbl, d.nl, d.egp);
     }
   }
   auto g = static_cast<const float*>(grad_n);
@@ -278,14 +278,11 @@ hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_
   auto o = static_cast<float*>(lg_out);
   switch (M->opts.eq) {
     case HWE_ADVECTION:
-      return adjoint_impl<EQ_ADV, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1f, d.p2f, d.nlf, d.egpf,
-                                         d.momf);
+      return adjoint_impl<EQ_ADV, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tblf, d.nlf, d.egpf);
     case HWE_BURGERS:
-      return adjoint_impl<EQ_BUR, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1f, d.p2f, d.nlf, d.egpf,
-                                         d.momf);
+      return adjoint_impl<EQ_BUR, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tblf, d.nlf, d.egpf);
     default:
-      return adjoint_impl<EQ_EUL, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.p1f, d.p2f, d.nlf, d.egpf,
-                                         d.momf);
+      return adjoint_impl<EQ_EUL, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tblf, d.nlf, d.egpf);
   }
 }
 

@@ -502,8 +502,7 @@ template <int EQ, class Real>
 __host__ __device__ __forceinline__ void recon_rev(int i, int q, int N, int NB, const Params& P,
                                                   const double* __restrict__ wbar, const Real* __restrict__ grad,
                                                   const int32_t* __restrict__ nbr, const double* __restrict__ bnd_n,
-                                                  const Real* __restrict__ p1, const Real* __restrict__ p2,
-                                                  const double* __restrict__ area, const Real* __restrict__ mom,
+                                                  const Real* __restrict__ tb, const double* __restrict__ area,
                                                   const Real (&la)[6], double (&slot)[4][3]) {
   constexpr int M = NComp<EQ>::m;
   const size_t sN = size_t(N);
@@ -515,16 +514,22 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int q, int N, int NB, 
   V[0] = grad[q * sN + i];
   Y[0] = grad[(M + q) * sN + i];
   Real gnx[3], gny[3];
+  double Wn[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) nb[f] = nbr[f * sN + i];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {  // every gather before any use; a ghost face reads the cell itself
+    const int c = nb[f] >= 0 ? nb[f] : i;
+    Wn[f] = wbar[q * sN + c];
+    V[f + 1] = grad[q * sN + c];
+    Y[f + 1] = grad[(M + q) * sN + c];
+  }
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
-    nb[f] = nbr[f * sN + i];
     gnx[f] = gny[f] = Real(0);
     if (nb[f] >= 0) {
-      const double w = wbar[q * sN + nb[f]];
-      dW[f] = w - W0;
-      Wsum += w;
-      V[f + 1] = grad[q * sN + nb[f]];
-      Y[f + 1] = grad[(M + q) * sN + nb[f]];
+      dW[f] = Wn[f] - W0;
+      Wsum += Wn[f];
     } else {
       const int b = -nb[f] - 1;
       gnx[f] = Real(bnd_n[b]);
@@ -540,18 +545,18 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int q, int N, int NB, 
   Real c[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
-    const Real* t = p1 + size_t(j * 11) * sN + i;
-    Real s = t[0] * d0 + t[sN] * d1 + t[2 * sN] * d2;
+    const Real* t = tb + (kTblP1 + j * 11) * kTile;
+    Real s = t[0] * d0 + t[kTile] * d1 + t[2 * kTile] * d2;
 #pragma unroll
-    for (int l = 0; l < 4; ++l) s += t[(3 + l) * sN] * V[l] + t[(7 + l) * sN] * Y[l];
+    for (int l = 0; l < 4; ++l) s += t[(3 + l) * kTile] * V[l] + t[(7 + l) * kTile] * Y[l];
     c[j] = s;
   }
   Real bl[3], cl[3], pdx[3], pdy[3], piv[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
-    pdx[f] = p2[(3 * f) * sN + i];
-    pdy[f] = p2[(3 * f + 1) * sN + i];
-    piv[f] = p2[(3 * f + 2) * sN + i];
+    pdx[f] = tb[(kTblP2 + 3 * f) * kTile];
+    pdy[f] = tb[(kTblP2 + 3 * f + 1) * kTile];
+    piv[f] = tb[(kTblP2 + 3 * f + 2) * kTile];
     const Real t = (Real(dW[f]) - pdx[f] * V[f + 1] - pdy[f] * Y[f + 1]) * piv[f];
     bl[f] = V[f + 1] + pdx[f] * t;
     cl[f] = Y[f + 1] + pdy[f] * t;
@@ -587,7 +592,7 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int q, int N, int NB, 
 #pragma unroll
   for (int f = 0; f < 3; ++f) kl[f] = Real(w[f + 1] - w[0] * P.lw[f + 1] / g1);
   // ---- reverse
-  const Real mxx = mom[i], mxy = mom[sN + i], myy = mom[2 * sN + i];
+  const Real mxx = tb[kTblMom * kTile], mxy = tb[(kTblMom + 1) * kTile], myy = tb[(kTblMom + 2) * kTile];
   const Real lR1 = la[1], lR2 = la[2];
   const Real lR3 = la[3] - mxx * la[0], lR4 = la[4] - mxy * la[0], lR5 = la[5] - myy * la[0];
   Real lc[5];
@@ -660,14 +665,14 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int q, int N, int NB, 
   // Step 1 reverse
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
-    const Real* t = p1 + size_t(j * 11) * sN + i;
+    const Real* t = tb + (kTblP1 + j * 11) * kTile;
     ldW[0] += double(t[0] * lc[j]);
-    ldW[1] += double(t[sN] * lc[j]);
-    ldW[2] += double(t[2 * sN] * lc[j]);
+    ldW[1] += double(t[kTile] * lc[j]);
+    ldW[2] += double(t[2 * kTile] * lc[j]);
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
-      lV[l] += t[(3 + l) * sN] * lc[j];
-      lY[l] += t[(7 + l) * sN] * lc[j];
+      lV[l] += t[(3 + l) * kTile] * lc[j];
+      lY[l] += t[(7 + l) * kTile] * lc[j];
     }
   }
   // stencil inputs -> slots

@@ -54,20 +54,16 @@ struct DevMesh {
   // FP64 geometry / tables
   double* bnd_n = nullptr;
   double* area = nullptr;
-  double* mom = nullptr;
-  double* p1 = nullptr;
-  double* p2 = nullptr;
+  double* tbl = nullptr;    // tiled reconstruction tables (Step-1 map, Step-2 data, moments)
   double* nl = nullptr;
   double* inv_area = nullptr;
   double* gpc = nullptr;    // [12][N] (limiter only)
   double* enl = nullptr;    // [3][E] edge normal and length (FP64 in both precisions)
   double* egp = nullptr;    // [8][E] Gauss-point offsets (FP64 path)
   // FP32 copies for the mixed path
-  float* p1f = nullptr;
-  float* p2f = nullptr;
+  float* tblf = nullptr;
   float* nlf = nullptr;
   float* egpf = nullptr;
-  float* momf = nullptr;
   // scratch: reconstruction coefficients [6][m][N] (double or float by
   // precision), edge flux [m][E] (double) and interface-value offset [m][E]
   // (double or float)

@@ -36,26 +36,45 @@ namespace {
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------- kernels
-// One work-item per (cell, component); the M lanes of a cell are adjacent, so
-// their table loads hit the same addresses.
+// One work-item per (cell, component); the M lanes of a cell are adjacent.
+// For Euler a block covers exactly one table tile (64 cells x 4 components):
+// the tile's tables are one contiguous block, staged into LDS with 16-byte
+// loads that are all in flight together, while the stencil gathers proceed.
 template <int EQ, class Real>
 __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, const double* __restrict__ wbar,
                                                         const Real* __restrict__ grad,
                                                         const int32_t* __restrict__ nbr,
                                                         const double* __restrict__ bnd_n,
-                                                        const Real* __restrict__ p1, const Real* __restrict__ p2,
+                                                        const Real* __restrict__ tbl,
                                                         const double* __restrict__ area,
-                                                        const Real* __restrict__ mom,
                                                         const double* __restrict__ gpc, Real* __restrict__ R) {
   constexpr int M = NComp<EQ>::m;
-  const int gid = xcd_block_id() * kBlock + threadIdx.x;
+  const int blk = xcd_block_id();
+  const int gid = blk * kBlock + threadIdx.x;
   const int i = gid / M, q = gid - (gid / M) * M;
   if constexpr (EQ == EQ_EUL) {
+    static_assert(kBlock == kTile * 4, "one Euler block per table tile");
+    constexpr int kChunks = kTblRows * kTile * int(sizeof(Real)) / 16;
+    constexpr int kFull = kChunks / kBlock, kRest = kChunks - kFull * kBlock;
+    __shared__ uint4 stage[(kFull + 1) * kBlock];  // the last row is partly padding
+    const uint4* src = reinterpret_cast<const uint4*>(tbl + size_t(blk) * (kTblRows * kTile));
+    const int t = threadIdx.x;
+    uint4 buf[kFull];
+#pragma unroll
+    for (int r = 0; r < kFull; ++r) buf[r] = src[t + r * kBlock];
+    // lanes past the tile's end reload an earlier chunk (in bounds) into the padding
+    const uint4 rest = src[t + kFull * kBlock - (t < kRest ? 0 : kBlock)];
     // all four component lanes of a cell stay active for the limiter's shuffles
     const bool valid = i < N;
     const int ic = valid ? i : N - 1;
+    const Stencil<Real> S = gather_stencil<EQ, Real>(ic, q, N, wbar, grad, nbr);
+#pragma unroll
+    for (int r = 0; r < kFull; ++r) stage[t + r * kBlock] = buf[r];
+    stage[t + kFull * kBlock] = rest;
+    __syncthreads();
+    const Real* tb = reinterpret_cast<const Real*>(stage) + (i % kTile);
     Real a[6];
-    recon_coeffs<EQ, Real>(ic, q, N, NB, P, wbar, grad, nbr, bnd_n, p1, p2, area, mom, a);
+    recon_from_stencil<EQ, Real>(ic, NB, P, S, bnd_n, tb, area, a);
     if (P.positivity) {
       const int lane0 = (threadIdx.x & 63) & ~3;
       Real all[4][6];
@@ -83,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
   } else {
     if (i >= N) return;
     Real a[6];
-    recon_coeffs<EQ, Real>(i, q, N, NB, P, wbar, grad, nbr, bnd_n, p1, p2, area, mom, a);
+    recon_coeffs<EQ, Real>(i, q, N, NB, P, wbar, grad, nbr, bnd_n, tbl + tbl_col(i), area, a);
     store_coeffs<EQ, Real>(i, q, N, a, R);
   }
 }
@@ -282,8 +301,8 @@ unsigned grid_for(int64_t items) { return unsigned((items + kBlock - 1) / kBlock
 
 template <int EQ, class Real>
 hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, const Real* grad_in, double* wbar_out,
-                     Real* grad_out, double dt, hipStream_t st, const Real* p1, const Real* p2, const Real* nl,
-                     const Real* egp, const Real* mom) {
+                     Real* grad_out, double dt, hipStream_t st, const Real* tbl, const Real* nl,
+                     const Real* egp) {
   const HostMesh& h = M->h;
   const DevMesh& d = M->d;
   const int N = int(h.N), E = int(h.E), NB = int(h.NB);
@@ -296,7 +315,7 @@ hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, cons
   if (d.prof_n < d.prof_cap) ev = reinterpret_cast<hipEvent_t*>(&M->d.prof_ev[4 * size_t(d.prof_n)]);
   if (ev) hipEventRecord(ev[0], st);
   hipLaunchKernelGGL((recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * Mc)), dim3(kBlock), 0, st, N, NB, P, wbar_in, grad_in,
-                     d.nbr, d.bnd_n, p1, p2, d.area, mom, d.gpc, R);
+                     d.nbr, d.bnd_n, tbl, d.area, d.gpc, R);
   if (ev) hipEventRecord(ev[1], st);
   hipLaunchKernelGGL((edge_kernel<EQ, Real>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, P, dt,
                      wbar_in, R, d.ecell, d.enl, egp, F, G);
@@ -314,13 +333,13 @@ hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, cons
 
 template <int EQ, class Real>
 hwe_status recon_impl(hwe_mesh_s* M, const Params& P, const double* wbar, const Real* grad, Real* R, hipStream_t st,
-                      const Real* p1, const Real* p2, const Real* mom) {
+                      const Real* tbl) {
   const HostMesh& h = M->h;
   const DevMesh& d = M->d;
   const int N = int(h.N), NB = int(h.NB);
   constexpr int Mc = NComp<EQ>::m;
   hipLaunchKernelGGL((recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * Mc)), dim3(kBlock), 0, st, N, NB, P, wbar, grad, d.nbr,
-                     d.bnd_n, p1, p2, d.area, mom, d.gpc, R);
+                     d.bnd_n, tbl, d.area, d.gpc, R);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return hip_fail(err, "kernel launch");
   return HWE_OK;
@@ -338,6 +357,21 @@ Params params_of(const hwe_opts& o) {
   P.eps = o.eps;
   P.linear = o.linear_weights ? 1 : 0;
   return P;
+}
+
+// Host tables [k][N] -> tiled device layout (see kTile), padded to whole tiles
+// with zeros.
+static std::vector<double> tiled_tables(const HostMesh& h) {
+  const int N = int(h.N);
+  const int tiles = (N + kTile - 1) / kTile;
+  std::vector<double> t(size_t(tiles) * kTblRows * kTile, 0.0);
+  for (int i = 0; i < N; ++i) {
+    double* col = t.data() + tbl_col(i);
+    for (int k = 0; k < 55; ++k) col[(kTblP1 + k) * kTile] = h.p1[size_t(k) * N + i];
+    for (int k = 0; k < 9; ++k) col[(kTblP2 + k) * kTile] = h.p2[size_t(k) * N + i];
+    for (int k = 0; k < 3; ++k) col[(kTblMom + k) * kTile] = h.mom[size_t(k) * N + i];
+  }
+  return t;
 }
 
 hwe_status upload_mesh(hwe_mesh_s* M) {
@@ -362,16 +396,13 @@ hwe_status upload_mesh(hwe_mesh_s* M) {
   if (M->opts.positivity) HWE_TRY(dev_copy(&d.gpc, h.gpc.data(), h.gpc.size()));
   const size_t N = size_t(h.N), E = size_t(h.E), m = size_t(h.m);
   HWE_TRY(dev_copy(&d.enl, h.egeo.data(), 3 * E));
+  const std::vector<double> tiled = tiled_tables(h);
   if (M->opts.prec == HWE_FP64) {
-    HWE_TRY(dev_copy(&d.mom, h.mom.data(), h.mom.size()));
-    HWE_TRY(dev_copy(&d.p1, h.p1.data(), h.p1.size()));
-    HWE_TRY(dev_copy(&d.p2, h.p2.data(), h.p2.size()));
+    HWE_TRY(dev_copy(&d.tbl, tiled.data(), tiled.size()));
     HWE_TRY(dev_copy(&d.nl, h.nl.data(), h.nl.size()));
     HWE_TRY(dev_copy(&d.egp, h.egeo.data() + 3 * E, 8 * E));
   } else {
-    HWE_TRY(dev_copy_f32(&d.momf, h.mom));
-    HWE_TRY(dev_copy_f32(&d.p1f, h.p1));
-    HWE_TRY(dev_copy_f32(&d.p2f, h.p2));
+    HWE_TRY(dev_copy_f32(&d.tblf, tiled));
     HWE_TRY(dev_copy_f32(&d.nlf, h.nl));
     HWE_TRY(dev_copy_f32(&d.egpf, std::vector<double>(h.egeo.begin() + 3 * E, h.egeo.end())));
   }
@@ -392,8 +423,8 @@ void free_device(hwe_mesh_s* M) {
   if (d.device < 0) return;
   hipSetDevice(d.device);
   hipDeviceSynchronize();
-  void* ptrs[] = {d.nbr, d.cell_edge, d.ecell, d.nbr_back, d.bnd_n, d.area, d.mom, d.p1, d.p2, d.nl, d.inv_area,
-                  d.gpc, d.enl, d.egp, d.p1f, d.p2f, d.nlf, d.egpf, d.momf, d.R, d.F, d.G, d.slots, d.sface,
+  void* ptrs[] = {d.nbr, d.cell_edge, d.ecell, d.nbr_back, d.bnd_n, d.area, d.tbl, d.nl, d.inv_area,
+                  d.gpc, d.enl, d.egp, d.tblf, d.nlf, d.egpf, d.R, d.F, d.G, d.slots, d.sface,
                   d.red, d.redi};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -411,22 +442,22 @@ hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in
     auto go = static_cast<double*>(grad_out);
     switch (M->opts.eq) {
       case HWE_ADVECTION:
-        return step_impl<EQ_ADV, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+        return step_impl<EQ_ADV, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp);
       case HWE_BURGERS:
-        return step_impl<EQ_BUR, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+        return step_impl<EQ_BUR, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp);
       default:
-        return step_impl<EQ_EUL, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1, d.p2, d.nl, d.egp, d.mom);
+        return step_impl<EQ_EUL, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp);
     }
   }
   auto gi = static_cast<const float*>(grad_in);
   auto go = static_cast<float*>(grad_out);
   switch (M->opts.eq) {
     case HWE_ADVECTION:
-      return step_impl<EQ_ADV, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1f, d.p2f, d.nlf, d.egpf, d.momf);
+      return step_impl<EQ_ADV, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf);
     case HWE_BURGERS:
-      return step_impl<EQ_BUR, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1f, d.p2f, d.nlf, d.egpf, d.momf);
+      return step_impl<EQ_BUR, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf);
     default:
-      return step_impl<EQ_EUL, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.p1f, d.p2f, d.nlf, d.egpf, d.momf);
+      return step_impl<EQ_EUL, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf);
   }
 }
 
@@ -438,17 +469,17 @@ hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, voi
     auto g = static_cast<const double*>(grad);
     auto R = static_cast<double*>(R_out);
     switch (M->opts.eq) {
-      case HWE_ADVECTION: return recon_impl<EQ_ADV, double>(M, P, wbar, g, R, st, d.p1, d.p2, d.mom);
-      case HWE_BURGERS: return recon_impl<EQ_BUR, double>(M, P, wbar, g, R, st, d.p1, d.p2, d.mom);
-      default: return recon_impl<EQ_EUL, double>(M, P, wbar, g, R, st, d.p1, d.p2, d.mom);
+      case HWE_ADVECTION: return recon_impl<EQ_ADV, double>(M, P, wbar, g, R, st, d.tbl);
+      case HWE_BURGERS: return recon_impl<EQ_BUR, double>(M, P, wbar, g, R, st, d.tbl);
+      default: return recon_impl<EQ_EUL, double>(M, P, wbar, g, R, st, d.tbl);
     }
   }
   auto g = static_cast<const float*>(grad);
   auto R = static_cast<float*>(R_out);
   switch (M->opts.eq) {
-    case HWE_ADVECTION: return recon_impl<EQ_ADV, float>(M, P, wbar, g, R, st, d.p1f, d.p2f, d.momf);
-    case HWE_BURGERS: return recon_impl<EQ_BUR, float>(M, P, wbar, g, R, st, d.p1f, d.p2f, d.momf);
-    default: return recon_impl<EQ_EUL, float>(M, P, wbar, g, R, st, d.p1f, d.p2f, d.momf);
+    case HWE_ADVECTION: return recon_impl<EQ_ADV, float>(M, P, wbar, g, R, st, d.tblf);
+    case HWE_BURGERS: return recon_impl<EQ_BUR, float>(M, P, wbar, g, R, st, d.tblf);
+    default: return recon_impl<EQ_EUL, float>(M, P, wbar, g, R, st, d.tblf);
   }
 }
 

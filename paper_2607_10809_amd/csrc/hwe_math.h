@@ -47,6 +47,18 @@ template <int CTRL> __device__ __forceinline__ double quad_perm(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Per-cell reconstruction tables, tiled: cells are grouped in tiles of kTile
+// consecutive cells; a tile stores kTblRows rows of kTile values (row-major),
+// so the tables of one tile are one contiguous block.  Rows: the 5 x 11 Step-1
+// map (row-major), the Step-2 data (dx, dy, 1/(1 + d.d) per face) and the
+// central second moments (Mxx, Mxy, Myy).  The table of cell i starts at
+// (i / kTile) * kTblRows * kTile + i % kTile.
+constexpr int kTile = 64;
+constexpr int kTblP1 = 0, kTblP2 = 55, kTblMom = 64, kTblRows = 67;
+__host__ __device__ __forceinline__ size_t tbl_col(int i) {
+  return size_t(i / kTile) * (kTblRows * kTile) + size_t(i % kTile);
+}
+
 template <int EQ> struct NComp {
   static constexpr int m = EQ == EQ_EUL ? 4 : 1;
 };

@@ -13,42 +13,61 @@
 namespace hwe {
 
 // ------------------------------------------------------------------ Steps 1-6
-// Reconstruction of component q of cell i (Sec. 2.2).
-// Writes the six coefficients a0..a5 of R - Wbar (monomials about the centroid).
-template <int EQ, class Real>
-__host__ __device__ __forceinline__ void recon_coeffs(int i, int q, int N, int NB, const Params& P,
-                                                     const double* __restrict__ wbar, const Real* __restrict__ grad,
-                                                     const int32_t* __restrict__ nbr, const double* __restrict__ bnd_n,
-                                                     const Real* __restrict__ p1, const Real* __restrict__ p2,
-                                                     const double* __restrict__ area, const Real* __restrict__ mom,
-                                                     Real (&a)[6]) {
-  constexpr int M = NComp<EQ>::m;
-  // All stencil loads are issued before any is used: a ghost face (nb < 0)
-  // reads the cell itself and its values are replaced below.
+// The stencil of component q of cell i: its own average and derivative
+// averages and its three face neighbours'.  All loads are issued before any
+// is used: a ghost face (nbi < 0) reads the cell itself; recon_from_stencil
+// replaces those values.
+template <class Real> struct Stencil {
   int nbi[3];
-#pragma unroll
-  for (int f = 0; f < 3; ++f) nbi[f] = nbr[f * N + i];
-  const double W0 = wbar[q * N + i];
-  double Wn[3];
+  double W0, Wn[3];
   Real V[4], Y[4];
-  V[0] = grad[q * N + i];
-  Y[0] = grad[(M + q) * N + i];
+};
+template <int EQ, class Real>
+__host__ __device__ __forceinline__ Stencil<Real> gather_stencil(int i, int q, int N,
+                                                                const double* __restrict__ wbar,
+                                                                const Real* __restrict__ grad,
+                                                                const int32_t* __restrict__ nbr) {
+  constexpr int M = NComp<EQ>::m;
+  Stencil<Real> S;
+#pragma unroll
+  for (int f = 0; f < 3; ++f) S.nbi[f] = nbr[f * N + i];
+  S.W0 = wbar[q * N + i];
+  S.V[0] = grad[q * N + i];
+  S.Y[0] = grad[(M + q) * N + i];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
-    const int c = nbi[f] >= 0 ? nbi[f] : i;
-    Wn[f] = wbar[q * N + c];
-    V[f + 1] = grad[q * N + c];
-    Y[f + 1] = grad[(M + q) * N + c];
+    const int c = S.nbi[f] >= 0 ? S.nbi[f] : i;
+    S.Wn[f] = wbar[q * N + c];
+    S.V[f + 1] = grad[q * N + c];
+    S.Y[f + 1] = grad[(M + q) * N + c];
+  }
+  return S;
+}
+
+// Reconstruction of component q of cell i (Sec. 2.2) from its stencil.
+// Writes the six coefficients a0..a5 of R - Wbar (monomials about the centroid).
+// tb: the cell's column of the tiled geometry table (row k at tb[k * kTile]).
+template <int EQ, class Real>
+__host__ __device__ __forceinline__ void recon_from_stencil(int i, int NB, const Params& P, const Stencil<Real>& S,
+                                                           const double* __restrict__ bnd_n,
+                                                           const Real* __restrict__ tb,
+                                                           const double* __restrict__ area, Real (&a)[6]) {
+  const double W0 = S.W0;
+  Real V[4], Y[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    V[l] = S.V[l];
+    Y[l] = S.Y[l];
   }
   double Wsum = W0, dW[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
-    if (nbi[f] >= 0) {
-      dW[f] = Wn[f] - W0;
-      Wsum += Wn[f];
+    if (S.nbi[f] >= 0) {
+      dW[f] = S.Wn[f] - W0;
+      Wsum += S.Wn[f];
     } else {
       // transmissive ghost: K0 mirrored across the face, gradient reflected
-      const int b = -nbi[f] - 1;
+      const int b = -S.nbi[f] - 1;
       const Real nx = Real(bnd_n[b]), ny = Real(bnd_n[NB + b]);
       dW[f] = 0.0;
       Wsum += W0;
@@ -59,21 +78,21 @@ __host__ __device__ __forceinline__ void recon_coeffs(int i, int q, int N, int N
   }
   // Step 1: c = P1 (dW1..3, V0..3, Y0..3); W differences formed in FP64
   const Real d0 = Real(dW[0]), d1 = Real(dW[1]), d2 = Real(dW[2]);
-  const size_t sN = size_t(N);
   Real c[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
-    const Real* t = p1 + size_t(j * 11) * sN + i;
-    Real s = t[0] * d0 + t[sN] * d1 + t[2 * sN] * d2;
+    const Real* t = tb + (kTblP1 + j * 11) * kTile;
+    Real s = t[0] * d0 + t[kTile] * d1 + t[2 * kTile] * d2;
 #pragma unroll
-    for (int l = 0; l < 4; ++l) s += t[(3 + l) * sN] * V[l] + t[(7 + l) * sN] * Y[l];
+    for (int l = 0; l < 4; ++l) s += t[(3 + l) * kTile] * V[l] + t[(7 + l) * kTile] * Y[l];
     c[j] = s;
   }
   // Step 2: linear candidates on {K0, K_l}
   Real bl[3], cl[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
-    const Real dx = p2[(3 * f) * sN + i], dy = p2[(3 * f + 1) * sN + i], iv = p2[(3 * f + 2) * sN + i];
+    const Real* t2 = tb + (kTblP2 + 3 * f) * kTile;
+    const Real dx = t2[0], dy = t2[kTile], iv = t2[2 * kTile];
     const Real t = (Real(dW[f]) - dx * V[f + 1] - dy * Y[f + 1]) * iv;
     bl[f] = V[f + 1] + dx * t;
     cl[f] = Y[f + 1] + dy * t;
@@ -120,12 +139,24 @@ __host__ __device__ __forceinline__ void recon_coeffs(int i, int q, int N, int N
     R2 += kl * cl[f];
   }
   const Real R3 = k1 * c[2], R4 = k1 * c[3], R5 = k1 * c[4];
-  a[0] = -(R3 * mom[i] + R4 * mom[sN + i] + R5 * mom[2 * sN + i]);
+  const Real* mo = tb + kTblMom * kTile;
+  a[0] = -(R3 * mo[0] + R4 * mo[kTile] + R5 * mo[2 * kTile]);
   a[1] = R1;
   a[2] = R2;
   a[3] = R3;
   a[4] = R4;
   a[5] = R5;
+}
+
+// Gather and reconstruct in one call (tb as in recon_from_stencil).
+template <int EQ, class Real>
+__host__ __device__ __forceinline__ void recon_coeffs(int i, int q, int N, int NB, const Params& P,
+                                                     const double* __restrict__ wbar, const Real* __restrict__ grad,
+                                                     const int32_t* __restrict__ nbr, const double* __restrict__ bnd_n,
+                                                     const Real* __restrict__ tb, const double* __restrict__ area,
+                                                     Real (&a)[6]) {
+  const Stencil<Real> S = gather_stencil<EQ, Real>(i, q, N, wbar, grad, nbr);
+  recon_from_stencil<EQ, Real>(i, NB, P, S, bnd_n, tb, area, a);
 }
 
 template <int EQ, class Real>
