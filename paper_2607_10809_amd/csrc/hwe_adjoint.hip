@@ -33,10 +33,10 @@ constexpr int kBlock = 256;
 template <class T> __device__ __forceinline__ T xshfl(T v, int mask) { return __shfl_xor(v, mask); }
 
 template <int EQ, class Real>
-__global__ __launch_bounds__(kBlock) void adj_cell_kernel(
+__global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_cell_kernel(
     int N, int E, int NB, Params P, double dt, const double* __restrict__ wbar, const Real* __restrict__ grad,
     const double* __restrict__ lw, const Real* __restrict__ lg, const Real* __restrict__ R,
-    const int32_t* __restrict__ nbr, const int32_t* __restrict__ cell_edge, const int32_t* __restrict__ ecell,
+    const int32_t* __restrict__ nbr, const int32_t* __restrict__ cell_edge,
     const double* __restrict__ enl, const Real* __restrict__ egp, const double* __restrict__ inv_area,
     const Real* __restrict__ nl, const double* __restrict__ bnd_n, const Real* __restrict__ tbl,
     const double* __restrict__ area,
@@ -57,29 +57,31 @@ __global__ __launch_bounds__(kBlock) void adj_cell_kernel(
   }
   if (lane < 3) {
     const int f = lane;
+    // the face's edge and neighbour (nbr < 0: boundary face, no neighbour); the
+    // neighbour's loads read the cell itself there and are not used
     const int ce = cell_edge[f * sN + ic];
+    const int nbv = nbr[f * sN + ic];
     const int e = ce >> 1, side = ce & 1;
-    const int c0 = ecell[e], c1 = ecell[sE + e];
-    const int nb = side ? c0 : c1;
+    const bool has = nbv >= 0;
+    const int nb = has ? nbv : -1, nc = has ? nbv : ic;
     const double nx = enl[e], ny = enl[sE + e], len = enl[2 * sE + e];
     const double sigma = side ? -1.0 : 1.0;
     const double iaK = inv_area[ic];
     const double nlx = double(nl[f * sN + ic]), nly = double(nl[(3 + f) * sN + ic]);
     double WK[M], Wn[M], lF[M], lG[M];
-    const double ian = nb >= 0 ? inv_area[nb] : 0.0;
+    const double ianc = inv_area[nc];
+    const double ian = has ? ianc : 0.0;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
       WK[q] = wbar[q * sN + ic];
-      Wn[q] = nb >= 0 ? wbar[q * sN + nb] : WK[q];
+      const double Wc = wbar[q * sN + nc], lwn = lw[q * sN + nc];
+      const double lgxn = double(lg[q * sN + nc]), lgyn = double(lg[(M + q) * sN + nc]);
+      Wn[q] = has ? Wc : WK[q];
       const double lwK = lw[q * sN + ic];
       const double lgxK = double(lg[q * sN + ic]), lgyK = double(lg[(M + q) * sN + ic]);
-      if (nb >= 0) {
-        lF[q] = -dt * sigma * (iaK * lwK - ian * lw[q * sN + nb]);
-        lG[q] = nlx * (iaK * lgxK - ian * double(lg[q * sN + nb])) + nly * (iaK * lgyK - ian * double(lg[(M + q) * sN + nb]));
-      } else {
-        lF[q] = -dt * iaK * lwK;
-        lG[q] = iaK * (nlx * lgxK + nly * lgyK);
-      }
+      lF[q] = has ? -dt * sigma * (iaK * lwK - ian * lwn) : -dt * iaK * lwK;
+      lG[q] = has ? nlx * (iaK * lgxK - ian * lgxn) + nly * (iaK * lgyK - ian * lgyn)
+                  : iaK * (nlx * lgxK + nly * lgyK);
     }
     double alpha = 0.0;
     if (nb >= 0) {
@@ -158,69 +160,86 @@ __global__ __launch_bounds__(kBlock) void adj_cell_kernel(
   }
 }
 
+// Every load is issued before the arithmetic that uses it, with boundary faces
+// (no neighbour) reading the cell itself and contributing nothing: the faces'
+// index loads, then one round of data gathers.
 template <int EQ, class Real>
-__global__ __launch_bounds__(kBlock) void adj_gather_kernel(
+__global__ __launch_bounds__(kBlock, 2) void adj_gather_kernel(
     int N, int E, Params P, double dt, const double* __restrict__ wbar, const double* __restrict__ lw,
     const Real* __restrict__ lg, const int32_t* __restrict__ nbr, const int32_t* __restrict__ nbr_back,
-    const int32_t* __restrict__ cell_edge, const int32_t* __restrict__ ecell, const double* __restrict__ enl,
-    const double* __restrict__ inv_area, const Real* __restrict__ nl, const double* __restrict__ slots,
-    const double* __restrict__ sface, double* __restrict__ lw_out, Real* __restrict__ lg_out) {
+    const int32_t* __restrict__ cell_edge, const double* __restrict__ enl, const double* __restrict__ inv_area,
+    const Real* __restrict__ nl, const double* __restrict__ slots, const double* __restrict__ sface,
+    double* __restrict__ lw_out, Real* __restrict__ lg_out) {
   constexpr int M = NComp<EQ>::m;
   const int i = xcd_block_id() * kBlock + threadIdx.x;
   if (i >= N) return;
   const size_t sN = size_t(N), sE = size_t(E);
+  int nbf[3], bkf[3], cef[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    nbf[f] = nbr[f * sN + i];
+    bkf[f] = nbr_back[f * sN + i];
+    cef[f] = cell_edge[f * sN + i];
+  }
   const double iaK = inv_area[i];
-  double aW[M], aV[M], aY[M], WK[M];
+  double aW[M], aV[M], aY[M], WK[M], lwK[M], lgxK[M], lgyK[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) {
     WK[q] = wbar[q * sN + i];
-    aW[q] = lw[q * sN + i] + slots[((0 * 3 + 0) * M + q) * sN + i];
+    lwK[q] = lw[q * sN + i];
+    lgxK[q] = double(lg[q * sN + i]);
+    lgyK[q] = double(lg[(M + q) * sN + i]);
+    aW[q] = lwK[q] + slots[((0 * 3 + 0) * M + q) * sN + i];
     aV[q] = slots[((0 * 3 + 1) * M + q) * sN + i];
     aY[q] = slots[((0 * 3 + 2) * M + q) * sN + i];
   }
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
-    const int nb = nbr[f * sN + i];
-    if (nb < 0) continue;
-    const int bk = nbr_back[f * sN + i];
+    const bool has = nbf[f] >= 0;
+    const int nb = has ? nbf[f] : i;
+    const int bk = has ? bkf[f] : 0;
+    const int e = cef[f] >> 1, side = cef[f] & 1;
+    double sW[M], sV[M], sY[M], Wn[M], lwn[M], lgxn[M], lgyn[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) {
-      aW[q] += slots[(((1 + bk) * 3 + 0) * M + q) * sN + nb];
-      aV[q] += slots[(((1 + bk) * 3 + 1) * M + q) * sN + nb];
-      aY[q] += slots[(((1 + bk) * 3 + 2) * M + q) * sN + nb];
+      sW[q] = slots[(((1 + bk) * 3 + 0) * M + q) * sN + nb];
+      sV[q] = slots[(((1 + bk) * 3 + 1) * M + q) * sN + nb];
+      sY[q] = slots[(((1 + bk) * 3 + 2) * M + q) * sN + nb];
+      Wn[q] = wbar[q * sN + nb];
+      lwn[q] = lw[q * sN + nb];
+      lgxn[q] = double(lg[q * sN + nb]);
+      lgyn[q] = double(lg[(M + q) * sN + nb]);
     }
-    // Green-Gauss: |K| Vbar_K includes n|e| (Wbar_nb - Wbar_K)/2 (and the neighbour's the mirror term)
-    const double nlx = double(nl[f * sN + i]), nly = double(nl[(3 + f) * sN + i]);
     const double ian = inv_area[nb];
-#pragma unroll
-    for (int q = 0; q < M; ++q)
-      aW[q] += -0.5 * (nlx * (iaK * double(lg[q * sN + i]) + ian * double(lg[q * sN + nb])) +
-                       nly * (iaK * double(lg[(M + q) * sN + i]) + ian * double(lg[(M + q) * sN + nb])));
-    // flux viscosity: alpha = max(lambda(Wbar_0), lambda(Wbar_1)), first cell on ties
-    const int ce = cell_edge[f * sN + i];
-    const int e = ce >> 1, side = ce & 1;
-    const int c0 = ecell[e], c1 = ecell[sE + e];
+    const double nlx = double(nl[f * sN + i]), nly = double(nl[(3 + f) * sN + i]);
     const double nx = enl[e], ny = enl[sE + e], len = enl[2 * sE + e];
-    double W0[M], W1[M];
+    const double sown = sface[f * sN + i], soth = sface[bk * sN + nb];
+    // every value feeds a select, so no load waits behind a branch
 #pragma unroll
     for (int q = 0; q < M; ++q) {
-      W0[q] = wbar[q * sN + c0];
-      W1[q] = wbar[q * sN + c1];
+      // Green-Gauss: |K| Vbar_K includes n|e| (Wbar_nb - Wbar_K)/2 (and the neighbour the mirror term)
+      const double gg = -0.5 * (nlx * (iaK * lgxK[q] + ian * lgxn[q]) + nly * (iaK * lgyK[q] + ian * lgyn[q]));
+      aW[q] += has ? sW[q] + gg : 0.0;
+      aV[q] += has ? sV[q] : 0.0;
+      aY[q] += has ? sY[q] : 0.0;
     }
-    const double l0 = spectral_radius<EQ>(P, W0, nx, ny), l1 = spectral_radius<EQ>(P, W1, nx, ny);
-    const bool mine = (l0 >= l1) ? (side == 0) : (side == 1);
-    if (!mine) continue;
-    const double ia0 = inv_area[c0], ia1 = inv_area[c1];
+    // flux viscosity: alpha = max(lambda(Wbar_0), lambda(Wbar_1)), first cell on ties;
+    // its derivative goes to the cell whose spectral radius the max selected
+    const double lK = spectral_radius<EQ>(P, WK, nx, ny), ln = spectral_radius<EQ>(P, Wn, nx, ny);
+    const double l0 = side == 0 ? lK : ln, l1 = side == 0 ? ln : lK;
+    const bool mine = has && ((l0 >= l1) ? (side == 0) : (side == 1));
+    const double ia0 = side == 0 ? iaK : ian, ia1 = side == 0 ? ian : iaK;
     double jb = 0.0;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
-      const double lFq = -dt * (ia0 * lw[q * sN + c0] - ia1 * lw[q * sN + c1]);
-      jb += lFq * (W1[q] - W0[q]);
+      const double lw0 = side == 0 ? lwK[q] : lwn[q], lw1 = side == 0 ? lwn[q] : lwK[q];
+      const double W0 = side == 0 ? WK[q] : Wn[q], W1 = side == 0 ? Wn[q] : WK[q];
+      const double lFq = -dt * (ia0 * lw0 - ia1 * lw1);
+      jb += lFq * (W1 - W0);
     }
-    const double sown = sface[f * sN + i], soth = sface[bk * sN + nb];
     const double s0 = side == 0 ? sown : soth, s1 = side == 0 ? soth : sown;
     jb += s1 - s0;
-    spectral_radius_grad<EQ>(P, WK, nx, ny, -0.5 * len * jb, aW);
+    spectral_radius_grad<EQ>(P, WK, nx, ny, mine ? -0.5 * len * jb : 0.0, aW);
   }
 #pragma unroll
   for (int q = 0; q < M; ++q) {
@@ -241,11 +260,10 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
   const int N = int(h.N), E = int(h.E), NB = int(h.NB);
   const Real* R = static_cast<const Real*>(d.R);
   hipLaunchKernelGGL((adj_cell_kernel<EQ, Real>), dim3(grid_for(4 * int64_t(N))), dim3(kBlock), 0, st, N, E, NB, P,
-                     dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.ecell, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl,
+                     dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl,
                      d.area, d.slots, d.sface);
   hipLaunchKernelGGL((adj_gather_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg,
-                     d.nbr, d.nbr_back, d.cell_edge, d.ecell, d.enl, d.inv_area, nl, d.slots, d.sface, lw_out,
-                     lg_out);
+                     d.nbr, d.nbr_back, d.cell_edge, d.enl, d.inv_area, nl, d.slots, d.sface, lw_out, lg_out);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return hip_fail(err, "kernel launch");
   return HWE_OK;
