@@ -28,15 +28,71 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+CSRC = os.path.join(ROOT, "paper_2607_10809_amd", "csrc")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_euler_vortex_204800.md")
 
 
-def kernel_bytes(N, E, m, s):
+def source_digest():
+    """sha256 (first 16 hex digits) over the kernel sources, sorted by name."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` (e.g. 'recon_kernel<2, double>') from the
+    committed counter summary, or None when the kernel sources have changed since
+    the counters were taken (the summary records the source digest)."""
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"source digest: `([0-9a-f]+)`", text)
+    if not m or m.group(1) != source_digest():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip().strip("`") for c in line.split("|")]
+        if len(cells) > 5 and cells[1] == kernel:
+            try:
+                return int(cells[5])
+            except ValueError:
+                return None
+    return None
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=20):
+    """Device-to-device copy rate (bytes read + written per second) of a 1 GiB buffer."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbps
+
+
+def kernel_bytes(N, E, m, s, positivity=False):
     """Algorithmic bytes per launch of the three kernels (each array once).
 
     s = bytes of the bulk real type (8 FP64, 4 mixed).  Counts the per-cell and
-    per-edge arrays each kernel must read or write at least once.
+    per-edge arrays each kernel must read or write at least once (with the
+    positivity limiter, recon also reads the six edge Gauss points per cell).
     """
-    recon = N * (m * 8 + 2 * m * s + 12 + 55 * s + 9 * s + 8 + 3 * s + 6 * m * s)
+    recon = N * (m * 8 + 2 * m * s + 12 + 55 * s + 9 * s + 8 + 3 * s + 6 * m * s + (96 if positivity else 0))
     edge = E * (8 + 24 + 8 * s + m * 8 + m * s) + N * (6 * m * s + m * 8)
     update = N * (m * 8 + 12 + 12 + 6 * s + 8 + m * 8 + 2 * m * s) + E * (m * 8 + m * s)
     return {"recon": recon, "edge": edge, "update": update}
@@ -129,21 +185,79 @@ def adjoint_leg(wl, nsteps=200, ckpt=20, precision="fp64"):
             "step_us": fs * 1e3, "adjoint_step_us": as_ * 1e3, "per_step_ratio": as_ / fs}
 
 
-def cpu_leg(wl, budget_s=12.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_leg(wl, budget_s=12.0, budget_1t_s=5.0):
+    """The oracle on the host cores (all of OMP_NUM_THREADS, then one thread)."""
     from oracle import OracleMesh
     om = OracleMesh.from_workload(wl)
     dt = om.max_dt(wl.state0, wl.cfl)
-    s = wl.state0
-    t0 = time.perf_counter()
-    s = om.step(s, dt)
-    n = 1
-    while time.perf_counter() - t0 < budget_s:
-        s = om.step(s, dt)
-        n += 1
-    el = time.perf_counter() - t0
+
+    def timed(budget, nthreads):
+        s = om.step(wl.state0, dt, nthreads)      # warm-up
+        t0 = time.perf_counter()
+        n = 0
+        while n == 0 or time.perf_counter() - t0 < budget:
+            s = om.step(s, dt, nthreads)
+            n += 1
+        return n, time.perf_counter() - t0
+
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n, el = timed(budget_s, cores)
+    n1, el1 = timed(budget_1t_s, 1)
     return dict(value=om.N * n / el, unit="cell-steps/s", cores=cores, kind="oracle",
-                sample=f"{n} full FP64 steps of the 204,800-triangle vortex mesh ({el:.1f} s wall)")
+                sample=f"{n} full FP64 steps of the 204,800-triangle vortex mesh after one warm-up step "
+                       f"({el:.1f} s wall)",
+                one_thread={"value": om.N * n1 / el1, "steps": n1, "seconds": round(el1, 2)},
+                cpu_model=cpu_model())
+
+
+def c4_leg(steps, warmup):
+    """Throughput on the 980,000-triangle Riemann problem (positivity limiter on):
+    its step moves ~1 GB in FP64, far more than the 256 MB Infinity Cache."""
+    import torch
+    from paper_2607_10809_amd.hwe import Mesh
+    from workloads import riemann_workload
+    wl = riemann_workload()
+    out = {"workload": "euler 2-D Riemann problem, [0,1]^2 transmissive, 700x700 split squares +-0.2h jitter "
+                       "seed 4 (980,000 triangles), positivity limiter", "steps": steps}
+    for prec in ("fp64", "mixed"):
+        mesh = Mesh.from_workload(wl, precision=prec, positivity=True)
+        w0, g0 = mesh.to_device(wl.state0)
+        dt = mesh.max_dt(w0, 0.2)
+        bufs = [(w0, g0), mesh.empty_state()]
+        for i in range(warmup):
+            mesh.step(bufs[i % 2][0], bufs[i % 2][1], dt, out=bufs[(i + 1) % 2])
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(warmup, warmup + steps):
+            mesh.step(bufs[i % 2][0], bufs[i % 2][1], dt, out=bufs[(i + 1) % 2])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        mesh.profile_begin(steps)
+        for i in range(steps):
+            mesh.step(bufs[i % 2][0], bufs[i % 2][1], dt, out=bufs[(i + 1) % 2])
+        kms, nk = mesh.profile_end()
+        torch.cuda.synchronize()
+        kb = kernel_bytes(mesh.N, mesh.E, mesh.m, 8 if prec == "fp64" else 4, positivity=True)
+        out[prec] = {"value": mesh.N / (ms * 1e-3), "ms_per_step": ms,
+                     "step_GBps": round(sum(kb.values()) / (ms * 1e-3) / 1e9, 1),
+                     "kernels": {n: {"us": round(t / nk * 1e3, 2), "GBps": round(kb[n] / (t / nk * 1e-3) / 1e9, 1)}
+                                 for n, t in zip(("recon", "edge", "update"), kms)}}
+        del mesh, bufs, w0, g0
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -153,7 +267,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--n", type=int, default=320, help="squares per side (default: 320 -> 204,800 triangles)")
-    ap.add_argument("--forward-only", action="store_true", help="skip the adjoint leg (for counter runs)")
+    ap.add_argument("--forward-only", action="store_true",
+                    help="skip the adjoint, copy and 980,000-triangle legs (for counter runs)")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 980,000-triangle Riemann leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 20 device copies of 256 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -184,8 +300,12 @@ def main():
     log(f"FP64: {f64['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {f64['kernel_ms']}")
     mix = gpu_leg(wl, args.steps, args.warmup, "mixed")
     log(f"mixed: {mix['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {mix['kernel_ms']}")
-    adj = adjm = None
+    adj = adjm = c4 = copy_gbps = None
     if not args.forward_only:
+        if not args.no_c4:
+            log("980,000-triangle Riemann leg ...")
+            c4 = c4_leg(200, 10)
+        copy_gbps = copy_bandwidth()
         adj = adjoint_leg(wl)
         log(f"adjoint (FP64, 200 steps, checkpoint 20): forward {adj['forward_ms']:.1f} ms, backward "
             f"{adj['backward_ms']:.1f} ms, ratio {adj['ratio']:.2f}; per step {adj['adjoint_step_us']:.1f} us vs "
@@ -206,8 +326,12 @@ def main():
     dom = names[int(np.argmax(f64["kernel_ms"]))]
     achieved = kb64[dom] / (f64["kernel_ms"][names.index(dom)] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"{dom}_kernel<euler,fp64>",
-                "per_launch_bytes": int(kb64[dom])}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f"{dom}_kernel<2, double>"),
+                "kernel": f"{dom}_kernel<2, double>", "per_launch_bytes": int(kb64[dom]),
+                "source_digest": source_digest()}
+    if copy_gbps:
+        roofline["measured_copy_GBps"] = round(copy_gbps, 1)
+        roofline["frac_of_copy"] = round(achieved / copy_gbps, 4)
     step_bytes = sum(kb64.values())
     out = {
         "metric": "cell-steps/s FP64 vs FP32 + adjoint/forward time ratio, Euler 204,800 tris",
@@ -236,6 +360,8 @@ def main():
         "kernels": per_kernel,
         "roofline": roofline,
         "state_flags": {"fp64": f64["flags"], "mixed": mix["flags"]},
+        "riemann_980k": c4,
+        "hip_graph": False,
     }
     if not args.no_cpu:
         log("CPU oracle baseline ...")
