@@ -13,7 +13,7 @@
 //      shuffles; work-item q then reverses the reconstruction of component q
 //      (Steps 1-6, including the nonlinear-weight derivatives) into four
 //      stencil "slots" (the cell itself and its three neighbours).
-//   3. adj_gather_kernel, one work-item per cell: its own slot, the slots its
+//   3. adj_gather_kernel, one work-item per (cell, component): its own slot, the slots its
 //      neighbours wrote for it, the Green-Gauss terms of the derivative
 //      averages and the derivative of the flux viscosity alpha (only on the
 //      cell whose spectral radius the max selected).
@@ -31,6 +31,13 @@ namespace {
 constexpr int kBlock = 256;
 
 template <class T> __device__ __forceinline__ T xshfl(T v, int mask) { return __shfl_xor(v, mask); }
+
+// Stencil-slot adjoints, cell-major: cell i's record holds 4 slots (itself,
+// then its neighbours across faces 0-2) x 3 fields (Wbar, V, Y) x M components,
+// so a neighbour's slot for this cell is one contiguous 3M-value run.
+template <int M> __device__ __forceinline__ size_t slot_index(int i, int sl, int fl, int q) {
+  return size_t(i) * (12 * M) + size_t((sl * 3 + fl) * M + q);
+}
 
 template <int EQ, class Real>
 __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_cell_kernel(
@@ -156,22 +163,25 @@ __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_cell_ke
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl)
 #pragma unroll
-      for (int fl = 0; fl < 3; ++fl) slots[((sl * 3 + fl) * M + q) * sN + i] = slot[sl][fl];
+      for (int fl = 0; fl < 3; ++fl) slots[slot_index<M>(i, sl, fl, q)] = slot[sl][fl];
   }
 }
 
-// Every load is issued before the arithmetic that uses it, with boundary faces
-// (no neighbour) reading the cell itself and contributing nothing: the faces'
-// index loads, then one round of data gathers.
+// One work-item per (cell, component q).  Every load is issued before the
+// arithmetic that uses it, with boundary faces (no neighbour) reading the cell
+// itself and contributing nothing: the faces' index loads, then one round of
+// data gathers.  The flux-viscosity term needs the whole state vectors of both
+// cells; each component's work-item forms it and keeps its own component.
 template <int EQ, class Real>
-__global__ __launch_bounds__(kBlock, 2) void adj_gather_kernel(
+__global__ __launch_bounds__(kBlock) void adj_gather_kernel(
     int N, int E, Params P, double dt, const double* __restrict__ wbar, const double* __restrict__ lw,
     const Real* __restrict__ lg, const int32_t* __restrict__ nbr, const int32_t* __restrict__ nbr_back,
     const int32_t* __restrict__ cell_edge, const double* __restrict__ enl, const double* __restrict__ inv_area,
     const Real* __restrict__ nl, const double* __restrict__ slots, const double* __restrict__ sface,
     double* __restrict__ lw_out, Real* __restrict__ lg_out) {
   constexpr int M = NComp<EQ>::m;
-  const int i = xcd_block_id() * kBlock + threadIdx.x;
+  const int gid = xcd_block_id() * kBlock + threadIdx.x;
+  const int i = gid / M, q = gid - (gid / M) * M;
   if (i >= N) return;
   const size_t sN = size_t(N), sE = size_t(E);
   int nbf[3], bkf[3], cef[3];
@@ -182,47 +192,45 @@ __global__ __launch_bounds__(kBlock, 2) void adj_gather_kernel(
     cef[f] = cell_edge[f * sN + i];
   }
   const double iaK = inv_area[i];
-  double aW[M], aV[M], aY[M], WK[M], lwK[M], lgxK[M], lgyK[M];
+  double WK[M], lwK[M];
 #pragma unroll
-  for (int q = 0; q < M; ++q) {
-    WK[q] = wbar[q * sN + i];
-    lwK[q] = lw[q * sN + i];
-    lgxK[q] = double(lg[q * sN + i]);
-    lgyK[q] = double(lg[(M + q) * sN + i]);
-    aW[q] = lwK[q] + slots[((0 * 3 + 0) * M + q) * sN + i];
-    aV[q] = slots[((0 * 3 + 1) * M + q) * sN + i];
-    aY[q] = slots[((0 * 3 + 2) * M + q) * sN + i];
+  for (int c = 0; c < M; ++c) {
+    WK[c] = wbar[c * sN + i];
+    lwK[c] = lw[c * sN + i];
   }
+  const double lgxK = double(lg[q * sN + i]), lgyK = double(lg[(M + q) * sN + i]);
+  double aW = slots[slot_index<M>(i, 0, 0, q)];
+  double aV = slots[slot_index<M>(i, 0, 1, q)];
+  double aY = slots[slot_index<M>(i, 0, 2, q)];
+  double aWall[M];  // flux-viscosity adjoint, all components
+#pragma unroll
+  for (int c = 0; c < M; ++c) aWall[c] = 0.0;
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const bool has = nbf[f] >= 0;
     const int nb = has ? nbf[f] : i;
     const int bk = has ? bkf[f] : 0;
     const int e = cef[f] >> 1, side = cef[f] & 1;
-    double sW[M], sV[M], sY[M], Wn[M], lwn[M], lgxn[M], lgyn[M];
+    const double sW = slots[slot_index<M>(nb, 1 + bk, 0, q)];
+    const double sV = slots[slot_index<M>(nb, 1 + bk, 1, q)];
+    const double sY = slots[slot_index<M>(nb, 1 + bk, 2, q)];
+    double Wn[M], lwn[M];
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-      sW[q] = slots[(((1 + bk) * 3 + 0) * M + q) * sN + nb];
-      sV[q] = slots[(((1 + bk) * 3 + 1) * M + q) * sN + nb];
-      sY[q] = slots[(((1 + bk) * 3 + 2) * M + q) * sN + nb];
-      Wn[q] = wbar[q * sN + nb];
-      lwn[q] = lw[q * sN + nb];
-      lgxn[q] = double(lg[q * sN + nb]);
-      lgyn[q] = double(lg[(M + q) * sN + nb]);
+    for (int c = 0; c < M; ++c) {
+      Wn[c] = wbar[c * sN + nb];
+      lwn[c] = lw[c * sN + nb];
     }
+    const double lgxn = double(lg[q * sN + nb]), lgyn = double(lg[(M + q) * sN + nb]);
     const double ian = inv_area[nb];
     const double nlx = double(nl[f * sN + i]), nly = double(nl[(3 + f) * sN + i]);
     const double nx = enl[e], ny = enl[sE + e], len = enl[2 * sE + e];
     const double sown = sface[f * sN + i], soth = sface[bk * sN + nb];
     // every value feeds a select, so no load waits behind a branch
-#pragma unroll
-    for (int q = 0; q < M; ++q) {
-      // Green-Gauss: |K| Vbar_K includes n|e| (Wbar_nb - Wbar_K)/2 (and the neighbour the mirror term)
-      const double gg = -0.5 * (nlx * (iaK * lgxK[q] + ian * lgxn[q]) + nly * (iaK * lgyK[q] + ian * lgyn[q]));
-      aW[q] += has ? sW[q] + gg : 0.0;
-      aV[q] += has ? sV[q] : 0.0;
-      aY[q] += has ? sY[q] : 0.0;
-    }
+    // Green-Gauss: |K| Vbar_K includes n|e| (Wbar_nb - Wbar_K)/2 (and the neighbour the mirror term)
+    const double gg = -0.5 * (nlx * (iaK * lgxK + ian * lgxn) + nly * (iaK * lgyK + ian * lgyn));
+    aW += has ? sW + gg : 0.0;
+    aV += has ? sV : 0.0;
+    aY += has ? sY : 0.0;
     // flux viscosity: alpha = max(lambda(Wbar_0), lambda(Wbar_1)), first cell on ties;
     // its derivative goes to the cell whose spectral radius the max selected
     const double lK = spectral_radius<EQ>(P, WK, nx, ny), ln = spectral_radius<EQ>(P, Wn, nx, ny);
@@ -231,22 +239,25 @@ __global__ __launch_bounds__(kBlock, 2) void adj_gather_kernel(
     const double ia0 = side == 0 ? iaK : ian, ia1 = side == 0 ? ian : iaK;
     double jb = 0.0;
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-      const double lw0 = side == 0 ? lwK[q] : lwn[q], lw1 = side == 0 ? lwn[q] : lwK[q];
-      const double W0 = side == 0 ? WK[q] : Wn[q], W1 = side == 0 ? Wn[q] : WK[q];
+    for (int c = 0; c < M; ++c) {
+      const double lw0 = side == 0 ? lwK[c] : lwn[c], lw1 = side == 0 ? lwn[c] : lwK[c];
+      const double W0 = side == 0 ? WK[c] : Wn[c], W1 = side == 0 ? Wn[c] : WK[c];
       const double lFq = -dt * (ia0 * lw0 - ia1 * lw1);
       jb += lFq * (W1 - W0);
     }
     const double s0 = side == 0 ? sown : soth, s1 = side == 0 ? soth : sown;
     jb += s1 - s0;
-    spectral_radius_grad<EQ>(P, WK, nx, ny, mine ? -0.5 * len * jb : 0.0, aW);
+    spectral_radius_grad<EQ>(P, WK, nx, ny, mine ? -0.5 * len * jb : 0.0, aWall);
   }
+  double av = aWall[0], lq = lwK[0];
 #pragma unroll
-  for (int q = 0; q < M; ++q) {
-    lw_out[q * sN + i] = aW[q];
-    lg_out[q * sN + i] = Real(aV[q]);
-    lg_out[(M + q) * sN + i] = Real(aY[q]);
+  for (int c = 1; c < M; ++c) {
+    av = q == c ? aWall[c] : av;
+    lq = q == c ? lwK[c] : lq;
   }
+  lw_out[q * sN + i] = lq + aW + av;
+  lg_out[q * sN + i] = Real(aV);
+  lg_out[(M + q) * sN + i] = Real(aY);
 }
 
 unsigned grid_for(int64_t items) { return unsigned((items + kBlock - 1) / kBlock); }
@@ -262,7 +273,7 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
   hipLaunchKernelGGL((adj_cell_kernel<EQ, Real>), dim3(grid_for(4 * int64_t(N))), dim3(kBlock), 0, st, N, E, NB, P,
                      dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl,
                      d.area, d.slots, d.sface);
-  hipLaunchKernelGGL((adj_gather_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg,
+  hipLaunchKernelGGL((adj_gather_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg,
                      d.nbr, d.nbr_back, d.cell_edge, d.enl, d.inv_area, nl, d.slots, d.sface, lw_out, lg_out);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return hip_fail(err, "kernel launch");

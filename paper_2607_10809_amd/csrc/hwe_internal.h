@@ -70,7 +70,7 @@ struct DevMesh {
   void* R = nullptr;
   void* F = nullptr;
   void* G = nullptr;
-  // adjoint scratch: stencil-slot adjoints [4][3][m][N] and per-face scalars [3][N]
+  // adjoint scratch: stencil-slot adjoints [N][4][3][m] and per-face scalars [3][N]
   double* slots = nullptr;
   double* sface = nullptr;
   // reductions
