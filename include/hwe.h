@@ -143,9 +143,10 @@ hwe_status hwe_max_dt(hwe_mesh m, const double* wbar, double cfl, double* dt_dev
 hwe_status hwe_check_state(hwe_mesh m, const double* wbar, int32_t* flags_dev, void* stream);
 
 /* Reconstruction only (Steps 1-6) for kernel-level tests: R_out is device
- * [6][m][N] of double (FP64) or float (MIXED) holding, per cell and component,
- * the coefficients a0..a5 of R - Wbar in the monomial basis about the cell
- * centroid: R(x,y) - Wbar = a0 + a1 X + a2 Y + a3 X^2 + a4 XY + a5 Y^2. */
+ * [N][6][m] (internal cell order) of double (FP64) or float
+ * (MIXED) holding, per cell and component, the coefficients a0..a5 of R - Wbar
+ * in the monomial basis about the cell centroid:
+ * R(x,y) - Wbar = a0 + a1 X + a2 Y + a3 X^2 + a4 XY + a5 Y^2. */
 hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, void* R_out, void* stream);
 
 /* Host copy of a precomputed per-cell array for host-logic tests (works for

@@ -119,10 +119,7 @@ __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_cell_ke
       }
     }
     Real a[6][M];
-#pragma unroll
-    for (int j = 0; j < 6; ++j)
-#pragma unroll
-      for (int q = 0; q < M; ++q) a[j][q] = R[(j * M + q) * sN + ic];
+    load_record<6 * M>(R + size_t(ic) * (6 * M), &a[0][0]);
     double s = 0.0;
 #pragma unroll
     for (int g = 0; g < 2; ++g) {

@@ -64,9 +64,9 @@ struct DevMesh {
   float* tblf = nullptr;
   float* nlf = nullptr;
   float* egpf = nullptr;
-  // scratch: reconstruction coefficients [6][m][N] (double or float by
-  // precision), edge flux [m][E] (double) and interface-value offset [m][E]
-  // (double or float)
+  // scratch: reconstruction coefficients [N][6][m] (double or float by
+  // precision), edge flux [E][m] (double) and interface-value offset [E][m]
+  // (double or float); hipMalloc's 256-byte alignment keeps every record 16-byte aligned
   void* R = nullptr;
   void* F = nullptr;
   void* G = nullptr;

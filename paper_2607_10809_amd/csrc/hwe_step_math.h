@@ -4,13 +4,69 @@
 //
 // Layouts (internal cell order, N cells, E edges, M components):
 //   wbar [M][N] double, grad [2][M][N] Real (W_x then W_y averages),
-//   R [6][M][N] Real: R - Wbar_K = a0 + a1 X + a2 Y + a3 X^2 + a4 XY + a5 Y^2
-//     about the centroid of K, F [M][E] double, G [M][E] Real.
+//   R [N][6][M] Real: R - Wbar_K = a0 + a1 X + a2 Y + a3 X^2 + a4 XY + a5 Y^2
+//     about the centroid of K (one contiguous record per cell),
+//   F [E][M] double, G [E][M] Real (one record per edge).
 #pragma once
+
+#include <type_traits>
 
 #include "hwe_math.h"
 
 namespace hwe {
+
+// Contiguous records (a cell's R, an edge's F or G) moved with 16-byte
+// accesses; records start 16-byte aligned (M = 4: 96 or 192 bytes per R,
+// 32 per F, 16 or 32 per G).  Scalar equations fall back to element access.
+template <int K, class T>
+__host__ __device__ __forceinline__ void load_record(const T* __restrict__ src, T* dst) {
+  if constexpr ((K * sizeof(T)) % 16 == 0) {
+    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    constexpr int W = 16 / sizeof(T);
+    const V* s = reinterpret_cast<const V*>(src);
+#pragma unroll
+    for (int k = 0; k < K / W; ++k) {
+      const V v = s[k];
+      if constexpr (W == 2) {
+        dst[2 * k] = v.x;
+        dst[2 * k + 1] = v.y;
+      } else {
+        dst[4 * k] = v.x;
+        dst[4 * k + 1] = v.y;
+        dst[4 * k + 2] = v.z;
+        dst[4 * k + 3] = v.w;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) dst[k] = src[k];
+  }
+}
+template <int K, class T>
+__host__ __device__ __forceinline__ void store_record(T* __restrict__ dst, const T* src) {
+  if constexpr ((K * sizeof(T)) % 16 == 0) {
+    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    constexpr int W = 16 / sizeof(T);
+    V* d = reinterpret_cast<V*>(dst);
+#pragma unroll
+    for (int k = 0; k < K / W; ++k) {
+      V v;
+      if constexpr (W == 2) {
+        v.x = src[2 * k];
+        v.y = src[2 * k + 1];
+      } else {
+        v.x = src[4 * k];
+        v.y = src[4 * k + 1];
+        v.z = src[4 * k + 2];
+        v.w = src[4 * k + 3];
+      }
+      d[k] = v;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) dst[k] = src[k];
+  }
+}
 
 // ------------------------------------------------------------------ Steps 1-6
 // The stencil of component q of cell i: its own average and derivative
@@ -162,9 +218,9 @@ __host__ __device__ __forceinline__ void recon_coeffs(int i, int q, int N, int N
 template <int EQ, class Real>
 __host__ __device__ __forceinline__ void store_coeffs(int i, int q, int N, const Real (&a)[6], Real* __restrict__ R) {
   constexpr int M = NComp<EQ>::m;
-  const size_t sN = size_t(N);
+  (void)N;
 #pragma unroll
-  for (int j = 0; j < 6; ++j) R[(j * M + q) * sN + i] = a[j];
+  for (int j = 0; j < 6; ++j) R[(size_t(i) * 6 + j) * M + q] = a[j];
 }
 
 // Positivity-preserving scaling of the Euler reconstruction of one cell (the
@@ -241,14 +297,14 @@ __host__ __device__ __forceinline__ void edge_lane(int e, int cell, int side, in
 #pragma unroll
   for (int q = 0; q < M; ++q) AH[q] = AD[q] = AT[q] = Real(0);
   if (cell < 0) return;
-  const size_t sN = size_t(N);
+  Real ac[6][M];
+  load_record<6 * M>(R + size_t(cell) * (6 * M), &ac[0][0]);
   const Real X = egp[(4 * side + 2 * g) * E + e];
   const Real Y = egp[(4 * side + 2 * g + 1) * E + e];
   Real D[6][M], dl[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) {
-    const Real a0 = R[(0 * M + q) * sN + cell], a1 = R[(1 * M + q) * sN + cell], a2 = R[(2 * M + q) * sN + cell];
-    const Real a3 = R[(3 * M + q) * sN + cell], a4 = R[(4 * M + q) * sN + cell], a5 = R[(5 * M + q) * sN + cell];
+    const Real a0 = ac[0][q], a1 = ac[1][q], a2 = ac[2][q], a3 = ac[3][q], a4 = ac[4][q], a5 = ac[5][q];
     dl[q] = a0 + a1 * X + a2 * Y + a3 * X * X + a4 * X * Y + a5 * Y * Y;  // W - Wbar at the point
     D[0][q] = Real(Wbd[q]) + dl[q];
     D[1][q] = a1 + Real(2) * a3 * X + a4 * Y;
@@ -304,18 +360,15 @@ __host__ __device__ __forceinline__ void edge_flux(int e, int E, double len, boo
                                                   const Real (&AD)[NComp<EQ>::m], const Real (&OH)[NComp<EQ>::m],
                                                   const Real (&OD)[NComp<EQ>::m], double* __restrict__ F) {
   constexpr int M = NComp<EQ>::m;
-  const size_t sE = size_t(E);
-  if (!second) {
-#pragma unroll
-    for (int q = 0; q < M; ++q) F[q * sE + e] = len * (Hl[q] + double(AH[q]));
-    return;
-  }
+  double f[M];
   const double alpha = la >= lb ? la : lb;
 #pragma unroll
   for (int q = 0; q < M; ++q) {
     const double jump = (Wr[q] - Wl[q]) + double(OD[q] - AD[q]);
-    F[q * sE + e] = len * 0.5 * ((Hl[q] + Hr[q]) + double(AH[q] + OH[q]) - alpha * jump);
+    f[q] = second ? len * 0.5 * ((Hl[q] + Hr[q]) + double(AH[q] + OH[q]) - alpha * jump)
+                  : len * (Hl[q] + double(AH[q]));
   }
+  store_record<M>(F + size_t(e) * M, f);
 }
 
 // Gauss average of the interface value of eq. (timeflux) at t_n + dt, as an
@@ -324,8 +377,10 @@ template <int EQ, class Real>
 __host__ __device__ __forceinline__ void edge_value(int e, int E, bool second, const Real (&AT)[NComp<EQ>::m],
                                                    const Real (&OT)[NComp<EQ>::m], Real* __restrict__ G) {
   constexpr int M = NComp<EQ>::m;
+  Real v[M];
 #pragma unroll
-  for (int q = 0; q < M; ++q) G[q * size_t(E) + e] = second ? Real(0.5) * (AT[q] + OT[q]) : AT[q];
+  for (int q = 0; q < M; ++q) v[q] = second ? Real(0.5) * (AT[q] + OT[q]) : AT[q];
+  store_record<M>(G + size_t(e) * M, v);
 }
 
 // ------------------------------------------------------------------ update
@@ -340,7 +395,7 @@ __host__ __device__ __forceinline__ void update_point(int i, int N, int E, doubl
                                                      const double* __restrict__ F, const Real* __restrict__ G,
                                                      double* __restrict__ wout, Real* __restrict__ gout) {
   constexpr int M = NComp<EQ>::m;
-  const size_t sN = size_t(N), sE = size_t(E);
+  const size_t sN = size_t(N);
   double W0[M], fs[M], vs[M], ys[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) {
@@ -361,13 +416,16 @@ __host__ __device__ __forceinline__ void update_point(int i, int N, int E, doubl
     const bool second = (ce[f] & 1) != 0;
     const int c = nb[f] >= 0 ? nb[f] : i;
     const double nlx = nl[f * sN + i], nly = nl[(3 + f) * sN + i];
+    double Fe[M];
+    Real Ge[M];
+    load_record<M>(F + size_t(e) * M, Fe);
+    load_record<M>(G + size_t(e) * M, Ge);
 #pragma unroll
     for (int q = 0; q < M; ++q) {
-      const double Fe = F[q * sE + e];
       const double Wn = wbar[q * sN + c];
-      fs[q] += second ? -Fe : Fe;
-      const double d = nb[f] >= 0 ? 0.5 * (Wn - W0[q]) : 0.0;
-      const double gq = double(G[q * sE + e]) + d;
+      fs[q] += second ? -Fe[q] : Fe[q];
+      const double d = 0.5 * (Wn - W0[q]);  // exactly 0 on a boundary face (Wn is the cell's own)
+      const double gq = double(Ge[q]) + d;
       vs[q] += nlx * gq;
       ys[q] += nly * gq;
     }

@@ -195,9 +195,11 @@ class Mesh:
         return int(out.item())
 
     def debug_recon(self, wbar, grad, stream=None):
-        R = torch.empty((6, self.m, self.N), dtype=self.gdtype, device=self.device)
+        """R - Wbar coefficients a0..a5 per cell and component, as a (6, m, N) view
+        of the library's cell-major [N][6][m] record."""
+        R = torch.empty((self.N, 6, self.m), dtype=self.gdtype, device=self.device)
         check(self._L.hwe_debug_recon(self._h, _ptr(wbar), _ptr(grad), _ptr(R), _stream(stream)))
-        return R
+        return R.permute(1, 2, 0)
 
     def profile_begin(self, n_steps):
         check(self._L.hwe_profile_begin(self._h, int(n_steps)))
