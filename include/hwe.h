@@ -77,6 +77,15 @@ typedef struct {
                              limiter cited in Sec. 3): density, then pressure, kept
                              >= min(1e-13, average density, average pressure) at
                              the cell's six edge Gauss points.  0: off */
+  int32_t time_rule;      /* quadrature of the time integral in eq. (flux):
+                             0 = 3-point Gauss-Lobatto, nodes {0, 1/2, 1} dt,
+                             weights {1, 4, 1}/6 (default); 1 = 2-point
+                             Gauss-Legendre, nodes (1/2 -+ sqrt(3)/6) dt, weights
+                             1/2.  The interface value of eq. (timeflux) is the
+                             Taylor polynomial at dt with either rule */
+  double deriv_weight;    /* weight w > 0 of the two derivative rows in the
+                             Step-2 least squares of Sec. 2.2 (the linear
+                             candidates); 1 = the rows as printed (default) */
 } hwe_opts;
 
 /* Fill *o with the paper's defaults: linear weights 0.94/0.02/0.02/0.02

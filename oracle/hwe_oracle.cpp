@@ -19,7 +19,9 @@
 //     with the interface value of eq. (timeflux) at tau = dt (eq. (taylor2dtime)).
 //
 // Readings where the paper is silent (both sides of the parity test use them):
-//   time rule: 3-point Gauss-Lobatto, nodes {0, 1/2, 1} dt, weights {1,4,1}/6;
+//   time rule: 3-point Gauss-Lobatto, nodes {0, 1/2, 1} dt, weights {1,4,1}/6
+//   (a 2-point Gauss-Legendre rule is an option; the interface value is the
+//   Taylor polynomial at dt either way);
 //   edge rule: 2-point Gauss-Legendre; alpha from the two cell averages;
 //   systems: component-wise reconstruction of the conservative variables;
 //   periodic boundaries by exact translation across seams; transmissive
@@ -104,11 +106,19 @@ template <class T> HD<T> recip(const HD<T>& x) {
 template <class T> HD<T> operator/(const HD<T>& x, const HD<T>& y) { return x * recip(y); }
 
 // ---------------------------------------------------------------- rules
-// 2-point Gauss-Legendre on each edge; 3-point Gauss-Lobatto in time
+// 2-point Gauss-Legendre on each edge.  In time (the rule of eq. (flux) on
+// [0, dt], nodes as fractions of dt): 3-point Gauss-Lobatto {0, 1/2, 1} with
+// weights {1, 4, 1}/6 (default), or 2-point Gauss-Legendre 1/2 -+ sqrt(3)/6
+// with weights 1/2.
 const double kGaussS[2] = {0.5 - 0.28867513459481288225, 0.5 + 0.28867513459481288225};  // 1/2 -+ sqrt(3)/6
 const double kGaussW[2] = {0.5, 0.5};
-const double kTimeL[3] = {0.0, 0.5, 1.0};
-const double kTimeW[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+struct TimeRule {
+  int n;
+  double node[3], w[3];
+};
+const TimeRule kTimeRules[2] = {{3, {0.0, 0.5, 1.0}, {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0}},
+                                {2, {0.5 - 0.28867513459481288225, 0.5 + 0.28867513459481288225, 0.0},
+                                 {0.5, 0.5, 0.0}}};
 
 // ---------------------------------------------------------------- options
 struct Opts {
@@ -121,6 +131,8 @@ struct Opts {
   double eps;       // epsilon of the nonlinear weights
   int linear_only;  // 1: use the linear weights (omega = gamma), for exactness pins
   int positivity;   // 1: scaling limiter on the reconstruction (Euler)
+  int time_rule;    // 0: 3-point Gauss-Lobatto, 1: 2-point Gauss-Legendre
+  double deriv_weight;  // weight of the derivative rows in the Step-2 least squares (1: as printed)
 };
 
 inline int ncomp(int eq) { return eq == 2 ? 4 : 1; }
@@ -406,18 +418,20 @@ bool reconstruct(const Mesh& M, const T* s, int64_t k, Recon<T>& R) {
   }
   // Step 2: linear p2, p3, p4 on {K0, K_l}: the K0 average exactly, the K_l
   // average and K_l derivative averages in the least-squares sense, with the
-  // rows as written (each divided by the common factor |K_l|).
+  // rows as written (each divided by the common factor |K_l|); the two
+  // derivative rows are multiplied by o.deriv_weight (1 by default).
+  const double wd = o.deriv_weight;
   for (int l = 1; l <= 3; ++l) {
     auto avg_x = [&](const Tri& t) { return tri_avg_quadratic(t, [&](double x, double) { return x - x0; }); };
     auto avg_y = [&](const Tri& t) { return tri_avg_quadratic(t, [&](double, double y) { return y - y0; }); };
     double C[3] = {1.0, avg_x(st[0].t), avg_y(st[0].t)};
-    double A[9] = {1.0, avg_x(st[l].t), avg_y(st[l].t), 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+    double A[9] = {1.0, avg_x(st[l].t), avg_y(st[l].t), 0.0, wd, 0.0, 0.0, 0.0, wd};
     std::vector<T> b(3 * m), d(m), x;
     for (int q = 0; q < m; ++q) {
       d[q] = st[0].W[q];
       b[0 * m + q] = st[l].W[q];
-      b[1 * m + q] = st[l].V[q];
-      b[2 * m + q] = st[l].Y[q];
+      b[1 * m + q] = T(wd) * st[l].V[q];
+      b[2 * m + q] = T(wd) * st[l].Y[q];
     }
     if (!constrained_lsq<T>(3, 3, 1, A, C, b, d, m, x)) return false;
     for (int q = 0; q < m; ++q) {
@@ -640,27 +654,33 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
       T it[4], itx[4], ity[4], itt[4], et[4], etx[4], ety[4], ett[4];
       lax_wendroff(o, m, Di, it, itx, ity, itt);
       if (F.nb >= 0) lax_wendroff(o, m, De, et, etx, ety, ett);
-      for (int sN = 0; sN < 3; ++sN) {
-        double tau = kTimeL[sN] * dt;
-        T Wi[4], We[4], fi[4], gi[4], fe[4], ge[4];
+      // Taylor polynomials in time, eq. (tay), of the interior and exterior values
+      auto taylor = [&](double tau, T Wi[4], T We[4]) {
         for (int q = 0; q < m; ++q) {
           Wi[q] = Di[0][q] + T(tau) * it[q] + T(0.5 * tau * tau) * itt[q];
           We[q] = F.nb >= 0 ? De[0][q] + T(tau) * et[q] + T(0.5 * tau * tau) * ett[q] : Wi[q];
         }
+      };
+      const TimeRule& rule = kTimeRules[o.time_rule == 1 ? 1 : 0];
+      for (int sN = 0; sN < rule.n; ++sN) {
+        T Wi[4], We[4], fi[4], gi[4], fe[4], ge[4];
+        taylor(rule.node[sN] * dt, Wi, We);
         flux_fg(o, Wi, fi, gi);
         flux_fg(o, We, fe, ge);
         for (int q = 0; q < m; ++q) {
           T Hi = fi[q] * T(F.nx) + gi[q] * T(F.ny);
           T He = fe[q] * T(F.nx) + ge[q] * T(F.ny);
           T Hhat = T(0.5) * (He + Hi - alpha * (We[q] - Wi[q]));
-          Fsum[q] += Hhat * T(kTimeW[sN] * kGaussW[G] * F.len);
+          Fsum[q] += Hhat * T(rule.w[sN] * kGaussW[G] * F.len);
         }
-        if (sN == 2) {  // tau = dt: interface value for the derivative averages
-          for (int q = 0; q < m; ++q) {
-            T What = T(0.5) * (Wi[q] + We[q]);
-            Vs[q] += What * T(F.nx * kGaussW[G] * F.len);
-            Ys[q] += What * T(F.ny * kGaussW[G] * F.len);
-          }
+      }
+      {  // tau = dt: interface value of eq. (timeflux) for the derivative averages
+        T Wi[4], We[4];
+        taylor(dt, Wi, We);
+        for (int q = 0; q < m; ++q) {
+          T What = T(0.5) * (Wi[q] + We[q]);
+          Vs[q] += What * T(F.nx * kGaussW[G] * F.len);
+          Ys[q] += What * T(F.ny * kGaussW[G] * F.len);
         }
       }
     }
@@ -845,6 +865,8 @@ struct or_opts {
   double eps;
   int linear_only;
   int positivity;
+  int time_rule;
+  double deriv_weight;
 };
 
 void* or_mesh_new(const double* nodes, int64_t nn, const int32_t* tris, int64_t nt, const or_opts* o,
@@ -860,6 +882,8 @@ void* or_mesh_new(const double* nodes, int64_t nn, const int32_t* tris, int64_t 
   M->o.eps = o->eps;
   M->o.linear_only = o->linear_only;
   M->o.positivity = o->positivity;
+  M->o.time_rule = o->time_rule;
+  M->o.deriv_weight = o->deriv_weight;
   int st = build_mesh(*M, nodes, nn, tris, nt);
   if (status) *status = st;
   if (st != 0) {

@@ -39,7 +39,7 @@ template <int M> __device__ __forceinline__ size_t slot_index(int i, int sl, int
   return size_t(i) * (12 * M) + size_t((sl * 3 + fl) * M + q);
 }
 
-template <int EQ, class Real>
+template <int EQ, class Real, int TR>
 __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_cell_kernel(
     int N, int E, int NB, Params P, double dt, const double* __restrict__ wbar, const Real* __restrict__ grad,
     const double* __restrict__ lw, const Real* __restrict__ lg, const Real* __restrict__ R,
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_cell_ke
       const Real X = egp[(4 * side + 2 * g) * sE + e];
       const Real Y = egp[(4 * side + 2 * g + 1) * sE + e];
       Real ADg[M];
-      edge_lane_rev<EQ, Real>(P, dt, a, WK, X, Y, Real(nx), Real(ny), sAH, sAD, sAT, la, lWf, ADg);
+      edge_lane_rev<EQ, Real, TR>(P, dt, a, WK, X, Y, Real(nx), Real(ny), sAH, sAD, sAT, la, lWf, ADg);
 #pragma unroll
       for (int q = 0; q < M; ++q) s += 0.5 * lF[q] * double(ADg[q]);
     }
@@ -267,9 +267,14 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
   const DevMesh& d = M->d;
   const int N = int(h.N), E = int(h.E), NB = int(h.NB);
   const Real* R = static_cast<const Real*>(d.R);
-  hipLaunchKernelGGL((adj_cell_kernel<EQ, Real>), dim3(grid_for(4 * int64_t(N))), dim3(kBlock), 0, st, N, E, NB, P,
-                     dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl,
-                     d.area, d.slots, d.sface);
+  if (P.time_rule == 1)
+    hipLaunchKernelGGL((adj_cell_kernel<EQ, Real, 1>), dim3(grid_for(4 * int64_t(N))), dim3(kBlock), 0, st, N, E, NB, P,
+                       dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl,
+                       d.area, d.slots, d.sface);
+  else
+    hipLaunchKernelGGL((adj_cell_kernel<EQ, Real, 0>), dim3(grid_for(4 * int64_t(N))), dim3(kBlock), 0, st, N, E, NB, P,
+                       dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl,
+                       d.area, d.slots, d.sface);
   hipLaunchKernelGGL((adj_gather_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg,
                      d.nbr, d.nbr_back, d.cell_edge, d.enl, d.inv_area, nl, d.slots, d.sface, lw_out, lg_out);
   hipError_t err = hipGetLastError();

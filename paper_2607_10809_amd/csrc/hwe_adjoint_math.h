@@ -419,7 +419,7 @@ __host__ __device__ __forceinline__ void spectral_radius_grad(const Params& P, c
 // adjoints of AH, AD, AT of this lane, accumulate the adjoints of the cell's
 // coefficients a[6][M] and of its cell average.  Returns (in ADout) the
 // forward AD of the lane, used by the flux viscosity's adjoint.
-template <int EQ, class Real>
+template <int EQ, class Real, int TR>
 __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double dt, const Real (&a)[6][NComp<EQ>::m],
                                                       const double (&Wbd)[NComp<EQ>::m], Real X, Real Y, Real nx,
                                                       Real ny, const Real (&lAH)[NComp<EQ>::m],
@@ -441,8 +441,6 @@ __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double d
   Real Wt[M], Wtt[M];
   lax_wendroff<EQ, Real>(P, D, Wt, Wtt);
   const FluxBase<EQ, Real> base = flux_base<EQ, Real>(P, Wbd);
-  const Real taus[3] = {Real(0), Real(0.5 * dt), Real(dt)};
-  const Real wts[3] = {Real(1.0 / 6.0), Real(4.0 / 6.0), Real(1.0 / 6.0)};
   FluxBaseAdj<EQ, Real> lb;
 #pragma unroll
   for (int q = 0; q < M; ++q) lb.w[q] = Real(0);
@@ -453,16 +451,17 @@ __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double d
     ldl[q] = lWt[q] = lWtt[q] = Real(0);
     ADout[q] = Real(0);
   }
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const Real tau = taus[s], h2 = Real(0.5) * tau * tau;
+  // one node of the time rule, reversed: d(tau) = dl + tau W_t + tau^2/2 W_tt
+  // feeds w dH(d) into AH and w d into AD
+  auto node_rev = [&](Real tau, Real w) {
+    const Real h2 = Real(0.5) * tau * tau;
     Real dls[M], L[M], lds[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) {
       dls[q] = dl[q] + tau * Wt[q] + h2 * Wtt[q];
-      ADout[q] += wts[s] * dls[q];
-      L[q] = wts[s] * lAH[q];
-      lds[q] = wts[s] * lAD[q] + (s == 2 ? lAT[q] : Real(0));
+      ADout[q] += w * dls[q];
+      L[q] = w * lAH[q];
+      lds[q] = w * lAD[q];
     }
     normal_flux_delta_rev<EQ, Real>(P, base, dls, nx, ny, L, lds, lb);
 #pragma unroll
@@ -470,6 +469,24 @@ __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double d
       ldl[q] += lds[q];
       lWt[q] += tau * lds[q];
       lWtt[q] += h2 * lds[q];
+    }
+  };
+  if constexpr (TR == 1) {
+    node_rev(Real(kGaussLegendre2[0] * dt), Real(0.5));
+    node_rev(Real(kGaussLegendre2[1] * dt), Real(0.5));
+  } else {
+    node_rev(Real(0), Real(1.0 / 6.0));
+    node_rev(Real(0.5 * dt), Real(4.0 / 6.0));
+    node_rev(Real(dt), Real(1.0 / 6.0));
+  }
+  // the interface value AT = d(dt)
+  {
+    const Real T1 = Real(dt), h2 = Real(0.5 * dt * dt);
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      ldl[q] += lAT[q];
+      lWt[q] += T1 * lAT[q];
+      lWtt[q] += h2 * lAT[q];
     }
   }
   Real lD[6][M];

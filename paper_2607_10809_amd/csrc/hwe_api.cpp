@@ -83,6 +83,8 @@ hwe_status hwe_opts_default(hwe_opts* o) {
   o->lin_w[3] = 0.02;
   o->eps = 1e-8;
   o->device = 0;
+  o->time_rule = 0;
+  o->deriv_weight = 1.0;
   return HWE_OK;
 }
 
@@ -95,7 +97,8 @@ hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tr
   *out = nullptr;
   const hwe_opts& o = *opts;
   if (o.eq < HWE_ADVECTION || o.eq > HWE_EULER || o.bc < 0 || o.bc > 1 || o.prec < 0 || o.prec > 1 ||
-      o.positivity < 0 || o.positivity > 1 || (o.positivity && o.eq != HWE_EULER)) {
+      o.positivity < 0 || o.positivity > 1 || (o.positivity && o.eq != HWE_EULER) || o.time_rule < 0 ||
+      o.time_rule > 1 || !(o.deriv_weight > 0.0) || !(o.deriv_weight < 1e300)) {
     set_error("invalid option value");
     return HWE_EINVAL;
   }

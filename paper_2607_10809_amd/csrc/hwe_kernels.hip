@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
 // 4k + 2 side + g.  Every lane loads its side's cell, cell average and the
 // edge normal; the Gauss points are combined with quad_perm exchanges, then
 // the (side 0) lanes take the other side's sums and FP64 terms the same way.
-template <int EQ, class Real>
+template <int EQ, class Real, int TR>
 __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, double dt,
                                                        const double* __restrict__ wbar,
                                                        const Real* __restrict__ R,
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, do
 #pragma unroll
   for (int q = 0; q < M; ++q) Wb[q] = wbar[q * size_t(N) + cc];
   Real AH[M], AD[M], AT[M];
-  edge_lane<EQ, Real>(ec, cell, side, g, E, N, P, dt, Wb, Real(nx), Real(ny), R, egp, AH, AD, AT);
+  edge_lane<EQ, Real, TR>(ec, cell, side, g, E, N, P, dt, Wb, Real(nx), Real(ny), R, egp, AH, AD, AT);
   double Hb[M];
   const double lam = side_terms<EQ>(P, Wb, nx, ny, Hb);
   // Gauss points (weights 1/2 each): combine lanes g = 0, 1
@@ -317,8 +317,12 @@ hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, cons
   hipLaunchKernelGGL((recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * Mc)), dim3(kBlock), 0, st, N, NB, P, wbar_in, grad_in,
                      d.nbr, d.bnd_n, tbl, d.area, d.gpc, R);
   if (ev) hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL((edge_kernel<EQ, Real>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, P, dt,
-                     wbar_in, R, d.ecell, d.enl, egp, F, G);
+  if (P.time_rule == 1)
+    hipLaunchKernelGGL((edge_kernel<EQ, Real, 1>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, P, dt,
+                       wbar_in, R, d.ecell, d.enl, egp, F, G);
+  else
+    hipLaunchKernelGGL((edge_kernel<EQ, Real, 0>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, P, dt,
+                       wbar_in, R, d.ecell, d.enl, egp, F, G);
   if (ev) hipEventRecord(ev[2], st);
   hipLaunchKernelGGL((update_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, dt, wbar_in, d.nbr,
                      d.cell_edge, nl, d.inv_area, F, G, wbar_out, grad_out);
@@ -356,6 +360,7 @@ Params params_of(const hwe_opts& o) {
   for (int l = 0; l < 4; ++l) P.lw[l] = o.lin_w[l];
   P.eps = o.eps;
   P.linear = o.linear_weights ? 1 : 0;
+  P.time_rule = o.time_rule;
   return P;
 }
 

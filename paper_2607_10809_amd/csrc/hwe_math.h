@@ -63,6 +63,9 @@ template <int EQ> struct NComp {
   static constexpr int m = EQ == EQ_EUL ? 4 : 1;
 };
 
+// 2-point Gauss-Legendre nodes on [0, 1]: 1/2 -+ sqrt(3)/6
+constexpr double kGaussLegendre2[2] = {0.5 - 0.28867513459481288225, 0.5 + 0.28867513459481288225};
+
 struct Params {
   double ax, ay;   // advection velocity
   double gam;      // ratio of specific heats
@@ -70,6 +73,7 @@ struct Params {
   double eps;      // epsilon of the nonlinear weights
   int linear;      // 1: omega = gamma
   int positivity;  // 1: scaling limiter on the Euler reconstruction
+  int time_rule;   // 0: 3-point Gauss-Lobatto in time, 1: 2-point Gauss-Legendre
 };
 
 template <class T> struct SJ {  // spatial jet

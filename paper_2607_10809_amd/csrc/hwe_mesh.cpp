@@ -248,6 +248,7 @@ hwe_status fail(hwe_status s, const std::string& msg) {
 
 hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* tris, int64_t n_tris,
                            const hwe_opts& o, HostMesh& h) {
+  const double w2 = o.deriv_weight * o.deriv_weight;
   const bool periodic = o.bc == HWE_BC_PERIODIC;
   const double Lx = o.box[1] - o.box[0], Ly = o.box[3] - o.box[2];
   if (n_tris <= 0 || n_nodes <= 0) return fail(HWE_EINVAL, "empty mesh");
@@ -499,11 +500,14 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
       dm[f][1] = (gn.mxy - g0.mxy) / g0.A;
       dm[f][2] = (gn.myy - g0.myy) / g0.A;
       ar[f] = gn.A / g0.A;
-      // Step 2 data (unscaled: the printed rows mix units, so no rescaling)
+      // Step 2 data (unscaled: the printed rows mix units, so no rescaling).
+      // With the derivative rows weighted by w the normal equations are
+      // (d d^T + w^2 I)(b, c) = d dW + w^2 (V, Y), solved as
+      // (b, c) = (V, Y) + d (dW - d.(V, Y)) / (w^2 + d.d).
       double dd = draw[f][0] * draw[f][0] + draw[f][1] * draw[f][1];
       h.p2[(3 * f + 0) * N + i] = draw[f][0];
       h.p2[(3 * f + 1) * N + i] = draw[f][1];
-      h.p2[(3 * f + 2) * N + i] = 1.0 / (1.0 + dd);
+      h.p2[(3 * f + 2) * N + i] = 1.0 / (w2 + dd);
     }
     rmin = std::min(rmin, 2.0 * g0.A / per);
     double Ms[5][11];

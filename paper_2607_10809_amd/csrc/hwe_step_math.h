@@ -287,7 +287,8 @@ __host__ __device__ __forceinline__ void positivity_theta(double gam, const doub
 // d = W - Wbar (AD), and d at t_n + dt (AT).  cell < 0 (no cell on this side)
 // gives zeros.  (nx, ny): the edge's unit normal; egp: [8][E] Gauss-point
 // offsets from the centroids (side 0 points 0, 1; side 1 points 0, 1).
-template <int EQ, class Real>
+// TR: the time rule (0: 3-point Gauss-Lobatto, 1: 2-point Gauss-Legendre).
+template <int EQ, class Real, int TR>
 __host__ __device__ __forceinline__ void edge_lane(int e, int cell, int side, int g, int E, int N, const Params& P,
                                                   double dt, const double (&Wbd)[NComp<EQ>::m], Real nx, Real ny,
                                                   const Real* __restrict__ R, const Real* __restrict__ egp,
@@ -316,24 +317,37 @@ __host__ __device__ __forceinline__ void edge_lane(int e, int cell, int side, in
   Real Wt[M], Wtt[M];
   lax_wendroff<EQ, Real>(P, D, Wt, Wtt);
   const FluxBase<EQ, Real> base = flux_base<EQ, Real>(P, Wbd);
-  // Lobatto nodes 0, dt/2, dt with weights 1/6, 4/6, 1/6
-  const Real taus[3] = {Real(0), Real(0.5 * dt), Real(dt)};
-  const Real wts[3] = {Real(1.0 / 6.0), Real(4.0 / 6.0), Real(1.0 / 6.0)};
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const Real tau = taus[s], h2 = Real(0.5) * tau * tau;
-    Real dls[M], dH[M];
+  // one node of the time rule: Taylor value d(tau) = dl + tau W_t + tau^2/2 W_tt
+  // and the weighted sums of dH(tau) and d(tau)
+  auto node = [&](Real tau, Real w, Real (&dls)[M]) {
+    const Real h2 = Real(0.5) * tau * tau;
+    Real dH[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) dls[q] = dl[q] + tau * Wt[q] + h2 * Wtt[q];
     normal_flux_delta<EQ, Real>(P, base, dls, nx, ny, dH);
 #pragma unroll
     for (int q = 0; q < M; ++q) {
-      AH[q] += wts[s] * dH[q];
-      AD[q] += wts[s] * dls[q];
+      AH[q] += w * dH[q];
+      AD[q] += w * dls[q];
     }
-    if (s == 2)
+  };
+  Real d[M];
+  if constexpr (TR == 1) {
+    // 2-point Gauss-Legendre, nodes (1/2 -+ sqrt(3)/6) dt, weights 1/2; the
+    // interface value at dt is the Taylor polynomial there
+    node(Real(kGaussLegendre2[0] * dt), Real(0.5), d);
+    node(Real(kGaussLegendre2[1] * dt), Real(0.5), d);
+    const Real T1 = Real(dt), h2 = Real(0.5 * dt * dt);
 #pragma unroll
-      for (int q = 0; q < M; ++q) AT[q] = dls[q];
+    for (int q = 0; q < M; ++q) AT[q] = dl[q] + T1 * Wt[q] + h2 * Wtt[q];
+  } else {
+    // Gauss-Lobatto nodes 0, dt/2, dt with weights 1/6, 4/6, 1/6; the node at
+    // dt also gives the interface value
+    node(Real(0), Real(1.0 / 6.0), d);
+    node(Real(0.5 * dt), Real(4.0 / 6.0), d);
+    node(Real(dt), Real(1.0 / 6.0), d);
+#pragma unroll
+    for (int q = 0; q < M; ++q) AT[q] = d[q];
   }
 }
 

@@ -27,7 +27,7 @@ def _stream(stream=None):
 
 def make_opts(eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp64", adv=(1.0, 1.0),
               gas_gamma=1.4, lin_w=(0.94, 0.02, 0.02, 0.02), eps=1e-8, linear_weights=False, device=0,
-              positivity=False) -> HweOpts:
+              positivity=False, time_rule=0, deriv_weight=1.0) -> HweOpts:
     L = load_library()
     o = HweOpts()
     check(L.hwe_opts_default(C.byref(o)))
@@ -42,6 +42,8 @@ def make_opts(eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp
     o.eps = float(eps)
     o.device = int(device)
     o.positivity = 1 if positivity else 0
+    o.time_rule = int(time_rule)
+    o.deriv_weight = float(deriv_weight)
     return o
 
 

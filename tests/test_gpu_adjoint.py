@@ -71,6 +71,26 @@ def test_dot_product_against_oracle_jvp(case):
         assert abs(a - b) <= 1e-11 * scale
 
 
+@pytest.mark.parametrize("time_rule,wd", [(1, 1.0), (1, 0.3)])
+def test_dot_product_variants(time_rule, wd):
+    """The adjoint with the Gauss-Legendre time rule and weighted Step-2 rows."""
+    rng = np.random.default_rng(17)
+    wl = vortex_workload(n=24)
+    om = OracleMesh.from_workload(wl, time_rule=time_rule, deriv_weight=wd)
+    s0 = _perturbed(wl, rng)
+    dt = om.max_dt(s0, 0.3)
+    mesh = _mesh(wl, time_rule=time_rule, deriv_weight=wd)
+    for _ in range(2):
+        v = rng.normal(size=s0.shape)
+        lam = rng.normal(size=s0.shape)
+        _, jv = om.jvp(s0, v, dt, 1)
+        vj = _gpu_vjp(mesh, s0, lam, dt)
+        a, b = float(np.sum(vj * v)), float(np.sum(lam * jv))
+        scale = float(np.abs(vj * v).sum())
+        print(f"time rule {time_rule}, weight {wd}: <J^T l, v> = {a}, <l, J v> = {b}", flush=True)
+        assert abs(a - b) <= 1e-11 * scale
+
+
 def test_full_gradient_against_oracle_jacobian_tiny_mesh():
     """J^T lam of 3 steps on an 18-triangle vortex mesh, against the oracle's
     Jacobian built column by column from dual-number JVPs."""

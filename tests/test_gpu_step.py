@@ -278,6 +278,30 @@ def test_c4_riemann_limited_run_to_T(prec):
     assert np.isfinite(s).all()
 
 
+# ------------------------------------------------------------------ variants of the method
+@pytest.mark.parametrize("time_rule,wd", [(1, 1.0), (0, 0.3), (1, 0.3)])
+def test_time_rule_and_derivative_row_weight_variants(time_rule, wd):
+    """The 2-point Gauss-Legendre time rule and weighted Step-2 derivative rows,
+    against the oracle with the same options: vortex (20 steps, FP64 and mixed)
+    and smooth Burgers to T = 0.5/pi."""
+    wl = vortex_workload(n=40)
+    om = OracleMesh.from_workload(wl, time_rule=time_rule, deriv_weight=wd)
+    dt = om.max_dt(wl.state0, wl.cfl)
+    ref = om.run(wl.state0, dt, 20)
+    got = gpu_run(_mesh(wl, time_rule=time_rule, deriv_weight=wd), wl.state0, dt, 20)
+    gm = gpu_run(_mesh(wl, "mixed", time_rule=time_rule, deriv_weight=wd), wl.state0, dt, 20)
+    err, errm = rel_max(got, ref), rel_max(gm[:1], ref[:1])
+    wb = burgers_workload(n=40, T=0.5 / np.pi)
+    ob = OracleMesh.from_workload(wb, time_rule=time_rule, deriv_weight=wd)
+    dtb = ob.max_dt(wb.state0, wb.cfl)
+    refb = ob.run_to(wb.state0, wb.T, dtb)
+    gotb = gpu_run_to(_mesh(wb, time_rule=time_rule, deriv_weight=wd), wb.state0, wb.T, dtb)
+    errb = rel_max(gotb, refb)
+    _say(f"time rule {time_rule}, derivative-row weight {wd}: vortex fp64 {err:.2e} mixed {errm:.2e}; "
+         f"burgers fp64 {errb:.2e}")
+    assert err <= FP64_SMOOTH and errb <= FP64_SMOOTH and errm <= MIXED
+
+
 # ------------------------------------------------------------------ invariants / determinism
 def test_free_stream_mass_and_determinism(c3):
     import torch

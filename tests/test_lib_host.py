@@ -63,9 +63,12 @@ def test_error_statuses():
         Mesh(mesh.nodes, np.vstack([mesh.tris, mesh.tris[:1]]), eq="burgers", bc="transmissive", box=box,
              device=-1)
     assert e.value.status == -2
-    with pytest.raises(HweError) as e:       # bad options
-        Mesh(mesh.nodes, mesh.tris, eq="euler", bc="transmissive", box=box, device=-1, gas_gamma=0.5)
-    assert e.value.status == -1
+    for bad_opts in (dict(eq="euler", gas_gamma=0.5), dict(eq="burgers", time_rule=2),
+                     dict(eq="burgers", deriv_weight=0.0), dict(eq="burgers", deriv_weight=float("nan")),
+                     dict(eq="burgers", positivity=True)):
+        with pytest.raises(HweError) as e:   # bad options
+            Mesh(mesh.nodes, mesh.tris, bc="transmissive", box=box, device=-1, **bad_opts)
+        assert e.value.status == -1, bad_opts
     m = Mesh(mesh.nodes, mesh.tris, eq="burgers", bc="transmissive", box=box, device=-1)
     from paper_2607_10809_amd import _lib
     L = _lib.load_library()

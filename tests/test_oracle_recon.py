@@ -113,10 +113,12 @@ def _stencil_vertices(om, k):
     return cells, [k] + list(g["nbr"][k])
 
 
-def test_least_squares_against_brute_force_nullspace_solution():
+@pytest.mark.parametrize("wd", [1.0, 0.35])
+def test_least_squares_against_brute_force_nullspace_solution(wd):
+    """wd: weight of the Step-2 derivative rows (1 = as printed)."""
     box = (0.0, 3.0, 0.0, 3.0)
     mesh = split_square_mesh(6, box, jitter=0.3, seed=4, periodic=True)
-    om = OracleMesh(mesh.nodes, mesh.tris, eq=1, bc=0, box=box)
+    om = OracleMesh(mesh.nodes, mesh.tris, eq=1, bc=0, box=box, deriv_weight=wd)
     rng = np.random.default_rng(0)
     s = np.empty((3, 1, om.N))
     s[0, 0] = rng.uniform(0.5, 1.5, om.N)
@@ -151,8 +153,8 @@ def test_least_squares_against_brute_force_nullspace_solution():
         # Step 2: the K0 average exactly; K_l average and derivative averages in LS
         for l in range(1, 4):
             C2 = np.array([[_tri_quad(cells[0], fj) for fj in mon[:3]]])
-            A2 = np.array([[_tri_quad(cells[l], fj) for fj in mon[:3]], [0, 1, 0], [0, 0, 1]])
-            b2 = np.array([s[0, 0, ids[l]], s[1, 0, ids[l]], s[2, 0, ids[l]]])
+            A2 = np.array([[_tri_quad(cells[l], fj) for fj in mon[:3]], [0, wd, 0], [0, 0, wd]])
+            b2 = np.array([s[0, 0, ids[l]], wd * s[1, 0, ids[l]], wd * s[2, 0, ids[l]]])
             xp = np.linalg.lstsq(C2, [s[0, 0, k]], rcond=None)[0]
             Z = sla.null_space(C2)
             y = np.linalg.lstsq(A2 @ Z, b2 - A2 @ xp, rcond=None)[0]

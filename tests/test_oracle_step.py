@@ -63,10 +63,13 @@ def _deep_interior(om, layers=2):
     return np.nonzero(ok)[0]
 
 
-def test_one_advection_step_is_exact_on_quadratics_with_linear_weights():
+@pytest.mark.parametrize("time_rule", [0, 1])
+def test_one_advection_step_is_exact_on_quadratics_with_linear_weights(time_rule):
+    """Either time rule integrates the quadratic-in-time linear flux exactly."""
     box = (0.0, 1.0, 0.0, 1.0)
     mesh = split_square_mesh(8, box, jitter=0.25, seed=12, periodic=False)
-    om = OracleMesh(mesh.nodes, mesh.tris, eq=0, bc=1, box=box, adv=(0.7, -0.4), linear_only=1)
+    om = OracleMesh(mesh.nodes, mesh.tris, eq=0, bc=1, box=box, adv=(0.7, -0.4), linear_only=1,
+                    time_rule=time_rule)
     q = lambda x, y: 0.4 - 1.3 * x + 0.6 * y + 0.8 * x * x - 0.5 * x * y + 1.1 * y * y
     f = lambda x, y, t: q(x - 0.7 * t, y + 0.4 * t)[..., None]
     s0 = cell_average_states(mesh, f, 0.0)
@@ -79,10 +82,12 @@ def test_one_advection_step_is_exact_on_quadratics_with_linear_weights():
     assert err[0] < 1e-14 and err[1] < 1e-12 and err[2] < 1e-12, err
 
 
-def test_one_step_is_exact_on_linear_data_with_nonlinear_weights():
+@pytest.mark.parametrize("time_rule,wd", [(0, 1.0), (1, 0.4)])
+def test_one_step_is_exact_on_linear_data_with_nonlinear_weights(time_rule, wd):
     box = (0.0, 1.0, 0.0, 1.0)
     mesh = split_square_mesh(8, box, jitter=0.25, seed=13, periodic=False)
-    om = OracleMesh(mesh.nodes, mesh.tris, eq=0, bc=1, box=box, adv=(1.0, 1.0))
+    om = OracleMesh(mesh.nodes, mesh.tris, eq=0, bc=1, box=box, adv=(1.0, 1.0), time_rule=time_rule,
+                    deriv_weight=wd)
     f = lambda x, y, t: (2.0 + 0.9 * (x - t) - 0.3 * (y - t))[..., None]
     s0 = cell_average_states(mesh, f, 0.0)
     dt = 0.02
@@ -139,12 +144,14 @@ def test_convergence_linear_advection():
     assert o[-1] > 2.6, (errs, o)
 
 
-def test_convergence_burgers_paper_example_4_1():
-    """Example 4.1: u0 = 0.5 + sin(pi(x+y)/2) on (-2,2)^2, T = 0.5/pi (smooth)."""
+@pytest.mark.parametrize("time_rule", [0, 1])
+def test_convergence_burgers_paper_example_4_1(time_rule):
+    """Example 4.1: u0 = 0.5 + sin(pi(x+y)/2) on (-2,2)^2, T = 0.5/pi (smooth);
+    third order with either time rule."""
     errs = []
     for n in (10, 20, 40):
         wl = burgers_workload(n=n, box=(-2.0, 2.0, -2.0, 2.0), jitter=0.1)
-        om = OracleMesh.from_workload(wl)
+        om = OracleMesh.from_workload(wl, time_rule=time_rule)
         dt = om.max_dt(wl.state0, 0.3)
         s = om.run_to(wl.state0, wl.T, dt)
         errs.append(_l1(s[0, 0], wl.exact_state(wl.T)[0, 0], om.geometry()["area"]))
@@ -162,6 +169,23 @@ def test_convergence_euler_density_wave_paper_example_4_2():
         errs.append(_l1(s[0, 0], wl.exact_state(wl.T)[0, 0], om.geometry()["area"]))
     o = _orders(errs)
     assert (o > 2.6).all(), (errs, o)
+
+
+def test_time_rules_differ_only_at_fifth_order_in_dt():
+    """Burgers: the flux is quartic in time along the Taylor polynomial, which
+    neither 3-point Gauss-Lobatto (error dt^5/120 on tau^4) nor 2-point
+    Gauss-Legendre (-dt^5/180) integrates exactly: the two one-step results
+    differ, by an amount that falls as dt^5 (local error per unit time dt^4,
+    times dt for one step)."""
+    wl = burgers_workload(n=12, box=(-2.0, 2.0, -2.0, 2.0), jitter=0.1)
+    oa = OracleMesh.from_workload(wl, time_rule=0)
+    ob = OracleMesh.from_workload(wl, time_rule=1)
+    d = []
+    for dt in (0.02, 0.01):
+        a, b = oa.step(wl.state0, dt), ob.step(wl.state0, dt)
+        d.append(np.abs(a[0] - b[0]).max())
+    assert d[0] > 0 and d[1] > 0
+    assert 20 < d[0] / d[1] < 50, d                   # ~2^5
 
 
 @pytest.mark.parametrize("eq", [0, 1, 2])
