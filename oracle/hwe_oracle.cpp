@@ -26,7 +26,8 @@
 //   systems: component-wise reconstruction of the conservative variables;
 //   periodic boundaries by exact translation across seams; transmissive
 //   boundaries by a mirrored ghost cell for the stencil and W_ext := W_int
-//   at boundary Gauss points; kappa/D := 0 when kappa == 0.
+//   at boundary Gauss points; reflective walls (Euler) likewise with the
+//   momentum reflected in the ghost and in W_ext; kappa/D := 0 when kappa == 0.
 //   Non-smooth points for derivatives: d|x| = sign(x) dx with sign(0) = 0;
 //   max(a, b) takes a (the edge's first cell, the one with the lower caller
 //   index) on ties.
@@ -133,6 +134,8 @@ struct Opts {
   int positivity;   // 1: scaling limiter on the reconstruction (Euler)
   int time_rule;    // 0: 3-point Gauss-Lobatto, 1: 2-point Gauss-Legendre
   double deriv_weight;  // weight of the derivative rows in the Step-2 least squares (1: as printed)
+  int walls;        // Euler, non-periodic: bit s set = boundary faces on box side s (x0, x1, y0, y1) are
+                    // reflective walls; the others are transmissive
 };
 
 inline int ncomp(int eq) { return eq == 2 ? 4 : 1; }
@@ -185,13 +188,35 @@ inline double tri_area(const Tri& t) {
 }
 
 struct Face {
-  int nb;         // neighbour cell, or -1 on a transmissive boundary
+  int nb;         // neighbour cell, or -1 on a boundary
+  bool wall;      // boundary face on a reflective wall
   int nb_face;    // neighbour's face index
   double sx, sy;  // translation mapping the neighbour's frame into this cell's frame
   double nx, ny;  // outward unit normal of this cell
   double len;
   Tri ghost;      // mirrored cell when nb == -1
 };
+
+// Reflection of the momentum components (Euler, components 1 and 2) across a
+// line with unit normal n: m -> m - 2 (m.n) n, applied to the averages W and,
+// row by row, to the derivative averages (V, Y) (the rows mix, the columns are
+// reflected by the caller).
+template <class T> void reflect_momentum(double nx, double ny, T* W, T* V, T* Y) {
+  T mn = W[1] * T(nx) + W[2] * T(ny);
+  W[1] = W[1] - T(2.0 * nx) * mn;
+  W[2] = W[2] - T(2.0 * ny) * mn;
+  T vn = V[1] * T(nx) + V[2] * T(ny);
+  V[1] = V[1] - T(2.0 * nx) * vn;
+  V[2] = V[2] - T(2.0 * ny) * vn;
+  T yn = Y[1] * T(nx) + Y[2] * T(ny);
+  Y[1] = Y[1] - T(2.0 * nx) * yn;
+  Y[2] = Y[2] - T(2.0 * ny) * yn;
+}
+template <class T> void reflect_momentum(double nx, double ny, T* W) {
+  T mn = W[1] * T(nx) + W[2] * T(ny);
+  W[1] = W[1] - T(2.0 * nx) * mn;
+  W[2] = W[2] - T(2.0 * ny) * mn;
+}
 
 struct Mesh {
   Opts o;
@@ -330,7 +355,10 @@ void stencil_of(const Mesh& M, const T* s, int64_t k, StencilCell<T> st[4]) {
         c.Y[q] = s[(2 * m + q) * N + F.nb];
       }
     } else {
-      // transmissive boundary: K0 mirrored across the face, state mirrored too
+      // boundary: K0 mirrored across the face, state mirrored too.  The ghost
+      // field is W_g(x) = S W(Mx) with M the reflection across the face line
+      // (so its gradient is S grad W M); S = I on a transmissive boundary, and
+      // on a wall S reflects the momentum vector by M as well.
       c.t = F.ghost;
       c.area = M.area[k];
       for (int q = 0; q < m; ++q) {
@@ -339,6 +367,7 @@ void stencil_of(const Mesh& M, const T* s, int64_t k, StencilCell<T> st[4]) {
         c.V[q] = st[0].V[q] - T(2.0 * F.nx) * vn;
         c.Y[q] = st[0].Y[q] - T(2.0 * F.ny) * vn;
       }
+      if (F.wall) reflect_momentum(F.nx, F.ny, c.W, c.V, c.Y);
     }
   }
 }
@@ -636,6 +665,14 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
       T aK = spectral_radius(o, Wbar, F.nx, F.ny);
       T aN = spectral_radius(o, Wbn, F.nx, F.ny);
       alpha = k < F.nb ? maxfirst(aK, aN) : maxfirst(aN, aK);
+    } else if (F.wall) {
+      // the ghost average is the reflected cell average: the same spectral radius
+      T Wg[4];
+      for (int q = 0; q < m; ++q) Wg[q] = Wbar[q];
+      reflect_momentum(F.nx, F.ny, Wg);
+      T aK = spectral_radius(o, Wbar, F.nx, F.ny);
+      T aG = spectral_radius(o, Wg, F.nx, F.ny);
+      alpha = maxfirst(aK, aG);
     }
     for (int G = 0; G < 2; ++G) {
       double xg = t.x[f] + kGaussS[G] * (t.x[f1] - t.x[f]);
@@ -655,11 +692,13 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
       lax_wendroff(o, m, Di, it, itx, ity, itt);
       if (F.nb >= 0) lax_wendroff(o, m, De, et, etx, ety, ett);
       // Taylor polynomials in time, eq. (tay), of the interior and exterior values
+      // (boundary: W_ext = W_int on a transmissive face, the reflected W_int on a wall)
       auto taylor = [&](double tau, T Wi[4], T We[4]) {
         for (int q = 0; q < m; ++q) {
           Wi[q] = Di[0][q] + T(tau) * it[q] + T(0.5 * tau * tau) * itt[q];
           We[q] = F.nb >= 0 ? De[0][q] + T(tau) * et[q] + T(0.5 * tau * tau) * ett[q] : Wi[q];
         }
+        if (F.nb < 0 && F.wall) reflect_momentum(F.nx, F.ny, We);
       };
       const TimeRule& rule = kTimeRules[o.time_rule == 1 ? 1 : 0];
       for (int sN = 0; sN < rule.n; ++sN) {
@@ -818,6 +857,18 @@ int build_mesh(Mesh& M, const double* nodes, int64_t nn, const int32_t* tris, in
         F.nb = -1;
         F.nb_face = -1;
         F.sx = F.sy = 0.0;
+        // on a wall: the face lies on a box side whose bit is set in o.walls
+        {
+          const double mx = 0.5 * (t.x[f] + t.x[f1]), my = 0.5 * (t.y[f] + t.y[f1]);
+          const double tol = 1e-9 * std::max(Lx, Ly);
+          const bool on[4] = {std::fabs(mx - o.box[0]) < tol && std::fabs(ex) < tol,
+                              std::fabs(mx - o.box[1]) < tol && std::fabs(ex) < tol,
+                              std::fabs(my - o.box[2]) < tol && std::fabs(ey) < tol,
+                              std::fabs(my - o.box[3]) < tol && std::fabs(ey) < tol};
+          F.wall = false;
+          for (int sd = 0; sd < 4; ++sd)
+            if (on[sd] && ((o.walls >> sd) & 1)) F.wall = true;
+        }
         // mirror image of K across the face line
         for (int v = 0; v < 3; ++v) {
           double rx = t.x[v] - t.x[f], ry = t.y[v] - t.y[f];
@@ -831,6 +882,7 @@ int build_mesh(Mesh& M, const double* nodes, int64_t nn, const int32_t* tris, in
         continue;
       }
       auto other = lst[0].first == k && lst[0].second == f ? lst[1] : lst[0];
+      F.wall = false;
       F.nb = static_cast<int>(other.first);
       F.nb_face = other.second;
       // translation from the neighbour's frame: compare the shared vertices
@@ -867,6 +919,7 @@ struct or_opts {
   int positivity;
   int time_rule;
   double deriv_weight;
+  int walls;
 };
 
 void* or_mesh_new(const double* nodes, int64_t nn, const int32_t* tris, int64_t nt, const or_opts* o,
@@ -884,6 +937,7 @@ void* or_mesh_new(const double* nodes, int64_t nn, const int32_t* tris, int64_t 
   M->o.positivity = o->positivity;
   M->o.time_rule = o->time_rule;
   M->o.deriv_weight = o->deriv_weight;
+  M->o.walls = (o->eq == 2 && o->bc != 0) ? o->walls : 0;
   int st = build_mesh(*M, nodes, nn, tris, nt);
   if (status) *status = st;
   if (st != 0) {

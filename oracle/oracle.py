@@ -12,14 +12,14 @@ _SRC = os.path.join(_HERE, "hwe_oracle.cpp")
 _LIB = os.path.join(_HERE, "libhwe_oracle.so")
 
 OPTS_DEFAULT = dict(adv=(1.0, 1.0), gas_gamma=1.4, lin_w=(0.94, 0.02, 0.02, 0.02), eps=1e-8,
-                    linear_only=0, positivity=0, time_rule=0, deriv_weight=1.0)
+                    linear_only=0, positivity=0, time_rule=0, deriv_weight=1.0, walls=0)
 
 
 class _Opts(C.Structure):
     _fields_ = [("eq", C.c_int), ("bc", C.c_int), ("box", C.c_double * 4), ("adv", C.c_double * 2),
                 ("gas_gamma", C.c_double), ("lin_w", C.c_double * 4), ("eps", C.c_double),
                 ("linear_only", C.c_int), ("positivity", C.c_int), ("time_rule", C.c_int),
-                ("deriv_weight", C.c_double)]
+                ("deriv_weight", C.c_double), ("walls", C.c_int)]
 
 
 def build_oracle(force: bool = True) -> str:
@@ -85,6 +85,7 @@ def _opts(eq, bc=0, box=(0.0, 1.0, 0.0, 1.0), **kw):
     s.positivity = int(o["positivity"])
     s.time_rule = int(o["time_rule"])
     s.deriv_weight = float(o["deriv_weight"])
+    s.walls = int(o["walls"])
     return s
 
 
@@ -114,6 +115,8 @@ class OracleMesh:
 
     @classmethod
     def from_workload(cls, wl, **kw):
+        if getattr(wl, "walls", 0) and "walls" not in kw:
+            kw["walls"] = wl.walls
         return cls(wl.mesh.nodes, wl.mesh.tris, wl.eq, wl.bc, wl.mesh.box, adv=wl.adv, **kw)
 
     def __del__(self):

@@ -15,6 +15,8 @@ Conventions
   triangles reference nodes modulo n.  Coordinates lie in [x0, x1) x [y0, y1);
   a triangle that straddles a seam is unwrapped by the consumer.
 * Non-periodic meshes have (n+1) x (n+1) nodes.
+* Rectangular meshes (n = (nx, ny)) follow the same rules with nx squares
+  along x and ny along y.
 * Jitter: nodes strictly inside the box get an independent uniform offset in
   [-f*h, f*h] per coordinate, drawn from ``numpy.random.default_rng(seed)`` as
   one array of shape (rows, cols, 2) in row-major node order; nodes on the box
@@ -41,42 +43,45 @@ class Mesh2D:
         return int(self.tris.shape[0])
 
 
-def split_square_mesh(n: int, box=(0.0, 1.0, 0.0, 1.0), jitter: float = 0.0,
+def split_square_mesh(n, box=(0.0, 1.0, 0.0, 1.0), jitter: float = 0.0,
                       seed: int | None = None, periodic: bool = True) -> Mesh2D:
-    """Return an n x n split-square mesh of ``box`` (2 n^2 triangles)."""
-    if n < 3:
+    """Return an n x n split-square mesh of ``box`` (2 n^2 triangles); ``n`` may
+    also be a pair (nx, ny) of squares along x and y (2 nx ny triangles)."""
+    nx, ny = (n, n) if np.isscalar(n) else (int(n[0]), int(n[1]))
+    if nx < 3 or ny < 3:
         raise ValueError("need at least 3 squares per side")
     x0, x1, y0, y1 = map(float, box)
-    hx = (x1 - x0) / n
-    hy = (y1 - y0) / n
-    nn = n if periodic else n + 1
-    jj, ii = np.meshgrid(np.arange(nn), np.arange(nn), indexing="ij")
+    hx = (x1 - x0) / nx
+    hy = (y1 - y0) / ny
+    mx = nx if periodic else nx + 1     # node columns
+    my = ny if periodic else ny + 1     # node rows
+    jj, ii = np.meshgrid(np.arange(my), np.arange(mx), indexing="ij")
     xs = x0 + ii * hx
     ys = y0 + jj * hy
     if jitter and jitter > 0.0:
         rng = np.random.default_rng(seed)
-        off = rng.uniform(-1.0, 1.0, size=(nn, nn, 2))
-        inner = (ii >= 1) & (ii <= n - 1) & (jj >= 1) & (jj <= n - 1)
+        off = rng.uniform(-1.0, 1.0, size=(my, mx, 2))
+        inner = (ii >= 1) & (ii <= nx - 1) & (jj >= 1) & (jj <= ny - 1)
         xs = xs + np.where(inner, off[..., 0] * jitter * hx, 0.0)
         ys = ys + np.where(inner, off[..., 1] * jitter * hy, 0.0)
     nodes = np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.float64)
 
     def nid(i, j):
         if periodic:
-            return (j % n) * n + (i % n)
-        return j * (n + 1) + i
+            return (j % ny) * nx + (i % nx)
+        return j * (nx + 1) + i
 
-    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    J, I = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
     I = I.ravel()
     J = J.ravel()
     a = nid(I, J)
     b = nid(I + 1, J)
     c = nid(I + 1, J + 1)
     d = nid(I, J + 1)
-    tris = np.empty((2 * n * n, 3), dtype=np.int32)
+    tris = np.empty((2 * nx * ny, 3), dtype=np.int32)
     tris[0::2] = np.stack([a, b, c], axis=1)
     tris[1::2] = np.stack([a, c, d], axis=1)
-    return Mesh2D(nodes=nodes, tris=tris, box=(x0, x1, y0, y1), periodic=periodic, n=n, h=hx)
+    return Mesh2D(nodes=nodes, tris=tris, box=(x0, x1, y0, y1), periodic=periodic, n=nx, h=hx)
 
 
 def unwrapped_triangles(mesh: Mesh2D) -> np.ndarray:

@@ -260,6 +260,7 @@ class Workload:
     exact: Callable | None = None       # f(x, y, t) -> (..., m), or None
     adv: tuple = (1.0, 1.0)
     extra: dict = field(default_factory=dict)
+    walls: int = 0                      # bit s: box side s (x0, x1, y0, y1) is a reflective wall
 
     @property
     def bc(self) -> int:
@@ -304,6 +305,57 @@ def riemann_workload(n=700, jitter=0.2, seed=4, T=0.3, cfl=0.3):
     """Four-quadrant Euler Riemann problem on [0,1]^2 with transmissive boundaries."""
     mesh = split_square_mesh(n, (0.0, 1.0, 0.0, 1.0), jitter, seed, periodic=False)
     return Workload("riemann", EQ_EULER, 4, mesh, riemann_average_states(mesh), T, cfl, None)
+
+
+def shock_tube_average_states(mesh: Mesh2D, x_split, left, right) -> np.ndarray:
+    """Exact [3][4][N] averages of piecewise-constant data that depend on x only:
+    primitive states left = (rho, u, v, p) for x < x_split, right beyond."""
+    P = unwrapped_triangles(mesh)
+    N = P.shape[0]
+    WL = _prim_to_cons(*map(np.float64, left))
+    WR = _prim_to_cons(*map(np.float64, right))
+    out = np.zeros((3, 4, N))
+    cen = P.mean(axis=1)
+    out[0] = np.where(cen[:, 0][None, :] >= x_split, WR[:, None], WL[:, None])
+    straddle = (P[:, :, 0].min(1) < x_split) & (P[:, :, 0].max(1) > x_split)
+    for c in np.nonzero(straddle)[0]:
+        tri = [tuple(P[c, k]) for k in range(3)]
+        area = _poly_area(tri)
+        aR = _poly_area(_clip(tri, 0, x_split, True))
+        out[0, :, c] = (aR * WR + (area - aR) * WL) / area
+        # derivative averages by the divergence theorem: the x-derivative of a
+        # step is the jump times the length of the step line inside the cell
+        pts = []
+        for k in range(3):
+            A, B = np.array(tri[k]), np.array(tri[(k + 1) % 3])
+            if (A[0] - x_split) * (B[0] - x_split) < 0:
+                s = (x_split - A[0]) / (B[0] - A[0])
+                pts.append(A[1] + s * (B[1] - A[1]))
+        length = abs(pts[1] - pts[0]) if len(pts) == 2 else 0.0
+        out[1, :, c] = (WR - WL) * length / area
+        out[2, :, c] = 0.0
+    return out
+
+
+# Shock tubes on a strip with reflective walls at y = y0, y1 (a 1-D Riemann
+# problem in 2-D, so that the exact solution is the 1-D one): the Lax problem
+# of Sec. 4 (states (rho, u, p) = (0.445, 0.698, 3.528) | (0.5, 0, 0.571) split
+# at x = 0, T = 0.16) and Sod's problem ((1, 0, 1) | (0.125, 0, 0.1), T = 0.2).
+SHOCK_TUBES = {
+    "lax": ((0.445, 0.698, 0.0, 3.528), (0.5, 0.0, 0.0, 0.571), 0.16),
+    "sod": ((1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.1), 0.2),
+}
+
+
+def shock_tube_workload(name="lax", nx=200, height=0.06, jitter=0.1, seed=8, cfl=0.3):
+    """A shock tube on (-0.5, 0.5) x (-height/2, height/2): nx x ny squares of side
+    1/nx, transmissive ends, reflective walls on the long sides."""
+    left, right, T = SHOCK_TUBES[name]
+    ny = max(3, int(round(height * nx)))
+    box = (-0.5, 0.5, -0.5 * ny / nx, 0.5 * ny / nx)
+    mesh = split_square_mesh((nx, ny), box, jitter, seed, periodic=False)
+    return Workload(name, EQ_EULER, 4, mesh, shock_tube_average_states(mesh, 0.0, left, right), T, cfl, None,
+                    extra=dict(left=left, right=right, x_split=0.0), walls=0b1100)
 
 
 def perturbed_vortex_target_center(seed=5, sigma=0.3, base=(5.0, 5.0)):
