@@ -86,6 +86,16 @@ typedef struct {
   double deriv_weight;    /* weight w > 0 of the two derivative rows in the
                              Step-2 least squares of Sec. 2.2 (the linear
                              candidates); 1 = the rows as printed (default) */
+  int32_t walls;          /* HWE_EULER with HWE_BC_TRANSMISSIVE only: bit s set
+                             (s = 0: x = x0, 1: x = x1, 2: y = y0, 3: y = y1)
+                             makes the boundary faces lying on that side of the
+                             box reflective walls: the ghost cell is the mirror
+                             image of the cell with its momentum reflected, and
+                             the exterior value at a wall Gauss point is the
+                             interior value with its momentum reflected.  Other
+                             boundary faces stay transmissive.  0 = no walls
+                             (default).  hwe_step_adjoint rejects meshes with
+                             walls */
 } hwe_opts;
 
 /* Fill *o with the paper's defaults: linear weights 0.94/0.02/0.02/0.02

@@ -19,7 +19,8 @@ class HweOpts(C.Structure):
     _fields_ = [("eq", C.c_int32), ("bc", C.c_int32), ("prec", C.c_int32), ("linear_weights", C.c_int32),
                 ("box", C.c_double * 4), ("adv", C.c_double * 2), ("gas_gamma", C.c_double),
                 ("lin_w", C.c_double * 4), ("eps", C.c_double), ("device", C.c_int32),
-                ("positivity", C.c_int32), ("time_rule", C.c_int32), ("deriv_weight", C.c_double)]
+                ("positivity", C.c_int32), ("time_rule", C.c_int32), ("deriv_weight", C.c_double),
+                ("walls", C.c_int32)]
 
 
 class HweError(RuntimeError):

@@ -85,6 +85,7 @@ hwe_status hwe_opts_default(hwe_opts* o) {
   o->device = 0;
   o->time_rule = 0;
   o->deriv_weight = 1.0;
+  o->walls = 0;
   return HWE_OK;
 }
 
@@ -98,7 +99,8 @@ hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tr
   const hwe_opts& o = *opts;
   if (o.eq < HWE_ADVECTION || o.eq > HWE_EULER || o.bc < 0 || o.bc > 1 || o.prec < 0 || o.prec > 1 ||
       o.positivity < 0 || o.positivity > 1 || (o.positivity && o.eq != HWE_EULER) || o.time_rule < 0 ||
-      o.time_rule > 1 || !(o.deriv_weight > 0.0) || !(o.deriv_weight < 1e300)) {
+      o.time_rule > 1 || !(o.deriv_weight > 0.0) || !(o.deriv_weight < 1e300) || o.walls < 0 || o.walls > 15 ||
+      (o.walls && (o.eq != HWE_EULER || o.bc != HWE_BC_TRANSMISSIVE))) {
     set_error("invalid option value");
     return HWE_EINVAL;
   }
@@ -207,6 +209,10 @@ hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n
     }
   if (overlaps(lam_wbar_n, wb, lam_grad_n, gb)) {
     set_error("output buffers overlap each other");
+    return HWE_EINVAL;
+  }
+  if (m->opts.walls) {
+    set_error("hwe_step_adjoint: meshes with reflective walls are not differentiated");
     return HWE_EINVAL;
   }
   if (m->opts.positivity) {

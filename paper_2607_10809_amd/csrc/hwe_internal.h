@@ -30,7 +30,7 @@ struct HostMesh {
   std::vector<double> mom;         // [3][N] central second moments Mxx, Mxy, Myy
   std::vector<int32_t> nbr;        // [3][N] neighbour across face f; -(b+1) for boundary face b
   std::vector<int32_t> nbr_back;   // [3][N] the neighbour's face index that points back (-1 on boundary)
-  std::vector<double> bnd_n;       // [2][NB] outward unit normal of boundary face b
+  std::vector<double> bnd_n;       // [3][NB] outward unit normal of boundary face b, then 1 on a wall (else 0)
   std::vector<double> p1;          // [55][N] Step-1 map (row-major 5 x 11 per cell)
   std::vector<double> p2;          // [9][N] Step-2 data
   std::vector<int32_t> cell_edge;  // [3][N] (edge << 1) | (cell is the edge's second cell)

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
     __syncthreads();
     const Real* tb = reinterpret_cast<const Real*>(stage) + (i % kTile);
     Real a[6];
-    recon_from_stencil<EQ, Real>(ic, NB, P, S, bnd_n, tb, area, a);
+    recon_from_stencil<EQ, Real>(ic, q, N, NB, P, S, bnd_n, tb, area, wbar, grad, a);
     if (P.positivity) {
       const int lane0 = (threadIdx.x & 63) & ~3;
       Real all[4][6];
@@ -111,6 +111,7 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
 // 4k + 2 side + g.  Every lane loads its side's cell, cell average and the
 // edge normal; the Gauss points are combined with quad_perm exchanges, then
 // the (side 0) lanes take the other side's sums and FP64 terms the same way.
+// On a reflective wall the second side is the first one's mirror image.
 template <int EQ, class Real, int TR>
 __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, double dt,
                                                        const double* __restrict__ wbar,
@@ -124,14 +125,47 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, do
   const int e = gid >> 2, side = (gid >> 1) & 1, g = gid & 1;
   const bool valid = e < E;
   const int ec = valid ? e : E - 1;
+  // second cell: -1 on a transmissive boundary, -2 on a reflective wall; a
+  // lane without a cell reads the edge's first cell
   const int cell = valid ? ecell[side * E + ec] : -1;
-  const int cc = cell >= 0 ? cell : 0;
+  const int cc = cell >= 0 ? cell : ecell[ec];
   const double nx = enl[ec], ny = enl[E + ec], len = enl[2 * E + ec];
   double Wb[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) Wb[q] = wbar[q * size_t(N) + cc];
+  Real dl[M], Wt[M], Wtt[M];
+  edge_point<EQ, Real>(ec, cell, side, g, E, P, Wb, R, egp, dl, Wt, Wtt);
+  const bool wall = cell == -2;
+  if constexpr (EQ == EQ_EUL) {
+    // the exterior of a wall is the interior with its momentum reflected: the
+    // wall lane takes the first side's point values from its quad partner
+    if (__ballot(wall) != 0) {  // uniform over the wave
+      Real pdl[M], pWt[M], pWtt[M];
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        pdl[q] = quad_perm<kQuadXor2>(dl[q]);
+        pWt[q] = quad_perm<kQuadXor2>(Wt[q]);
+        pWtt[q] = quad_perm<kQuadXor2>(Wtt[q]);
+      }
+      if (wall) {
+        const Real rx = Real(nx), ry = Real(ny);
+        reflect_momentum(rx, ry, pdl);
+        reflect_momentum(rx, ry, pWt);
+        reflect_momentum(rx, ry, pWtt);
+        reflect_momentum(nx, ny, Wb);
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          dl[q] = pdl[q];
+          Wt[q] = pWt[q];
+          Wtt[q] = pWtt[q];
+        }
+      }
+    }
+  }
   Real AH[M], AD[M], AT[M];
-  edge_lane<EQ, Real, TR>(ec, cell, side, g, E, N, P, dt, Wb, Real(nx), Real(ny), R, egp, AH, AD, AT);
+#pragma unroll
+  for (int q = 0; q < M; ++q) AH[q] = AD[q] = AT[q] = Real(0);
+  if (cell >= 0 || wall) edge_nodes<EQ, Real, TR>(P, dt, Wb, Real(nx), Real(ny), dl, Wt, Wtt, AH, AD, AT);
   double Hb[M];
   const double lam = side_terms<EQ>(P, Wb, nx, ny, Hb);
   // Gauss points (weights 1/2 each): combine lanes g = 0, 1
@@ -153,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, do
     Ho[q] = quad_perm<kQuadXor2>(Hb[q]);
   }
   const double lo = quad_perm<kQuadXor2>(lam);
-  const bool second = quad_perm<kQuadXor2>(cell) >= 0;
+  const bool second = quad_perm<kQuadXor2>(cell) != -1;  // a cell or a wall on the other side
   if (!valid || side != 0) return;
   if (g == 0)
     edge_flux<EQ, Real>(e, E, len, second, Wb, Hb, lam, Wo, Ho, lo, AH, AD, OH, OD, F);
@@ -162,7 +196,9 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, do
 }
 
 template <int EQ, class Real>
-__global__ __launch_bounds__(kBlock) void update_kernel(int N, int E, double dt, const double* __restrict__ wbar,
+__global__ __launch_bounds__(kBlock) void update_kernel(int N, int E, int NB, double dt,
+                                                         const double* __restrict__ wbar,
+                                                         const double* __restrict__ bnd_n,
                                                          const int32_t* __restrict__ nbr,
                                                          const int32_t* __restrict__ cell_edge,
                                                          const Real* __restrict__ nl,
@@ -171,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(int N, int E, double dt,
                                                          double* __restrict__ wout, Real* __restrict__ gout) {
   const int i = xcd_block_id() * kBlock + threadIdx.x;
   if (i >= N) return;
-  update_point<EQ, Real>(i, N, E, dt, wbar, nbr, cell_edge, nl, inv_area, F, G, wout, gout);
+  update_point<EQ, Real>(i, N, E, NB, dt, wbar, bnd_n, nbr, cell_edge, nl, inv_area, F, G, wout, gout);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -324,8 +360,8 @@ hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, cons
     hipLaunchKernelGGL((edge_kernel<EQ, Real, 0>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, P, dt,
                        wbar_in, R, d.ecell, d.enl, egp, F, G);
   if (ev) hipEventRecord(ev[2], st);
-  hipLaunchKernelGGL((update_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, dt, wbar_in, d.nbr,
-                     d.cell_edge, nl, d.inv_area, F, G, wbar_out, grad_out);
+  hipLaunchKernelGGL((update_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, NB, dt, wbar_in,
+                     d.bnd_n, d.nbr, d.cell_edge, nl, d.inv_area, F, G, wbar_out, grad_out);
   if (ev) {
     hipEventRecord(ev[3], st);
     ++M->d.prof_n;

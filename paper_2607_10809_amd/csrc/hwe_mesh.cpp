@@ -246,6 +246,23 @@ hwe_status fail(hwe_status s, const std::string& msg) {
 
 }  // namespace
 
+// A boundary face on a reflective wall: it lies on a side of the box (s = 0:
+// x = x0, 1: x = x1, 2: y = y0, 3: y = y1) whose bit is set in o.walls.
+static bool on_wall(const hwe_opts& o, const Tri& t, int f) {
+  if (!o.walls) return false;
+  const int f1 = (f + 1) % 3;
+  const double ex = t.x[f1] - t.x[f], ey = t.y[f1] - t.y[f];
+  const double mx = 0.5 * (t.x[f] + t.x[f1]), my = 0.5 * (t.y[f] + t.y[f1]);
+  const double tol = 1e-9 * std::max(o.box[1] - o.box[0], o.box[3] - o.box[2]);
+  const bool on[4] = {std::fabs(mx - o.box[0]) < tol && std::fabs(ex) < tol,
+                      std::fabs(mx - o.box[1]) < tol && std::fabs(ex) < tol,
+                      std::fabs(my - o.box[2]) < tol && std::fabs(ey) < tol,
+                      std::fabs(my - o.box[3]) < tol && std::fabs(ey) < tol};
+  for (int s = 0; s < 4; ++s)
+    if (on[s] && ((o.walls >> s) & 1)) return true;
+  return false;
+}
+
 hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* tris, int64_t n_tris,
                            const hwe_opts& o, HostMesh& h) {
   const double w2 = o.deriv_weight * o.deriv_weight;
@@ -400,7 +417,7 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
     double ex = t.x[f1] - t.x[f], ey = t.y[f1] - t.y[f];
     double len = std::hypot(ex, ey);
     h.ecell[e] = int32_t(inv[r.c0]);
-    h.ecell[E + e] = r.c1 >= 0 ? int32_t(inv[r.c1]) : -1;
+    h.ecell[E + e] = r.c1 >= 0 ? int32_t(inv[r.c1]) : (on_wall(o, t, f) ? -2 : -1);
     h.egeo[0 * E + e] = ey / len;
     h.egeo[1 * E + e] = -ex / len;
     h.egeo[2 * E + e] = len;
@@ -425,7 +442,7 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
   h.mom.assign(3 * N, 0);
   h.nbr.assign(3 * N, 0);
   h.nbr_back.assign(3 * N, -1);
-  h.bnd_n.assign(2 * std::max<int64_t>(h.NB, 1), 0);
+  h.bnd_n.assign(3 * std::max<int64_t>(h.NB, 1), 0);
   h.p1.assign(size_t(kP1) * N, 0);
   h.p2.assign(size_t(kP2) * N, 0);
   h.cell_edge.assign(3 * N, 0);
@@ -478,6 +495,7 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
         h.nbr[f * N + i] = int32_t(-(bcount + 1));
         h.bnd_n[bcount] = nx;
         h.bnd_n[h.NB + bcount] = ny;
+        h.bnd_n[2 * h.NB + bcount] = on_wall(o, t, f) ? 1.0 : 0.0;
         ++bcount;
         Tri gt;
         for (int v = 0; v < 3; ++v) {

@@ -103,11 +103,17 @@ __host__ __device__ __forceinline__ Stencil<Real> gather_stencil(int i, int q, i
 // Reconstruction of component q of cell i (Sec. 2.2) from its stencil.
 // Writes the six coefficients a0..a5 of R - Wbar (monomials about the centroid).
 // tb: the cell's column of the tiled geometry table (row k at tb[k * kTile]).
+// On a reflective wall (Euler) the momentum components of the ghost are
+// reflected too, which mixes the two momentum rows: wbar and grad are read for
+// the cell's other momentum component there.
 template <int EQ, class Real>
-__host__ __device__ __forceinline__ void recon_from_stencil(int i, int NB, const Params& P, const Stencil<Real>& S,
+__host__ __device__ __forceinline__ void recon_from_stencil(int i, int q, int N, int NB, const Params& P,
+                                                           const Stencil<Real>& S,
                                                            const double* __restrict__ bnd_n,
                                                            const Real* __restrict__ tb,
-                                                           const double* __restrict__ area, Real (&a)[6]) {
+                                                           const double* __restrict__ area,
+                                                           const double* __restrict__ wbar,
+                                                           const Real* __restrict__ grad, Real (&a)[6]) {
   const double W0 = S.W0;
   Real V[4], Y[4];
 #pragma unroll
@@ -122,7 +128,7 @@ __host__ __device__ __forceinline__ void recon_from_stencil(int i, int NB, const
       dW[f] = S.Wn[f] - W0;
       Wsum += S.Wn[f];
     } else {
-      // transmissive ghost: K0 mirrored across the face, gradient reflected
+      // ghost: K0 mirrored across the face, gradient columns reflected
       const int b = -S.nbi[f] - 1;
       const Real nx = Real(bnd_n[b]), ny = Real(bnd_n[NB + b]);
       dW[f] = 0.0;
@@ -130,6 +136,25 @@ __host__ __device__ __forceinline__ void recon_from_stencil(int i, int NB, const
       const Real vn = V[0] * nx + Y[0] * ny;
       V[f + 1] = V[0] - Real(2) * nx * vn;
       Y[f + 1] = Y[0] - Real(2) * ny * vn;
+      if constexpr (EQ == EQ_EUL) {
+        if ((q == 1 || q == 2) && bnd_n[2 * NB + b] != 0.0) {
+          // wall: m -> m - 2 (m.n) n in the average, and the rows of the two
+          // momentum components mixed the same way
+          constexpr int M = NComp<EQ>::m;
+          const double dnx = bnd_n[b], dny = bnd_n[NB + b], na = q == 1 ? dnx : dny;
+          const double mn = wbar[1 * size_t(N) + i] * dnx + wbar[2 * size_t(N) + i] * dny;
+          dW[f] = -2.0 * na * mn;
+          Wsum += dW[f];
+          const Real V1 = grad[1 * size_t(N) + i], Y1 = grad[(M + 1) * size_t(N) + i];
+          const Real V2 = grad[2 * size_t(N) + i], Y2 = grad[(M + 2) * size_t(N) + i];
+          const Real v1 = V1 * nx + Y1 * ny, v2 = V2 * nx + Y2 * ny;
+          const Real R1x = V1 - Real(2) * nx * v1, R1y = Y1 - Real(2) * ny * v1;
+          const Real R2x = V2 - Real(2) * nx * v2, R2y = Y2 - Real(2) * ny * v2;
+          const Real rn = Real(2) * Real(na);
+          V[f + 1] = V[f + 1] - rn * (nx * R1x + ny * R2x);
+          Y[f + 1] = Y[f + 1] - rn * (nx * R1y + ny * R2y);
+        }
+      }
     }
   }
   // Step 1: c = P1 (dW1..3, V0..3, Y0..3); W differences formed in FP64
@@ -212,7 +237,7 @@ __host__ __device__ __forceinline__ void recon_coeffs(int i, int q, int N, int N
                                                      const Real* __restrict__ tb, const double* __restrict__ area,
                                                      Real (&a)[6]) {
   const Stencil<Real> S = gather_stencil<EQ, Real>(i, q, N, wbar, grad, nbr);
-  recon_from_stencil<EQ, Real>(i, NB, P, S, bnd_n, tb, area, a);
+  recon_from_stencil<EQ, Real>(i, q, N, NB, P, S, bnd_n, tb, area, wbar, grad, a);
 }
 
 template <int EQ, class Real>
@@ -281,28 +306,25 @@ __host__ __device__ __forceinline__ void positivity_theta(double gam, const doub
 }
 
 // ------------------------------------------------------------------ edge lane
-// Contribution of one side (0: the edge's first cell, 1: its second) at one
-// Gauss point, as offsets from that cell's average Wbd: time integrals over
-// the Lobatto nodes of the normal-flux offset dH = H(W) - H(Wbar) (AH) and of
-// d = W - Wbar (AD), and d at t_n + dt (AT).  cell < 0 (no cell on this side)
-// gives zeros.  (nx, ny): the edge's unit normal; egp: [8][E] Gauss-point
-// offsets from the centroids (side 0 points 0, 1; side 1 points 0, 1).
-// TR: the time rule (0: 3-point Gauss-Lobatto, 1: 2-point Gauss-Legendre).
-template <int EQ, class Real, int TR>
-__host__ __device__ __forceinline__ void edge_lane(int e, int cell, int side, int g, int E, int N, const Params& P,
-                                                  double dt, const double (&Wbd)[NComp<EQ>::m], Real nx, Real ny,
-                                                  const Real* __restrict__ R, const Real* __restrict__ egp,
-                                                  Real (&AH)[NComp<EQ>::m], Real (&AD)[NComp<EQ>::m],
-                                                  Real (&AT)[NComp<EQ>::m]) {
+// One side (0: the edge's first cell, 1: its second) at one Gauss point, in two
+// parts.  edge_point: the reconstruction's offset d = W - Wbar at the point and
+// its time derivatives W_t, W_tt by the Lax-Wendroff procedure (zeros when
+// cell < 0).  egp: [8][E] Gauss-point offsets from the centroids (side 0
+// points 0, 1; side 1 points 0, 1).
+template <int EQ, class Real>
+__host__ __device__ __forceinline__ void edge_point(int e, int cell, int side, int g, int E, const Params& P,
+                                                   const double (&Wbd)[NComp<EQ>::m], const Real* __restrict__ R,
+                                                   const Real* __restrict__ egp, Real (&dl)[NComp<EQ>::m],
+                                                   Real (&Wt)[NComp<EQ>::m], Real (&Wtt)[NComp<EQ>::m]) {
   constexpr int M = NComp<EQ>::m;
 #pragma unroll
-  for (int q = 0; q < M; ++q) AH[q] = AD[q] = AT[q] = Real(0);
+  for (int q = 0; q < M; ++q) dl[q] = Wt[q] = Wtt[q] = Real(0);
   if (cell < 0) return;
   Real ac[6][M];
   load_record<6 * M>(R + size_t(cell) * (6 * M), &ac[0][0]);
   const Real X = egp[(4 * side + 2 * g) * E + e];
   const Real Y = egp[(4 * side + 2 * g + 1) * E + e];
-  Real D[6][M], dl[M];
+  Real D[6][M];
 #pragma unroll
   for (int q = 0; q < M; ++q) {
     const Real a0 = ac[0][q], a1 = ac[1][q], a2 = ac[2][q], a3 = ac[3][q], a4 = ac[4][q], a5 = ac[5][q];
@@ -314,11 +336,24 @@ __host__ __device__ __forceinline__ void edge_lane(int e, int cell, int side, in
     D[4][q] = a4;
     D[5][q] = Real(2) * a5;
   }
-  Real Wt[M], Wtt[M];
   lax_wendroff<EQ, Real>(P, D, Wt, Wtt);
+}
+
+// edge_nodes: the time integrals, over the nodes of the time rule TR (0:
+// 3-point Gauss-Lobatto, 1: 2-point Gauss-Legendre), of the normal-flux offset
+// dH = H(Wbar + d) - H(Wbar) (AH) and of d (AD), and d at t_n + dt (AT), with
+// d(tau) = dl + tau W_t + tau^2/2 W_tt.  (nx, ny): the edge's unit normal.
+template <int EQ, class Real, int TR>
+__host__ __device__ __forceinline__ void edge_nodes(const Params& P, double dt, const double (&Wbd)[NComp<EQ>::m],
+                                                   Real nx, Real ny, const Real (&dl)[NComp<EQ>::m],
+                                                   const Real (&Wt)[NComp<EQ>::m], const Real (&Wtt)[NComp<EQ>::m],
+                                                   Real (&AH)[NComp<EQ>::m], Real (&AD)[NComp<EQ>::m],
+                                                   Real (&AT)[NComp<EQ>::m]) {
+  constexpr int M = NComp<EQ>::m;
+#pragma unroll
+  for (int q = 0; q < M; ++q) AH[q] = AD[q] = Real(0);
   const FluxBase<EQ, Real> base = flux_base<EQ, Real>(P, Wbd);
-  // one node of the time rule: Taylor value d(tau) = dl + tau W_t + tau^2/2 W_tt
-  // and the weighted sums of dH(tau) and d(tau)
+  // one node of the time rule: Taylor value d(tau) and the weighted sums
   auto node = [&](Real tau, Real w, Real (&dls)[M]) {
     const Real h2 = Real(0.5) * tau * tau;
     Real dH[M];
@@ -349,6 +384,15 @@ __host__ __device__ __forceinline__ void edge_lane(int e, int cell, int side, in
 #pragma unroll
     for (int q = 0; q < M; ++q) AT[q] = d[q];
   }
+}
+
+// Reflection of the momentum components (Euler: 1 and 2) across a line with
+// unit normal n: m -> m - 2 (m.n) n.
+template <class T>
+__host__ __device__ __forceinline__ void reflect_momentum(T nx, T ny, T (&W)[4]) {
+  const T mn = W[1] * nx + W[2] * ny;
+  W[1] = W[1] - T(2) * nx * mn;
+  W[2] = W[2] - T(2) * ny * mn;
 }
 
 // FP64 terms of one side at its cell average: the normal flux H(Wbar) and the
@@ -398,11 +442,13 @@ __host__ __device__ __forceinline__ void edge_value(int e, int E, bool second, c
 }
 
 // ------------------------------------------------------------------ update
-// eq. (flx) with FP64 accumulation, and eq. (derave2d2):  using sum_e n_e|e| = 0
+// eq. (flx) with FP64 accumulation (walls: the ghost average reflected), and eq. (derave2d2):  using sum_e n_e|e| = 0
 // over the closed cell, |K| Vbar = sum_e n_e|e| (Wface_e - Wbar_K + G_e) where
 // Wface_e = mean of the two cell averages, so a constant state gives exactly 0.
 template <int EQ, class Real>
-__host__ __device__ __forceinline__ void update_point(int i, int N, int E, double dt, const double* __restrict__ wbar,
+__host__ __device__ __forceinline__ void update_point(int i, int N, int E, int NB, double dt,
+                                                     const double* __restrict__ wbar,
+                                                     const double* __restrict__ bnd_n,
                                                      const int32_t* __restrict__ nbr,
                                                      const int32_t* __restrict__ cell_edge,
                                                      const Real* __restrict__ nl, const double* __restrict__ inv_area,
@@ -434,12 +480,29 @@ __host__ __device__ __forceinline__ void update_point(int i, int N, int E, doubl
     Real Ge[M];
     load_record<M>(F + size_t(e) * M, Fe);
     load_record<M>(G + size_t(e) * M, Ge);
+    double d[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) {
       const double Wn = wbar[q * sN + c];
       fs[q] += second ? -Fe[q] : Fe[q];
-      const double d = 0.5 * (Wn - W0[q]);  // exactly 0 on a boundary face (Wn is the cell's own)
-      const double gq = double(Ge[q]) + d;
+      d[q] = 0.5 * (Wn - W0[q]);  // exactly 0 on a boundary face (Wn is the cell's own)
+    }
+    if constexpr (EQ == EQ_EUL) {
+      if (nb[f] < 0) {
+        // wall: the ghost average is the reflected one, half the difference is
+        // -(m.n) n in the momentum components
+        const int b = -nb[f] - 1;
+        if (bnd_n[2 * NB + b] != 0.0) {
+          const double bx = bnd_n[b], by = bnd_n[NB + b];
+          const double mn = W0[1] * bx + W0[2] * by;
+          d[1] = -mn * bx;
+          d[2] = -mn * by;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const double gq = double(Ge[q]) + d[q];
       vs[q] += nlx * gq;
       ys[q] += nly * gq;
     }

@@ -27,7 +27,7 @@ def _stream(stream=None):
 
 def make_opts(eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp64", adv=(1.0, 1.0),
               gas_gamma=1.4, lin_w=(0.94, 0.02, 0.02, 0.02), eps=1e-8, linear_weights=False, device=0,
-              positivity=False, time_rule=0, deriv_weight=1.0) -> HweOpts:
+              positivity=False, time_rule=0, deriv_weight=1.0, walls=0) -> HweOpts:
     L = load_library()
     o = HweOpts()
     check(L.hwe_opts_default(C.byref(o)))
@@ -44,6 +44,7 @@ def make_opts(eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp
     o.positivity = 1 if positivity else 0
     o.time_rule = int(time_rule)
     o.deriv_weight = float(deriv_weight)
+    o.walls = int(walls)
     return o
 
 
@@ -94,6 +95,8 @@ class Mesh:
     def from_workload(cls, wl, precision="fp64", device=0, **kw):
         bc = "periodic" if wl.mesh.periodic else "transmissive"
         eq = {0: "advection", 1: "burgers", 2: "euler"}[wl.eq]
+        if getattr(wl, "walls", 0) and "walls" not in kw:
+            kw["walls"] = wl.walls
         return cls(wl.mesh.nodes, wl.mesh.tris, eq=eq, bc=bc, box=wl.mesh.box, precision=precision,
                    device=device, adv=wl.adv, **kw)
 
