@@ -146,10 +146,36 @@ hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, doub
  * Non-smooth points: d|x| = sign(x) dx with sign(0) = 0; the max of the two
  * spectral radii in the flux viscosity takes the edge's first cell (the one
  * with the lower caller index) on ties.  Returns HWE_EINVAL for meshes built
- * with opts.positivity = 1 (the limiter is not differentiated). */
+ * with opts.positivity = 1 (the limiter is not differentiated) or with
+ * reflective walls. */
 hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n,
                             const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n,
                             void* lam_grad_n, double dt, void* stream);
+
+/* Reverse sweeps that recompute the forward states of a checkpoint segment
+ * (Sec. 2 step, reversed by hwe_step_adjoint) can keep each step's
+ * reconstruction (Steps 1-6) so that the adjoint does not rebuild it.
+ *
+ * hwe_step_keep: hwe_step whose reconstruction of the state at t_n is written
+ * to recon_out and read from there by the step's edge stage (in place of the
+ * handle's scratch).  Results are bitwise those of hwe_step.
+ *  recon_out : device, caller-owned, [N][6][m] of double (FP64) or float
+ *              (MIXED): per cell and component the coefficients a0..a5 of
+ *              R - Wbar in the monomial basis about the cell centroid (the
+ *              layout of hwe_debug_recon); must not overlap the state buffers.
+ *
+ * hwe_step_adjoint_kept: hwe_step_adjoint with recon_n = the buffer that
+ * hwe_step_keep wrote for the same (wbar_n, grad_n) on this handle; the
+ * reconstruction launch is skipped and the result is bitwise that of
+ * hwe_step_adjoint.  The library cannot check that recon_n belongs to the
+ * state: a buffer from another state gives a wrong product without an error.
+ * Both return HWE_EINVAL for a null recon buffer and under the conditions of
+ * the calls they extend. */
+hwe_status hwe_step_keep(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out,
+                         void* grad_out, double dt, void* recon_out, void* stream);
+hwe_status hwe_step_adjoint_kept(hwe_mesh m, const double* wbar_n, const void* grad_n, const void* recon_n,
+                                 const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n,
+                                 void* lam_grad_n, double dt, void* stream);
 
 /* Largest stable step of the driver: dt = cfl * min_K r_K / max_K lambda_K
  * (r_K inradius, lambda_K the largest signal speed at the cell average).

@@ -4,8 +4,12 @@
 steps (hwe_step) and returns the final state; its backward pass applies the
 hand-written adjoint (hwe_step_adjoint) in reverse.  Only every ``ckpt``-th
 state is kept during the forward pass; the backward pass recomputes each
-segment of ``ckpt`` steps from its checkpoint, then walks it backwards.
-The time step is a constant (not differentiated).
+segment of ``ckpt`` steps from its checkpoint, keeping the reconstruction
+of every recomputed step (hwe_step_keep), then walks it backwards with the
+adjoint that reuses them (hwe_step_adjoint_kept).  The last state of a
+segment is never stepped during the recomputation, so its reconstruction is
+rebuilt by the adjoint itself.  The time step is a constant (not
+differentiated).
 """
 from __future__ import annotations
 
@@ -38,18 +42,20 @@ class Rollout(torch.autograd.Function):
         lam = (lw.contiguous().to(torch.float64), lg.contiguous().to(mesh.gdtype))
         nseg = len(ctx.checkpoints)
         out = [mesh.empty_state(), mesh.empty_state()]
+        recon = [mesh.empty_recon() for _ in range(min(ckpt, n) - 1)]
         flip = 0
         for s in reversed(range(nseg)):
             start = s * ckpt
             length = min(ckpt, n - start)
-            # recompute the states of the segment
+            # recompute the states of the segment, keeping each step's reconstruction
             states = [ctx.checkpoints[s]]
             for k in range(length - 1):
-                states.append(mesh.step(states[-1][0], states[-1][1], dt))
+                states.append(mesh.step(states[-1][0], states[-1][1], dt, keep=recon[k]))
             for k in reversed(range(length)):
                 dst = out[flip]
                 flip ^= 1
-                mesh.adjoint(states[k][0], states[k][1], lam[0], lam[1], dt, out=dst)
+                R = recon[k] if k < length - 1 else None
+                mesh.adjoint(states[k][0], states[k][1], lam[0], lam[1], dt, out=dst, recon=R)
                 lam = dst
             ctx.checkpoints[s] = None
         return lam[0].clone(), lam[1].clone(), None, None, None, None

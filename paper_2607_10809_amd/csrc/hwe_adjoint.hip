@@ -3,7 +3,8 @@
 //   hwe_step_adjoint(state_n, lam_{n+1}) = J(state_n)^T lam_{n+1}
 //
 // Three launches on the caller's stream, none with atomics:
-//   1. the forward reconstruction kernel (R of every cell at state_n);
+//   1. the forward reconstruction kernel (R of every cell at state_n), skipped
+//      when the caller hands in the R that a step kept for this state;
 //   2. adj_cell_kernel, four work-items per cell.  Work-items 0-2 take the
 //      cell's faces: from the cell's and the neighbour's lam_{n+1} they form the
 //      adjoints of the edge flux F_e and of the interface-value integral G_e,
@@ -262,11 +263,10 @@ unsigned grid_for(int64_t items) { return unsigned((items + kBlock - 1) / kBlock
 template <int EQ, class Real>
 hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, const Real* grad, const double* lw,
                         const Real* lg, double* lw_out, Real* lg_out, double dt, hipStream_t st, const Real* tbl,
-                        const Real* nl, const Real* egp) {
+                        const Real* nl, const Real* egp, const Real* R) {
   const HostMesh& h = M->h;
   const DevMesh& d = M->d;
   const int N = int(h.N), E = int(h.E), NB = int(h.NB);
-  const Real* R = static_cast<const Real*>(d.R);
   if (P.time_rule == 1)
     hipLaunchKernelGGL((adj_cell_kernel<EQ, Real, 1>), dim3(grid_for(4 * int64_t(N))), dim3(kBlock), 0, st, N, E, NB, P,
                        dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl,
@@ -284,10 +284,13 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
 
 }  // namespace
 
-hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_n, const double* lw, const void* lg,
-                          double* lw_out, void* lg_out, double dt, void* stream) {
-  hwe_status s = launch_recon(M, wbar_n, grad_n, M->d.R, stream);
-  if (s != HWE_OK) return s;
+hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_n, const void* R_n, const double* lw,
+                          const void* lg, double* lw_out, void* lg_out, double dt, void* stream) {
+  if (!R_n) {
+    hwe_status s = launch_recon(M, wbar_n, grad_n, M->d.R, stream);
+    if (s != HWE_OK) return s;
+    R_n = M->d.R;
+  }
   const Params P = params_of(M->opts);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const DevMesh& d = M->d;
@@ -297,11 +300,11 @@ hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_
     auto o = static_cast<double*>(lg_out);
     switch (M->opts.eq) {
       case HWE_ADVECTION:
-        return adjoint_impl<EQ_ADV, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tbl, d.nl, d.egp);
+        return adjoint_impl<EQ_ADV, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tbl, d.nl, d.egp, static_cast<const double*>(R_n));
       case HWE_BURGERS:
-        return adjoint_impl<EQ_BUR, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tbl, d.nl, d.egp);
+        return adjoint_impl<EQ_BUR, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tbl, d.nl, d.egp, static_cast<const double*>(R_n));
       default:
-        return adjoint_impl<EQ_EUL, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tbl, d.nl, d.egp);
+        return adjoint_impl<EQ_EUL, double>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tbl, d.nl, d.egp, static_cast<const double*>(R_n));
     }
   }
   auto g = static_cast<const float*>(grad_n);
@@ -309,11 +312,11 @@ hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_
   auto o = static_cast<float*>(lg_out);
   switch (M->opts.eq) {
     case HWE_ADVECTION:
-      return adjoint_impl<EQ_ADV, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tblf, d.nlf, d.egpf);
+      return adjoint_impl<EQ_ADV, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tblf, d.nlf, d.egpf, static_cast<const float*>(R_n));
     case HWE_BURGERS:
-      return adjoint_impl<EQ_BUR, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tblf, d.nlf, d.egpf);
+      return adjoint_impl<EQ_BUR, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tblf, d.nlf, d.egpf, static_cast<const float*>(R_n));
     default:
-      return adjoint_impl<EQ_EUL, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tblf, d.nlf, d.egpf);
+      return adjoint_impl<EQ_EUL, float>(M, P, wbar_n, g, lw, l, lw_out, o, dt, st, d.tblf, d.nlf, d.egpf, static_cast<const float*>(R_n));
   }
 }
 

@@ -168,8 +168,12 @@ hwe_status hwe_mesh_cell_perm(hwe_mesh m, int64_t* perm_host) {
   return HWE_OK;
 }
 
-hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,
-                    double dt, void* stream) {
+namespace {
+
+// Argument checks shared by hwe_step and hwe_step_keep; recon (may be null)
+// is the kept-reconstruction buffer, which must not overlap the state buffers.
+hwe_status check_step(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,
+                      double dt, const void* recon) {
   hwe_status s = need_device(m);
   if (s != HWE_OK) return s;
   if ((s = check_dt(dt)) != HWE_OK) return s;
@@ -185,12 +189,22 @@ hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, doub
     set_error("output buffers overlap the inputs or each other");
     return HWE_EINVAL;
   }
-  if ((s = set_dev(m)) != HWE_OK) return s;
-  return launch_step(m, wbar_in, grad_in, wbar_out, grad_out, dt, stream);
+  if (recon) {
+    const size_t rb = 6 * mm * N * real_size(m);
+    const void* st[4] = {wbar_in, grad_in, wbar_out, grad_out};
+    const size_t sz[4] = {wb, gb, wb, gb};
+    for (int k = 0; k < 4; ++k)
+      if (overlaps(st[k], sz[k], recon, rb)) {
+        set_error("the reconstruction buffer overlaps a state buffer");
+        return HWE_EINVAL;
+      }
+  }
+  return set_dev(m);
 }
 
-hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n, const double* lam_wbar_np1,
-                            const void* lam_grad_np1, double* lam_wbar_n, void* lam_grad_n, double dt, void* stream) {
+hwe_status check_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n, const void* recon_n,
+                         const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n, void* lam_grad_n,
+                         double dt) {
   hwe_status s = need_device(m);
   if (s != HWE_OK) return s;
   if ((s = check_dt(dt)) != HWE_OK) return s;
@@ -200,10 +214,11 @@ hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n
   }
   const size_t N = size_t(m->h.N), mm = size_t(m->h.m);
   const size_t wb = mm * N * sizeof(double), gb = 2 * mm * N * real_size(m);
-  const void* ins[4] = {wbar_n, grad_n, lam_wbar_np1, lam_grad_np1};
-  const size_t insz[4] = {wb, gb, wb, gb};
-  for (int k = 0; k < 4; ++k)
-    if (overlaps(ins[k], insz[k], lam_wbar_n, wb) || overlaps(ins[k], insz[k], lam_grad_n, gb)) {
+  const size_t rb = 6 * mm * N * real_size(m);
+  const void* ins[5] = {wbar_n, grad_n, lam_wbar_np1, lam_grad_np1, recon_n};
+  const size_t insz[5] = {wb, gb, wb, gb, rb};
+  for (int k = 0; k < 5; ++k)
+    if (ins[k] && (overlaps(ins[k], insz[k], lam_wbar_n, wb) || overlaps(ins[k], insz[k], lam_grad_n, gb))) {
       set_error("output buffers overlap the inputs");
       return HWE_EINVAL;
     }
@@ -219,8 +234,46 @@ hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n
     set_error("hwe_step_adjoint: the positivity limiter is not differentiated");
     return HWE_EINVAL;
   }
-  if ((s = set_dev(m)) != HWE_OK) return s;
-  return launch_adjoint(m, wbar_n, grad_n, lam_wbar_np1, lam_grad_np1, lam_wbar_n, lam_grad_n, dt, stream);
+  return set_dev(m);
+}
+
+}  // namespace
+
+hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,
+                    double dt, void* stream) {
+  hwe_status s = check_step(m, wbar_in, grad_in, wbar_out, grad_out, dt, nullptr);
+  if (s != HWE_OK) return s;
+  return launch_step(m, wbar_in, grad_in, wbar_out, grad_out, dt, nullptr, stream);
+}
+
+hwe_status hwe_step_keep(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,
+                         double dt, void* recon_out, void* stream) {
+  if (!recon_out) {
+    set_error("null reconstruction buffer");
+    return HWE_EINVAL;
+  }
+  hwe_status s = check_step(m, wbar_in, grad_in, wbar_out, grad_out, dt, recon_out);
+  if (s != HWE_OK) return s;
+  return launch_step(m, wbar_in, grad_in, wbar_out, grad_out, dt, recon_out, stream);
+}
+
+hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n, const double* lam_wbar_np1,
+                            const void* lam_grad_np1, double* lam_wbar_n, void* lam_grad_n, double dt, void* stream) {
+  hwe_status s = check_adjoint(m, wbar_n, grad_n, nullptr, lam_wbar_np1, lam_grad_np1, lam_wbar_n, lam_grad_n, dt);
+  if (s != HWE_OK) return s;
+  return launch_adjoint(m, wbar_n, grad_n, nullptr, lam_wbar_np1, lam_grad_np1, lam_wbar_n, lam_grad_n, dt, stream);
+}
+
+hwe_status hwe_step_adjoint_kept(hwe_mesh m, const double* wbar_n, const void* grad_n, const void* recon_n,
+                                 const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n,
+                                 void* lam_grad_n, double dt, void* stream) {
+  if (!recon_n) {
+    set_error("null reconstruction buffer");
+    return HWE_EINVAL;
+  }
+  hwe_status s = check_adjoint(m, wbar_n, grad_n, recon_n, lam_wbar_np1, lam_grad_np1, lam_wbar_n, lam_grad_n, dt);
+  if (s != HWE_OK) return s;
+  return launch_adjoint(m, wbar_n, grad_n, recon_n, lam_wbar_np1, lam_grad_np1, lam_wbar_n, lam_grad_n, dt, stream);
 }
 
 hwe_status hwe_max_dt(hwe_mesh m, const double* wbar, double cfl, double* dt_dev, void* stream) {

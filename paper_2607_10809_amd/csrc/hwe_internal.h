@@ -101,10 +101,15 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
 hwe_status upload_mesh(hwe_mesh_s* M);
 void free_device(hwe_mesh_s* M);
 // Launchers (hwe_kernels.hip).  All asynchronous on stream.
+// R_keep (may be null): caller memory [N][6][m] that receives the
+// reconstruction of the step and is read by its edge kernel in place of the
+// handle's scratch R.
 hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out,
-                       void* grad_out, double dt, void* stream);
+                       void* grad_out, double dt, void* R_keep, void* stream);
 hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, void* R_out, void* stream);
-hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_n, const double* lw,
+// R_n (may be null): the reconstruction of state n kept by a step; null
+// recomputes it into the handle's scratch.
+hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_n, const void* R_n, const double* lw,
                           const void* lg, double* lw_out, void* lg_out, double dt, void* stream);
 hwe_status launch_max_dt(hwe_mesh_s* M, const double* wbar, double cfl, double* dt_dev, void* stream);
 hwe_status launch_check(hwe_mesh_s* M, const double* wbar, int32_t* flags, void* stream);

@@ -338,11 +338,10 @@ unsigned grid_for(int64_t items) { return unsigned((items + kBlock - 1) / kBlock
 template <int EQ, class Real>
 hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, const Real* grad_in, double* wbar_out,
                      Real* grad_out, double dt, hipStream_t st, const Real* tbl, const Real* nl,
-                     const Real* egp) {
+                     const Real* egp, Real* R) {
   const HostMesh& h = M->h;
   const DevMesh& d = M->d;
   const int N = int(h.N), E = int(h.E), NB = int(h.NB);
-  Real* R = static_cast<Real*>(d.R);
   double* F = static_cast<double*>(d.F);
   Real* G = static_cast<Real*>(d.G);
   constexpr int Mc = NComp<EQ>::m;
@@ -474,31 +473,32 @@ void free_device(hwe_mesh_s* M) {
 }
 
 hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,
-                       double dt, void* stream) {
+                       double dt, void* R_keep, void* stream) {
   const Params P = params_of(M->opts);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const DevMesh& d = M->d;
+  void* R = R_keep ? R_keep : d.R;
   if (M->opts.prec == HWE_FP64) {
     auto gi = static_cast<const double*>(grad_in);
     auto go = static_cast<double*>(grad_out);
     switch (M->opts.eq) {
       case HWE_ADVECTION:
-        return step_impl<EQ_ADV, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp);
+        return step_impl<EQ_ADV, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp, static_cast<double*>(R));
       case HWE_BURGERS:
-        return step_impl<EQ_BUR, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp);
+        return step_impl<EQ_BUR, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp, static_cast<double*>(R));
       default:
-        return step_impl<EQ_EUL, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp);
+        return step_impl<EQ_EUL, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp, static_cast<double*>(R));
     }
   }
   auto gi = static_cast<const float*>(grad_in);
   auto go = static_cast<float*>(grad_out);
   switch (M->opts.eq) {
     case HWE_ADVECTION:
-      return step_impl<EQ_ADV, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf);
+      return step_impl<EQ_ADV, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf, static_cast<float*>(R));
     case HWE_BURGERS:
-      return step_impl<EQ_BUR, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf);
+      return step_impl<EQ_BUR, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf, static_cast<float*>(R));
     default:
-      return step_impl<EQ_EUL, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf);
+      return step_impl<EQ_EUL, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf, static_cast<float*>(R));
   }
 }
 

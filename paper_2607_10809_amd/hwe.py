@@ -69,6 +69,18 @@ def hwe_step_adjoint(handle, wbar_n, grad_n, lam_wbar_np1, lam_grad_np1, lam_wba
                                           _stream(stream)))
 
 
+def hwe_step_keep(handle, wbar_in, grad_in, wbar_out, grad_out, dt, recon_out, stream=None):
+    check(load_library().hwe_step_keep(handle, _ptr(wbar_in), _ptr(grad_in), _ptr(wbar_out), _ptr(grad_out),
+                                       float(dt), _ptr(recon_out), _stream(stream)))
+
+
+def hwe_step_adjoint_kept(handle, wbar_n, grad_n, recon_n, lam_wbar_np1, lam_grad_np1, lam_wbar_n, lam_grad_n, dt,
+                          stream=None):
+    check(load_library().hwe_step_adjoint_kept(handle, _ptr(wbar_n), _ptr(grad_n), _ptr(recon_n),
+                                               _ptr(lam_wbar_np1), _ptr(lam_grad_np1), _ptr(lam_wbar_n),
+                                               _ptr(lam_grad_n), float(dt), _stream(stream)))
+
+
 class Mesh:
     """A triangular mesh on one GPU with the scheme's options.
 
@@ -143,12 +155,29 @@ class Mesh:
             raise ValueError("state tensors must live on the mesh's device")
 
     # ------------------------------------------------------------ the step
-    def step(self, wbar, grad, dt, out=None, stream=None):
+    def step(self, wbar, grad, dt, out=None, stream=None, keep=None):
+        """One step.  keep: a buffer from empty_recon() that receives the
+        step's reconstruction (for a later adjoint(..., recon=keep))."""
         self._check_state(wbar, grad)
         wo, go = out if out is not None else self.empty_state()
         self._check_state(wo, go)
-        hwe_step(self._h, wbar, grad, wo, go, dt, stream)
+        if keep is None:
+            hwe_step(self._h, wbar, grad, wo, go, dt, stream)
+        else:
+            self._check_recon(keep)
+            hwe_step_keep(self._h, wbar, grad, wo, go, dt, keep, stream)
         return wo, go
+
+    def empty_recon(self):
+        """Buffer for one step's reconstruction: the library's cell-major
+        [N][6][m] record of the coefficients a0..a5 (gdtype)."""
+        return torch.empty((self.N, 6, self.m), dtype=self.gdtype, device=self.device)
+
+    def _check_recon(self, R):
+        if R.dtype != self.gdtype or R.shape != (self.N, 6, self.m) or not R.is_contiguous():
+            raise ValueError(f"recon must be a contiguous {self.gdtype} tensor of shape (N, 6, m)")
+        if R.device != self.device:
+            raise ValueError("recon must live on the mesh's device")
 
     def run(self, wbar, grad, dt, nsteps, stream=None):
         """nsteps steps of size dt with two ping-pong buffers; returns the final state."""
@@ -182,11 +211,17 @@ class Mesh:
                 steps += 1
         return bufs[cur][0], bufs[cur][1], steps
 
-    def adjoint(self, wbar, grad, lam_wbar, lam_grad, dt, out=None, stream=None):
+    def adjoint(self, wbar, grad, lam_wbar, lam_grad, dt, out=None, stream=None, recon=None):
+        """J^T lam at the state (wbar, grad).  recon: the buffer that
+        step(wbar, grad, ..., keep=recon) filled; skips the reconstruction."""
         self._check_state(wbar, grad)
         self._check_state(lam_wbar, lam_grad)
         lw, lg = out if out is not None else self.empty_state()
-        hwe_step_adjoint(self._h, wbar, grad, lam_wbar, lam_grad, lw, lg, dt, stream)
+        if recon is None:
+            hwe_step_adjoint(self._h, wbar, grad, lam_wbar, lam_grad, lw, lg, dt, stream)
+        else:
+            self._check_recon(recon)
+            hwe_step_adjoint_kept(self._h, wbar, grad, recon, lam_wbar, lam_grad, lw, lg, dt, stream)
         return lw, lg
 
     def max_dt(self, wbar, cfl, stream=None):

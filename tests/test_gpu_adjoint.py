@@ -199,6 +199,40 @@ def test_checkpointing_does_not_change_the_gradient():
         assert torch.equal(a[0], grads[0][0]) and torch.equal(a[1], grads[0][1])
 
 
+@pytest.mark.parametrize("case,precision", [("advection", "fp64"), ("burgers", "fp64"), ("vortex", "fp64"),
+                                            ("vortex", "mixed"), ("burgers", "mixed")])
+def test_kept_reconstruction_is_bitwise(case, precision):
+    """hwe_step_keep = hwe_step and writes what hwe_debug_recon returns;
+    hwe_step_adjoint_kept with that buffer = hwe_step_adjoint, all bitwise."""
+    import torch
+    from paper_2607_10809_amd._lib import HweError
+    rng = np.random.default_rng(31)
+    wl = {"advection": lambda: advection_workload(n=20), "burgers": lambda: burgers_workload(n=24, T=1.0),
+          "vortex": lambda: vortex_workload(n=24)}[case]()
+    mesh = _mesh(wl, precision)
+    w, g = mesh.to_device(_perturbed(wl, rng))
+    lw, lg = mesh.to_device(rng.normal(size=wl.state0.shape))
+    dt = mesh.max_dt(w, wl.cfl)
+    a = mesh.step(w, g, dt)
+    R = mesh.empty_recon()
+    b = mesh.step(w, g, dt, keep=R)
+    ref = mesh.debug_recon(w, g).permute(2, 0, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert torch.equal(R, ref)
+    x = mesh.adjoint(w, g, lw, lg, dt)
+    y = mesh.adjoint(w, g, lw, lg, dt, recon=R)
+    torch.cuda.synchronize()
+    assert torch.equal(x[0], y[0]) and torch.equal(x[1], y[1])
+    # a reconstruction buffer that overlaps an output state buffer is refused
+    es = torch.finfo(mesh.gdtype).bits // 8
+    raw = torch.empty(6 * mesh.m * mesh.N * es, dtype=torch.uint8, device=mesh.device)
+    Rbad = raw.view(mesh.gdtype).view(mesh.N, 6, mesh.m)
+    wo = raw[:8 * mesh.m * mesh.N].view(torch.float64).view(mesh.m, mesh.N)
+    with pytest.raises(HweError):
+        mesh.step(w, g, dt, out=(wo, torch.empty_like(g)), keep=Rbad)
+
+
 def test_mixed_adjoint_close_to_fp64():
     import torch
     rng = np.random.default_rng(9)
