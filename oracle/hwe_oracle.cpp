@@ -27,7 +27,12 @@
 //   periodic boundaries by exact translation across seams; transmissive
 //   boundaries by a mirrored ghost cell for the stencil and W_ext := W_int
 //   at boundary Gauss points; reflective walls (Euler) likewise with the
-//   momentum reflected in the ghost and in W_ext; kappa/D := 0 when kappa == 0.
+//   momentum reflected in the ghost and in W_ext; prescribed (inflow) states
+//   by a mirrored ghost cell holding that state with zero derivative averages
+//   and W_ext := the state at every time node; a prescribed state that
+//   switches across a moving line x = x_s(t) (a shock meeting the boundary)
+//   takes the side of the face midpoint at the middle of the step,
+//   t_n + dt/2, for the ghost and for W_ext alike; kappa/D := 0 when kappa == 0.
 //   Non-smooth points for derivatives: d|x| = sign(x) dx with sign(0) = 0;
 //   max(a, b) takes a (the edge's first cell, the one with the lower caller
 //   index) on ties.
@@ -136,7 +141,19 @@ struct Opts {
   double deriv_weight;  // weight of the derivative rows in the Step-2 least squares (1: as printed)
   int walls;        // Euler, non-periodic: bit s set = boundary faces on box side s (x0, x1, y0, y1) are
                     // reflective walls; the others are transmissive
+  // boundary regions (non-periodic): a boundary face whose midpoint lies in
+  // region r's closed rectangle takes region r's kind (first match wins); the
+  // faces no region holds follow `walls`.  Kinds: 0 transmissive, 1 wall,
+  // 2 prescribed state A, 3 prescribed state B, 4 A where the face midpoint
+  // has x < shock_x0 + shock_speed * t, else B.
+  int nreg;
+  int reg_kind[8];
+  double reg_box[8][4];
+  double bstate[2][4];  // states A and B (conservative variables)
+  double shock_x0, shock_speed;
 };
+
+enum { kBndTrans = 0, kBndWall = 1, kBndStateA = 2, kBndStateB = 3, kBndMoving = 4 };
 
 inline int ncomp(int eq) { return eq == 2 ? 4 : 1; }
 
@@ -189,7 +206,8 @@ inline double tri_area(const Tri& t) {
 
 struct Face {
   int nb;         // neighbour cell, or -1 on a boundary
-  bool wall;      // boundary face on a reflective wall
+  int kind;       // boundary kind (kBnd*) when nb == -1
+  double mx;      // x of the face midpoint
   int nb_face;    // neighbour's face index
   double sx, sy;  // translation mapping the neighbour's frame into this cell's frame
   double nx, ny;  // outward unit normal of this cell
@@ -220,12 +238,23 @@ template <class T> void reflect_momentum(double nx, double ny, T* W) {
 
 struct Mesh {
   Opts o;
+  double time = 0.0;   // t_n of the next step (moving boundary states)
+  double t_bnd = 0.0;  // time at which the current step evaluates them (t_n + dt/2)
   int64_t N = 0, E = 0;
   int m = 1;
   std::vector<Tri> tri;
   std::vector<double> area, cx, cy;
   std::vector<std::array<Face, 3>> face;
 };
+
+// The prescribed state of a boundary face of kind A, B or moving.
+template <class T>
+void boundary_state(const Mesh& M, const Face& F, T* W) {
+  int which = F.kind == kBndStateB ? 1 : 0;
+  if (F.kind == kBndMoving) which = F.mx < M.o.shock_x0 + M.o.shock_speed * M.t_bnd ? 0 : 1;
+  for (int q = 0; q < M.m; ++q) W[q] = T(M.o.bstate[which][q]);
+}
+inline bool prescribed(const Face& F) { return F.kind >= kBndStateA; }
 
 // Cell average over a triangle of a polynomial given through a callback:
 // the three edge midpoints with weights 1/3 integrate quadratics exactly.
@@ -359,6 +388,8 @@ void stencil_of(const Mesh& M, const T* s, int64_t k, StencilCell<T> st[4]) {
       // field is W_g(x) = S W(Mx) with M the reflection across the face line
       // (so its gradient is S grad W M); S = I on a transmissive boundary, and
       // on a wall S reflects the momentum vector by M as well.
+      // A prescribed state is a ghost holding that state, flat (zero
+      // derivative averages).
       c.t = F.ghost;
       c.area = M.area[k];
       for (int q = 0; q < m; ++q) {
@@ -367,7 +398,11 @@ void stencil_of(const Mesh& M, const T* s, int64_t k, StencilCell<T> st[4]) {
         c.V[q] = st[0].V[q] - T(2.0 * F.nx) * vn;
         c.Y[q] = st[0].Y[q] - T(2.0 * F.ny) * vn;
       }
-      if (F.wall) reflect_momentum(F.nx, F.ny, c.W, c.V, c.Y);
+      if (F.kind == kBndWall) reflect_momentum(F.nx, F.ny, c.W, c.V, c.Y);
+      if (prescribed(F)) {
+        boundary_state(M, F, c.W);
+        for (int q = 0; q < m; ++q) c.V[q] = c.Y[q] = T(0.0);
+      }
     }
   }
 }
@@ -665,7 +700,11 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
       T aK = spectral_radius(o, Wbar, F.nx, F.ny);
       T aN = spectral_radius(o, Wbn, F.nx, F.ny);
       alpha = k < F.nb ? maxfirst(aK, aN) : maxfirst(aN, aK);
-    } else if (F.wall) {
+    } else if (prescribed(F)) {
+      T Wg[4];
+      boundary_state(M, F, Wg);
+      alpha = maxfirst(spectral_radius(o, Wbar, F.nx, F.ny), spectral_radius(o, Wg, F.nx, F.ny));
+    } else if (F.kind == kBndWall) {
       // the ghost average is the reflected cell average: the same spectral radius
       T Wg[4];
       for (int q = 0; q < m; ++q) Wg[q] = Wbar[q];
@@ -698,7 +737,8 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
           Wi[q] = Di[0][q] + T(tau) * it[q] + T(0.5 * tau * tau) * itt[q];
           We[q] = F.nb >= 0 ? De[0][q] + T(tau) * et[q] + T(0.5 * tau * tau) * ett[q] : Wi[q];
         }
-        if (F.nb < 0 && F.wall) reflect_momentum(F.nx, F.ny, We);
+        if (F.nb < 0 && F.kind == kBndWall) reflect_momentum(F.nx, F.ny, We);
+        if (F.nb < 0 && prescribed(F)) boundary_state(M, F, We);
       };
       const TimeRule& rule = kTimeRules[o.time_rule == 1 ? 1 : 0];
       for (int sN = 0; sN < rule.n; ++sN) {
@@ -857,17 +897,26 @@ int build_mesh(Mesh& M, const double* nodes, int64_t nn, const int32_t* tris, in
         F.nb = -1;
         F.nb_face = -1;
         F.sx = F.sy = 0.0;
-        // on a wall: the face lies on a box side whose bit is set in o.walls
+        // kind: the first region holding the face midpoint, else a wall
+        // when the face lies on a box side whose bit is set in o.walls
         {
           const double mx = 0.5 * (t.x[f] + t.x[f1]), my = 0.5 * (t.y[f] + t.y[f1]);
           const double tol = 1e-9 * std::max(Lx, Ly);
-          const bool on[4] = {std::fabs(mx - o.box[0]) < tol && std::fabs(ex) < tol,
-                              std::fabs(mx - o.box[1]) < tol && std::fabs(ex) < tol,
-                              std::fabs(my - o.box[2]) < tol && std::fabs(ey) < tol,
-                              std::fabs(my - o.box[3]) < tol && std::fabs(ey) < tol};
-          F.wall = false;
-          for (int sd = 0; sd < 4; ++sd)
-            if (on[sd] && ((o.walls >> sd) & 1)) F.wall = true;
+          F.mx = mx;
+          F.kind = -1;
+          for (int r = 0; r < o.nreg && F.kind < 0; ++r)
+            if (mx >= o.reg_box[r][0] - tol && mx <= o.reg_box[r][1] + tol && my >= o.reg_box[r][2] - tol &&
+                my <= o.reg_box[r][3] + tol)
+              F.kind = o.reg_kind[r];
+          if (F.kind < 0) {
+            const bool on[4] = {std::fabs(mx - o.box[0]) < tol && std::fabs(ex) < tol,
+                                std::fabs(mx - o.box[1]) < tol && std::fabs(ex) < tol,
+                                std::fabs(my - o.box[2]) < tol && std::fabs(ey) < tol,
+                                std::fabs(my - o.box[3]) < tol && std::fabs(ey) < tol};
+            F.kind = kBndTrans;
+            for (int sd = 0; sd < 4; ++sd)
+              if (on[sd] && ((o.walls >> sd) & 1)) F.kind = kBndWall;
+          }
         }
         // mirror image of K across the face line
         for (int v = 0; v < 3; ++v) {
@@ -882,7 +931,8 @@ int build_mesh(Mesh& M, const double* nodes, int64_t nn, const int32_t* tris, in
         continue;
       }
       auto other = lst[0].first == k && lst[0].second == f ? lst[1] : lst[0];
-      F.wall = false;
+      F.kind = kBndTrans;
+      F.mx = 0.5 * (t.x[f] + t.x[f1]);
       F.nb = static_cast<int>(other.first);
       F.nb_face = other.second;
       // translation from the neighbour's frame: compare the shared vertices
@@ -920,6 +970,11 @@ struct or_opts {
   int time_rule;
   double deriv_weight;
   int walls;
+  int nreg;
+  int reg_kind[8];
+  double reg_box[8][4];
+  double bstate[2][4];
+  double shock_x0, shock_speed;
 };
 
 void* or_mesh_new(const double* nodes, int64_t nn, const int32_t* tris, int64_t nt, const or_opts* o,
@@ -938,6 +993,17 @@ void* or_mesh_new(const double* nodes, int64_t nn, const int32_t* tris, int64_t 
   M->o.time_rule = o->time_rule;
   M->o.deriv_weight = o->deriv_weight;
   M->o.walls = (o->eq == 2 && o->bc != 0) ? o->walls : 0;
+  M->o.nreg = o->bc != 0 ? std::max(0, std::min(8, o->nreg)) : 0;
+  for (int r = 0; r < 8; ++r) {
+    M->o.reg_kind[r] = o->reg_kind[r];
+    // walls exist for the Euler equations only
+    if (o->eq != 2 && M->o.reg_kind[r] == kBndWall) M->o.reg_kind[r] = kBndTrans;
+    for (int i = 0; i < 4; ++i) M->o.reg_box[r][i] = o->reg_box[r][i];
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < 4; ++i) M->o.bstate[a][i] = o->bstate[a][i];
+  M->o.shock_x0 = o->shock_x0;
+  M->o.shock_speed = o->shock_speed;
   int st = build_mesh(*M, nodes, nn, tris, nt);
   if (status) *status = st;
   if (st != 0) {
@@ -980,6 +1046,15 @@ int or_geometry(void* h, double* area, double* cx, double* cy, double* face_out)
   return 0;
 }
 
+// Boundary kind of every face, [N][3] (kBnd*: 0 transmissive, 1 wall,
+// 2 state A, 3 state B, 4 moving switch), -1 for interior faces.
+int or_face_kinds(void* h, int32_t* out) {
+  Mesh* M = static_cast<Mesh*>(h);
+  for (int64_t k = 0; k < M->N; ++k)
+    for (int f = 0; f < 3; ++f) out[k * 3 + f] = M->face[k][f].nb >= 0 ? -1 : M->face[k][f].kind;
+  return 0;
+}
+
 // Triangle vertices in the cell's own (unwrapped, counter-clockwise) frame, [N][3][2].
 int or_cell_vertices(void* h, double* out) {
   Mesh* M = static_cast<Mesh*>(h);
@@ -991,21 +1066,36 @@ int or_cell_vertices(void* h, double* out) {
   return 0;
 }
 
+// Time t_n of the state given to the next or_step / or_step_cells (and the
+// start time of or_run / or_jvp); only moving boundary states depend on it.
+int or_set_time(void* h, double t) {
+  Mesh* M = static_cast<Mesh*>(h);
+  M->time = t;
+  M->t_bnd = t;
+  return 0;
+}
+
 // One step: s_in, s_out are [3][m][N] (averages of W, W_x, W_y).
 int or_step(void* h, const double* s_in, double* s_out, double dt, int nthr) {
-  return step_all(*static_cast<Mesh*>(h), s_in, s_out, dt, nthr);
+  Mesh* M = static_cast<Mesh*>(h);
+  M->t_bnd = M->time + 0.5 * dt;
+  return step_all(*M, s_in, s_out, dt, nthr);
 }
 
 int or_step_cells(void* h, const double* s_in, const int64_t* cells, int64_t nc, double* out, double dt,
                   int nthr) {
-  return step_cells(*static_cast<Mesh*>(h), s_in, cells, nc, out, dt, nthr);
+  Mesh* M = static_cast<Mesh*>(h);
+  M->t_bnd = M->time + 0.5 * dt;
+  return step_cells(*M, s_in, cells, nc, out, dt, nthr);
 }
 
-// nsteps steps in place with a fixed dt.
+// nsteps steps in place with a fixed dt, from t_n = the mesh's time (which
+// is left unchanged).
 int or_run(void* h, double* s, double dt, int64_t nsteps, int nthr) {
   Mesh* M = static_cast<Mesh*>(h);
   std::vector<double> tmp(3 * M->m * M->N);
   for (int64_t n = 0; n < nsteps; ++n) {
+    M->t_bnd = M->time + (double(n) + 0.5) * dt;
     int st = step_all(*M, s, tmp.data(), dt, nthr);
     if (st) return st;
     std::memcpy(s, tmp.data(), tmp.size() * sizeof(double));
@@ -1020,6 +1110,7 @@ int or_jvp(void* h, double* s, double* ds, double dt, int64_t nsteps, int nthr) 
   std::vector<Dual> a(n), b(n);
   for (size_t i = 0; i < n; ++i) a[i] = Dual(s[i], ds[i]);
   for (int64_t k = 0; k < nsteps; ++k) {
+    M->t_bnd = M->time + (double(k) + 0.5) * dt;
     int st = step_all(*M, a.data(), b.data(), dt, nthr);
     if (st) return st;
     std::swap(a, b);

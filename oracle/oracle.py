@@ -12,14 +12,20 @@ _SRC = os.path.join(_HERE, "hwe_oracle.cpp")
 _LIB = os.path.join(_HERE, "libhwe_oracle.so")
 
 OPTS_DEFAULT = dict(adv=(1.0, 1.0), gas_gamma=1.4, lin_w=(0.94, 0.02, 0.02, 0.02), eps=1e-8,
-                    linear_only=0, positivity=0, time_rule=0, deriv_weight=1.0, walls=0)
+                    linear_only=0, positivity=0, time_rule=0, deriv_weight=1.0, walls=0,
+                    regions=(), states=((0.0,) * 4, (0.0,) * 4), shock=(0.0, 0.0))
+
+# boundary kinds of a region
+BND_KINDS = {"transmissive": 0, "wall": 1, "A": 2, "B": 3, "moving": 4}
 
 
 class _Opts(C.Structure):
     _fields_ = [("eq", C.c_int), ("bc", C.c_int), ("box", C.c_double * 4), ("adv", C.c_double * 2),
                 ("gas_gamma", C.c_double), ("lin_w", C.c_double * 4), ("eps", C.c_double),
                 ("linear_only", C.c_int), ("positivity", C.c_int), ("time_rule", C.c_int),
-                ("deriv_weight", C.c_double), ("walls", C.c_int)]
+                ("deriv_weight", C.c_double), ("walls", C.c_int), ("nreg", C.c_int),
+                ("reg_kind", C.c_int * 8), ("reg_box", (C.c_double * 4) * 8), ("bstate", (C.c_double * 4) * 2),
+                ("shock_x0", C.c_double), ("shock_speed", C.c_double)]
 
 
 def build_oracle(force: bool = True) -> str:
@@ -49,9 +55,11 @@ def _load():
                                     C.POINTER(C.c_int32)]
         L.or_geometry.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.or_cell_vertices.argtypes = [C.c_void_p, dp]
+        L.or_face_kinds.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
         L.or_step.argtypes = [C.c_void_p, dp, dp, C.c_double, C.c_int]
         L.or_step_cells.argtypes = [C.c_void_p, dp, C.POINTER(C.c_int64), C.c_int64, dp, C.c_double, C.c_int]
         L.or_run.argtypes = [C.c_void_p, dp, C.c_double, C.c_int64, C.c_int]
+        L.or_set_time.argtypes = [C.c_void_p, C.c_double]
         L.or_jvp.argtypes = [C.c_void_p, dp, dp, C.c_double, C.c_int64, C.c_int]
         L.or_recon_cell.argtypes = [C.c_void_p, dp, C.c_int64, dp, dp, dp, dp]
         L.or_eval_recon.argtypes = [C.c_void_p, dp, C.c_int64, dp, C.c_int64, dp]
@@ -86,6 +94,17 @@ def _opts(eq, bc=0, box=(0.0, 1.0, 0.0, 1.0), **kw):
     s.time_rule = int(o["time_rule"])
     s.deriv_weight = float(o["deriv_weight"])
     s.walls = int(o["walls"])
+    regs = list(o["regions"])
+    if len(regs) > 8:
+        raise ValueError("at most 8 boundary regions")
+    s.nreg = len(regs)
+    for r, (kind, rect) in enumerate(regs):
+        s.reg_kind[r] = BND_KINDS[kind]
+        s.reg_box[r][:] = [float(v) for v in rect]
+    for a in range(2):
+        st = list(o["states"][a]) + [0.0] * (4 - len(o["states"][a]))
+        s.bstate[a][:] = [float(v) for v in st]
+    s.shock_x0, s.shock_speed = float(o["shock"][0]), float(o["shock"][1])
     return s
 
 
@@ -117,6 +136,9 @@ class OracleMesh:
     def from_workload(cls, wl, **kw):
         if getattr(wl, "walls", 0) and "walls" not in kw:
             kw["walls"] = wl.walls
+        for key in ("regions", "states", "shock"):
+            if getattr(wl, key, None) and key not in kw:
+                kw[key] = getattr(wl, key)
         return cls(wl.mesh.nodes, wl.mesh.tris, wl.eq, wl.bc, wl.mesh.box, adv=wl.adv, **kw)
 
     def __del__(self):
@@ -134,6 +156,12 @@ class OracleMesh:
         return dict(area=area, cx=cx, cy=cy, normal=faces[..., 0:2], length=faces[..., 2],
                     nbr=faces[..., 3].astype(np.int64), shift=faces[..., 4:6])
 
+    def face_kinds(self):
+        """(N, 3) int32: boundary kind of each face (BND_KINDS values), -1 inside."""
+        out = np.empty((self.N, 3), dtype=np.int32)
+        _lib.or_face_kinds(self._h, out.ctypes.data_as(C.POINTER(C.c_int32)))
+        return out
+
     def cell_vertices(self):
         out = np.empty((self.N, 3, 2))
         _lib.or_cell_vertices(self._h, _p(out))
@@ -146,43 +174,49 @@ class OracleMesh:
         return s
 
     # ------------------------------------------------------------- the step
-    def step(self, s, dt, nthreads=0):
+    def step(self, s, dt, nthreads=0, t=0.0):
+        """One step from the state s at time t (t matters for moving boundary states only)."""
         s = self._check_state(s)
         out = np.empty_like(s)
+        _lib.or_set_time(self._h, float(t))
         st = _lib.or_step(self._h, _p(s), _p(out), float(dt), int(nthreads))
         if st:
             raise RuntimeError(f"oracle step failed ({st})")
         return out
 
-    def step_cells(self, s, cells, dt, nthreads=0):
+    def step_cells(self, s, cells, dt, nthreads=0, t=0.0):
         s = self._check_state(s)
         cells = np.ascontiguousarray(cells, dtype=np.int64)
         out = np.empty((3, self.m, cells.size))
+        _lib.or_set_time(self._h, float(t))
         st = _lib.or_step_cells(self._h, _p(s), cells.ctypes.data_as(C.POINTER(C.c_int64)), cells.size,
                                 _p(out), float(dt), int(nthreads))
         if st:
             raise RuntimeError(f"oracle step_cells failed ({st})")
         return out
 
-    def run(self, s, dt, nsteps, nthreads=0):
+    def run(self, s, dt, nsteps, nthreads=0, t=0.0):
+        """nsteps steps of size dt from the state s at time t."""
         s = self._check_state(s).copy()
+        _lib.or_set_time(self._h, float(t))
         st = _lib.or_run(self._h, _p(s), float(dt), int(nsteps), int(nthreads))
         if st:
             raise RuntimeError(f"oracle run failed ({st})")
         return s
 
     def run_to(self, s, T, dt, nthreads=0):
-        """Steps of size dt with the last one clipped so that the run ends at T."""
+        """Steps of size dt from t = 0 with the last one clipped so that the run ends at T."""
         n = int(np.floor(T / dt + 1e-12))
         s = self.run(s, dt, n, nthreads)
         rem = T - n * dt
         if rem > 1e-14 * T:
-            s = self.step(s, rem, nthreads)
+            s = self.step(s, rem, nthreads, t=n * dt)
         return s
 
-    def jvp(self, s, ds, dt, nsteps, nthreads=0):
+    def jvp(self, s, ds, dt, nsteps, nthreads=0, t=0.0):
         s = self._check_state(s).copy()
         ds = self._check_state(ds).copy()
+        _lib.or_set_time(self._h, float(t))
         st = _lib.or_jvp(self._h, _p(s), _p(ds), float(dt), int(nsteps), int(nthreads))
         if st:
             raise RuntimeError(f"oracle jvp failed ({st})")

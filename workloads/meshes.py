@@ -93,3 +93,88 @@ def unwrapped_triangles(mesh: Mesh2D) -> np.ndarray:
         d -= L * np.round(d / L)
         P = P[:, :1, :] + d
     return P
+
+
+def _boundary_nodes(tris: np.ndarray, n_nodes: int) -> np.ndarray:
+    """Mask of the nodes on edges that belong to one triangle only."""
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])
+    e.sort(axis=1)
+    uniq, cnt = np.unique(e, axis=0, return_counts=True)
+    mask = np.zeros(n_nodes, dtype=bool)
+    mask[uniq[cnt == 1].ravel()] = True
+    return mask
+
+
+def _jitter_interior(nodes, tris, jitter, seed, hx, hy):
+    """Uniform offsets in [-f h, f h] per coordinate, drawn as one (V, 2) array in
+    node order, applied to the nodes on no boundary edge."""
+    if not jitter or jitter <= 0.0:
+        return nodes
+    rng = np.random.default_rng(seed)
+    off = rng.uniform(-1.0, 1.0, size=nodes.shape)
+    inner = ~_boundary_nodes(tris, nodes.shape[0])
+    out = nodes.copy()
+    out[inner, 0] += off[inner, 0] * jitter * hx
+    out[inner, 1] += off[inner, 1] * jitter * hy
+    return out
+
+
+def forward_step_mesh(n: int, jitter: float = 0.0, seed: int | None = None) -> Mesh2D:
+    """The wind tunnel (0, 3) x (0, 1) with the step [0.6, 3] x [0, 0.2] removed:
+    split squares of side 1/n (n a multiple of 5, so the step corner is a node),
+    interior nodes jittered (nodes on the tunnel walls, the step, the inlet and
+    the outlet stay on the grid).  Nodes are renumbered to the ones in use."""
+    if n % 5 or n < 5:
+        raise ValueError("n must be a positive multiple of 5")
+    full = split_square_mesh((3 * n, n), (0.0, 3.0, 0.0, 1.0), 0.0, None, periodic=False)
+    cen = full.nodes[full.tris].mean(axis=1)
+    keep = ~((cen[:, 0] > 0.6) & (cen[:, 1] < 0.2))
+    tris = full.tris[keep]
+    used = np.unique(tris)
+    remap = -np.ones(full.nodes.shape[0], dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    tris = remap[tris].astype(np.int32)
+    nodes = full.nodes[used]
+    h = 1.0 / n
+    nodes = _jitter_interior(nodes, tris, jitter, seed, h, h)
+    return Mesh2D(nodes=nodes, tris=tris, box=(0.0, 3.0, 0.0, 1.0), periodic=False, n=3 * n, h=h)
+
+
+def wedge_mesh(nx: int, ny: int, jitter: float = 0.0, seed: int | None = None,
+               x0: float = -1.0 / 6.0, x1: float = 2.5, top: float = 2.0,
+               angle_deg: float = 30.0) -> Mesh2D:
+    """The region over a wedge: x in (x0, x1), y from b(x) to ``top`` with
+    b(x) = 0 for x <= 0 and x tan(angle) beyond.  A mapped grid of nx columns
+    (x = 0 must be a grid line: nx (0 - x0) / (x1 - x0) an integer) and ny rows
+    evenly spaced between b(x) and top; each quadrilateral is split along the
+    diagonal from its lower-left corner.  Interior nodes are jittered by up to
+    f times the local spacing."""
+    k = nx * (0.0 - x0) / (x1 - x0)
+    if abs(k - round(k)) > 1e-9:
+        raise ValueError("x = 0 must be a grid line")
+    t = np.tan(np.radians(angle_deg))
+    xs = x0 + (x1 - x0) * np.arange(nx + 1) / nx
+    xs[int(round(k))] = 0.0
+    b = np.where(xs > 0.0, xs * t, 0.0)
+    jj, ii = np.meshgrid(np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    X = xs[ii]
+    Y = b[ii] + (top - b[ii]) * jj / ny
+    nodes = np.stack([X.ravel(), Y.ravel()], axis=1).astype(np.float64)
+    J, I = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    I = I.ravel()
+    J = J.ravel()
+    nid = lambda i, j: j * (nx + 1) + i  # noqa: E731
+    a, bb, c, d = nid(I, J), nid(I + 1, J), nid(I + 1, J + 1), nid(I, J + 1)
+    tris = np.empty((2 * nx * ny, 3), dtype=np.int32)
+    tris[0::2] = np.stack([a, bb, c], axis=1)
+    tris[1::2] = np.stack([a, c, d], axis=1)
+    if jitter and jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        off = rng.uniform(-1.0, 1.0, size=(ny + 1, nx + 1, 2))
+        inner = (ii >= 1) & (ii <= nx - 1) & (jj >= 1) & (jj <= ny - 1)
+        hx = (x1 - x0) / nx
+        hy = (top - b[ii]) / ny
+        Xj = X + np.where(inner, off[..., 0] * jitter * hx, 0.0)
+        Yj = Y + np.where(inner, off[..., 1] * jitter * hy, 0.0)
+        nodes = np.stack([Xj.ravel(), Yj.ravel()], axis=1).astype(np.float64)
+    return Mesh2D(nodes=nodes, tris=tris, box=(x0, x1, 0.0, top), periodic=False, n=nx, h=(x1 - x0) / nx)

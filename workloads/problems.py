@@ -22,7 +22,7 @@ from typing import Callable
 
 import numpy as np
 
-from .meshes import Mesh2D, split_square_mesh, unwrapped_triangles
+from .meshes import Mesh2D, forward_step_mesh, split_square_mesh, unwrapped_triangles, wedge_mesh
 
 EQ_ADVECTION, EQ_BURGERS, EQ_EULER = 0, 1, 2
 GAMMA_GAS = 1.4
@@ -261,6 +261,13 @@ class Workload:
     adv: tuple = (1.0, 1.0)
     extra: dict = field(default_factory=dict)
     walls: int = 0                      # bit s: box side s (x0, x1, y0, y1) is a reflective wall
+    # boundary regions, first match wins: (kind, (x0, x1, y0, y1)) with kind one of
+    # "transmissive", "wall", "A", "B" (prescribed states) or "moving" (A where the
+    # face midpoint has x < shock[0] + shock[1] t, else B); faces in no region
+    # follow `walls`
+    regions: tuple = ()
+    states: tuple = ()                  # (A, B) conservative states of the prescribed boundaries
+    shock: tuple = ()                   # (x0, speed) of the moving switch between A and B
 
     @property
     def bc(self) -> int:
@@ -337,6 +344,80 @@ def shock_tube_average_states(mesh: Mesh2D, x_split, left, right) -> np.ndarray:
     return out
 
 
+def _split_halfplane(poly, a, b, c):
+    """Split a convex polygon by the line a x + b y = c: (part < c, part >= c)."""
+    lo, hi = [], []
+    n = len(poly)
+    for i in range(n):
+        A = poly[i]
+        B = poly[(i + 1) % n]
+        fa = a * A[0] + b * A[1] - c
+        fb = a * B[0] + b * B[1] - c
+        (hi if fa >= 0 else lo).append(A)
+        if (fa >= 0) != (fb >= 0):
+            s = fa / (fa - fb)
+            P = (A[0] + s * (B[0] - A[0]), A[1] + s * (B[1] - A[1]))
+            lo.append(P)
+            hi.append(P)
+    return lo, hi
+
+
+def piecewise_average_states(mesh: Mesh2D, f: Callable, lines, t: float = 0.0) -> np.ndarray:
+    """[3][m][N] cell averages of f, f_x and f_y for f smooth except across the
+    straight lines a x + b y = c in ``lines``.  Cells that a line crosses are cut
+    into pieces, each integrated with the triangle rule on a fan of triangles;
+    the derivative averages are (1/|K|) times the boundary integral of f n,
+    with the edges split where the lines cross them (so the jumps count)."""
+    out = cell_average_states(mesh, f, t)
+    P = unwrapped_triangles(mesh)
+    cut = np.zeros(P.shape[0], dtype=bool)
+    for a, b, c in lines:
+        v = a * P[:, :, 0] + b * P[:, :, 1] - c
+        cut |= (v.min(axis=1) < 0) & (v.max(axis=1) > 0)
+    for k in np.nonzero(cut)[0]:
+        tri = [tuple(P[k, j]) for j in range(3)]
+        area = _poly_area(tri)
+        pieces = [tri]
+        for a, b, c in lines:
+            nxt = []
+            for pc in pieces:
+                for part in _split_halfplane(pc, a, b, c):
+                    if len(part) >= 3 and _poly_area(part) > 0.0:
+                        nxt.append(part)
+            pieces = nxt
+        acc = 0.0
+        for pc in pieces:
+            Q0 = np.array(pc[0])
+            for j in range(1, len(pc) - 1):
+                Q1, Q2 = np.array(pc[j]), np.array(pc[j + 1])
+                ar = 0.5 * ((Q1[0] - Q0[0]) * (Q2[1] - Q0[1]) - (Q1[1] - Q0[1]) * (Q2[0] - Q0[0]))
+                X = Q0[None, :] + _TRI_A1[:, None] * (Q1 - Q0)[None, :] + _TRI_A2[:, None] * (Q2 - Q0)[None, :]
+                acc = acc + ar * np.einsum("qm,q->m", f(X[:, 0], X[:, 1], t), _TRI_W)
+        out[0, :, k] = acc / area
+        gx = 0.0
+        gy = 0.0
+        for j in range(3):
+            A, B = np.array(tri[j]), np.array(tri[(j + 1) % 3])
+            ts = [0.0, 1.0]
+            for a, b, c in lines:
+                fa = a * A[0] + b * A[1] - c
+                fb = a * B[0] + b * B[1] - c
+                if fa != fb:
+                    s_ = fa / (fa - fb)
+                    if 0.0 < s_ < 1.0:
+                        ts.append(s_)
+            ts.sort()
+            line = 0.0
+            for t0, t1 in zip(ts[:-1], ts[1:]):
+                Y = A[None, :] + (t0 + (t1 - t0) * _GL_T)[:, None] * (B - A)[None, :]
+                line = line + (t1 - t0) * np.einsum("qm,q->m", f(Y[:, 0], Y[:, 1], t), _GL_W)
+            gx = gx + line * (B[1] - A[1])
+            gy = gy - line * (B[0] - A[0])
+        out[1, :, k] = gx / area
+        out[2, :, k] = gy / area
+    return out
+
+
 # Shock tubes on a strip with reflective walls at y = y0, y1 (a 1-D Riemann
 # problem in 2-D, so that the exact solution is the 1-D one): the Lax problem
 # of Sec. 4 (states (rho, u, p) = (0.445, 0.698, 3.528) | (0.5, 0, 0.571) split
@@ -356,6 +437,134 @@ def shock_tube_workload(name="lax", nx=200, height=0.06, jitter=0.1, seed=8, cfl
     mesh = split_square_mesh((nx, ny), box, jitter, seed, periodic=False)
     return Workload(name, EQ_EULER, 4, mesh, shock_tube_average_states(mesh, 0.0, left, right), T, cfl, None,
                     extra=dict(left=left, right=right, x_split=0.0), walls=0b1100)
+
+
+def _two_state(WA, WB, a, b, c):
+    """Pointwise data: conservative WA where a x + b y < c, WB elsewhere."""
+    WA, WB = np.asarray(WA, dtype=np.float64), np.asarray(WB, dtype=np.float64)
+
+    def f(x, y, t):
+        side = (a * np.asarray(x) + b * np.asarray(y) - c) < 0
+        return np.where(side[..., None], WA, WB)
+    return f
+
+
+def _strip(x0, x1, height, nx, jitter, seed):
+    ny = max(3, int(round(height * nx / (x1 - x0))))
+    hy = 0.5 * ny * (x1 - x0) / nx
+    return split_square_mesh((nx, ny), (x0, x1, -hy, hy), jitter, seed, periodic=False)
+
+
+# The Shu-Osher problem of Sec. 4: a Mach 3 shock at x = -4 running into a
+# density sine wave on (-5, 5) x (-0.1, 0.1), T = 1.8.  Prescribed inflow
+# state on the left, transmissive outflow on the right, walls on the long sides.
+SHU_OSHER_LEFT = (3.857143, 2.629369, 0.0, 10.333333)
+
+
+def shu_osher_workload(nx=300, height=0.2, jitter=0.1, seed=9, cfl=0.3, T=1.8):
+    mesh = _strip(-5.0, 5.0, height, nx, jitter, seed)
+    WL = _prim_to_cons(*map(np.float64, SHU_OSHER_LEFT))
+
+    def f(x, y, t):
+        x = np.asarray(x)
+        rho = 1.0 + 0.2 * np.sin(5.0 * x)
+        right = _prim_to_cons(rho, np.zeros_like(x), np.zeros_like(x), np.ones_like(x))
+        return np.where((x < -4.0)[..., None], WL, right)
+    st = piecewise_average_states(mesh, f, [(1.0, 0.0, -4.0)])
+    x0, y0, y1 = mesh.box[0], mesh.box[2], mesh.box[3]
+    return Workload("shu_osher", EQ_EULER, 4, mesh, st, T, cfl, None, walls=0b1100,
+                    regions=(("A", (x0, x0, y0, y1)),), states=(tuple(WL), tuple(WL)), shock=(0.0, 0.0))
+
+
+# Interacting blast waves of Sec. 4 on (0, 1) x (-0.0075, 0.0075), walls all
+# round, T = 0.038: rho = 1, u = v = 0, p = 1000 | 0.01 | 100 split at 0.1, 0.9.
+def blast_wave_workload(nx=400, height=0.015, jitter=0.1, seed=10, cfl=0.3, T=0.038):
+    mesh = _strip(0.0, 1.0, height, nx, jitter, seed)
+
+    def f(x, y, t):
+        x = np.asarray(x)
+        p = np.where(x < 0.1, 1000.0, np.where(x < 0.9, 0.01, 100.0))
+        z = np.zeros_like(x)
+        return _prim_to_cons(np.ones_like(x), z, z, p)
+    st = piecewise_average_states(mesh, f, [(1.0, 0.0, 0.1), (1.0, 0.0, 0.9)])
+    return Workload("blast_wave", EQ_EULER, 4, mesh, st, T, cfl, None, walls=0b1111)
+
+
+# Double Mach reflection of Sec. 4 on (0, 4) x (0, 1), T = 0.2: a Mach 10 shock
+# through x = 1/6 at 60 degrees to the bottom wall.  State A (behind the shock,
+# the conservative values printed in the paper) where y >= sqrt(3) (x - 1/6),
+# B = (1.4, 0, 0, 2.5) ahead.  Boundaries: A on the left and on the bottom for
+# x < 1/6, wall on the rest of the bottom, transmissive on the right, and on
+# the top the exact shock position x_s(t) = 1/6 + (1 + 20 t) / sqrt(3).
+DMR_A = (8.0, 57.1597, -33.0012, 563.544)
+DMR_B = (1.4, 0.0, 0.0, 2.5)
+
+
+def double_mach_workload(n=60, jitter=0.1, seed=11, cfl=0.3, T=0.2):
+    """n squares per unit length: 4n x n split squares (8 n^2 triangles); n a
+    multiple of 6 puts x = 1/6 on the grid."""
+    mesh = split_square_mesh((4 * n, n), (0.0, 4.0, 0.0, 1.0), jitter, seed, periodic=False)
+    r3 = np.sqrt(3.0)
+    st = piecewise_average_states(mesh, _two_state(DMR_A, DMR_B, r3, -1.0, r3 / 6.0), [(r3, -1.0, r3 / 6.0)])
+    regions = (("A", (0.0, 1.0 / 6.0, 0.0, 0.0)), ("wall", (1.0 / 6.0, 4.0, 0.0, 0.0)),
+               ("moving", (0.0, 4.0, 1.0, 1.0)), ("A", (0.0, 0.0, 0.0, 1.0)))
+    return Workload("double_mach", EQ_EULER, 4, mesh, st, T, cfl, None, regions=regions,
+                    states=(DMR_A, DMR_B), shock=(1.0 / 6.0 + 1.0 / r3, 20.0 / r3))
+
+
+# Double Mach reflection over a 30-degree wedge of Sec. 4 on (-1/6, 2.5) x (0, 2),
+# T = 0.2: a Mach 10 shock at x = 0 moving right; (rho, u, v, p) = (8, 8.25, 0,
+# 116.5) behind it, (1.4, 0, 0, 1) ahead.  Boundaries: behind-shock state on the
+# left and on the bottom for x < 0, transmissive on the right, the exact shock
+# position x_s(t) = 10 t on the top, walls elsewhere (the wedge).
+WEDGE_A = (8.0, 8.25, 0.0, 116.5)
+WEDGE_B = (1.4, 0.0, 0.0, 1.0)
+
+
+def wedge_workload(nx=160, ny=120, jitter=0.1, seed=12, cfl=0.3, T=0.2):
+    """nx a multiple of 16 puts the wedge tip x = 0 on the grid."""
+    mesh = wedge_mesh(nx, ny, jitter, seed)
+    WA = tuple(_prim_to_cons(*map(np.float64, WEDGE_A)))
+    WB = tuple(_prim_to_cons(*map(np.float64, WEDGE_B)))
+    st = piecewise_average_states(mesh, _two_state(WA, WB, 1.0, 0.0, 0.0), [(1.0, 0.0, 0.0)])
+    x0, x1, y0, y1 = mesh.box
+    regions = (("A", (x0, 0.0, 0.0, 0.0)), ("A", (x0, x0, y0, y1)), ("moving", (x0, x1, y1, y1)),
+               ("transmissive", (x1, x1, y0, y1)), ("wall", (x0, x1, y0, y1)))
+    return Workload("wedge", EQ_EULER, 4, mesh, st, T, cfl, None, regions=regions, states=(WA, WB),
+                    shock=(0.0, 10.0))
+
+
+# The forward-facing step of Sec. 4: a Mach 3 wind tunnel (0, 3) x (0, 1) with a
+# step of height 0.2 from x = 0.6, uniform (1.4, 3, 0, 1) initially and at the
+# inlet, transmissive outlet, walls elsewhere; T = 4.
+STEP_A = (1.4, 3.0, 0.0, 1.0)
+
+
+def forward_step_workload(n=40, jitter=0.1, seed=13, cfl=0.3, T=4.0):
+    mesh = forward_step_mesh(n, jitter, seed)
+    WA = tuple(_prim_to_cons(*map(np.float64, STEP_A)))
+    st = np.zeros((3, 4, mesh.n_cells))
+    st[0] = np.asarray(WA)[:, None]
+    regions = (("A", (0.0, 0.0, 0.0, 1.0)), ("transmissive", (3.0, 3.0, 0.2, 1.0)),
+               ("wall", (0.0, 3.0, 0.0, 1.0)))
+    return Workload("forward_step", EQ_EULER, 4, mesh, st, T, cfl, None, regions=regions, states=(WA, WA),
+                    shock=(0.0, 0.0))
+
+
+# A planar Mach 10 shock (the wedge problem's states) running along a strip
+# (0, 1) x (0, 0.1) from x = 0.2 at speed 10: an exact travelling solution,
+# with the behind-shock state prescribed on the left, transmissive on the right
+# and the moving switch on the long sides.
+def moving_shock_workload(nx=100, height=0.1, jitter=0.1, seed=14, cfl=0.3, T=0.05):
+    ny = max(3, int(round(height * nx)))
+    mesh = split_square_mesh((nx, ny), (0.0, 1.0, 0.0, ny / nx), jitter, seed, periodic=False)
+    WA = tuple(_prim_to_cons(*map(np.float64, WEDGE_A)))
+    WB = tuple(_prim_to_cons(*map(np.float64, WEDGE_B)))
+    st = piecewise_average_states(mesh, _two_state(WA, WB, 1.0, 0.0, 0.2), [(1.0, 0.0, 0.2)])
+    x0, x1, y0, y1 = mesh.box
+    regions = (("A", (x0, x0, y0, y1)), ("moving", (x0, x1, y0, y0)), ("moving", (x0, x1, y1, y1)))
+    return Workload("moving_shock", EQ_EULER, 4, mesh, st, T, cfl, None, regions=regions, states=(WA, WB),
+                    shock=(0.2, 10.0), extra=dict(x_shock=lambda t: 0.2 + 10.0 * t))
 
 
 def perturbed_vortex_target_center(seed=5, sigma=0.3, base=(5.0, 5.0)):
