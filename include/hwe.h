@@ -55,6 +55,33 @@ typedef enum { HWE_ADVECTION = 0, HWE_BURGERS = 1, HWE_EULER = 2 } hwe_equation;
 typedef enum { HWE_BC_PERIODIC = 0, HWE_BC_TRANSMISSIVE = 1 } hwe_bc;
 typedef enum { HWE_FP64 = 0, HWE_MIXED = 1 } hwe_precision;
 
+/* Boundary kinds of a region (Sec. 4's boundary conditions on generated
+ * meshes).  HWE_BND_TRANSMISSIVE: outflow, the ghost cell is the mirror image
+ * of the cell with its state, the exterior value is the interior one.
+ * HWE_BND_WALL (Euler): reflective, as for opts.walls.  HWE_BND_STATE_A / _B:
+ * inflow, a prescribed state: the ghost cell holds it with zero derivative
+ * averages and it is the exterior value at every time node.
+ * HWE_BND_MOVING: state A where the face midpoint has
+ * x < shock_x0 + shock_speed * t, else state B, with t the middle of the step
+ * (the exact position of a shock meeting the boundary, as on the top of the
+ * double Mach reflection problems). */
+typedef enum {
+  HWE_BND_TRANSMISSIVE = 0,
+  HWE_BND_WALL = 1,
+  HWE_BND_STATE_A = 2,
+  HWE_BND_STATE_B = 3,
+  HWE_BND_MOVING = 4
+} hwe_bnd_kind;
+
+#define HWE_MAX_REGIONS 8
+
+typedef struct {
+  int32_t kind;   /* hwe_bnd_kind */
+  int32_t pad;
+  double box[4];  /* x0, x1, y0, y1: boundary faces whose midpoint lies in this
+                     closed rectangle (a side: x0 == x1 or y0 == y1) */
+} hwe_region;
+
 typedef struct {
   int32_t eq;             /* hwe_equation; linear advection u_t + a.grad u = 0,
                              Burgers (Example 4.1), Euler gamma-law gas (eq. (2d)) */
@@ -96,6 +123,17 @@ typedef struct {
                              boundary faces stay transmissive.  0 = no walls
                              (default).  hwe_step_adjoint rejects meshes with
                              walls */
+  int32_t n_regions;      /* HWE_BC_TRANSMISSIVE only: 0..HWE_MAX_REGIONS.  Each
+                             boundary face takes the kind of the first region
+                             that holds its midpoint (within 1e-9 of the box
+                             size); faces in no region follow `walls`.  Walls
+                             need HWE_EULER.  0 = none (default) */
+  int32_t pad_regions;
+  hwe_region regions[HWE_MAX_REGIONS];
+  double bstate[2][4];    /* states A and B of the prescribed kinds, conservative
+                             variables (m of the 4 entries used) */
+  double shock_x0;        /* HWE_BND_MOVING: switch position at t = 0 */
+  double shock_speed;     /* and its speed in x */
 } hwe_opts;
 
 /* Fill *o with the paper's defaults: linear weights 0.94/0.02/0.02/0.02
@@ -177,6 +215,12 @@ hwe_status hwe_step_adjoint_kept(hwe_mesh m, const double* wbar_n, const void* g
                                  const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n,
                                  void* lam_grad_n, double dt, void* stream);
 
+/* Time of the state handed to the following hwe_step / hwe_step_keep calls on
+ * this handle (default 0).  Only HWE_BND_MOVING faces depend on it: a step
+ * from time t with size dt evaluates them at t + dt/2.  Host-side; the value is
+ * taken when a step is launched. */
+hwe_status hwe_set_time(hwe_mesh m, double t);
+
 /* Largest stable step of the driver: dt = cfl * min_K r_K / max_K lambda_K
  * (r_K inradius, lambda_K the largest signal speed at the cell average).
  * Writes one double to device memory dt_dev. */
@@ -198,8 +242,9 @@ hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, voi
  * host-only handles).  which: 0 = p1 map [55][N] (rows: c1..c5 of the
  * zero-mean basis X, Y, X^2-Mxx, XY-Mxy, Y^2-Myy; columns: dW1..dW3, V0..V3,
  * Y0..Y3), 1 = centroid [2][N], 2 = area [N], 3 = moments [3][N],
- * 4 = neighbours [3][N] (as double; negative = boundary).  out is host double
- * with room for the stated size. */
+ * 4 = neighbours [3][N] (as double; negative = boundary), 5 = boundary kind
+ * of each face [3][N] (hwe_bnd_kind as double; -1 = interior face).  out is
+ * host double with room for the stated size. */
 hwe_status hwe_debug_host_array(hwe_mesh m, int32_t which, double* out);
 
 /* Per-kernel timing for measurement tools.  hwe_profile_begin arms HIP events

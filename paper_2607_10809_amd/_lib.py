@@ -13,6 +13,12 @@ STATUS = {0: "HWE_OK", -1: "HWE_EINVAL", -2: "HWE_EMESH", -3: "HWE_ESINGULAR", -
 EQUATIONS = {"advection": 0, "burgers": 1, "euler": 2}
 BCS = {"periodic": 0, "transmissive": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
+BND_KINDS = {"transmissive": 0, "wall": 1, "A": 2, "B": 3, "moving": 4}
+MAX_REGIONS = 8
+
+
+class HweRegion(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("box", C.c_double * 4)]
 
 
 class HweOpts(C.Structure):
@@ -20,7 +26,9 @@ class HweOpts(C.Structure):
                 ("box", C.c_double * 4), ("adv", C.c_double * 2), ("gas_gamma", C.c_double),
                 ("lin_w", C.c_double * 4), ("eps", C.c_double), ("device", C.c_int32),
                 ("positivity", C.c_int32), ("time_rule", C.c_int32), ("deriv_weight", C.c_double),
-                ("walls", C.c_int32)]
+                ("walls", C.c_int32), ("n_regions", C.c_int32), ("pad_regions", C.c_int32),
+                ("regions", HweRegion * MAX_REGIONS), ("bstate", (C.c_double * 4) * 2),
+                ("shock_x0", C.c_double), ("shock_speed", C.c_double)]
 
 
 class HweError(RuntimeError):
@@ -50,6 +58,7 @@ def load_library():
     L.hwe_step.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp]
     L.hwe_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_double, vp]
     L.hwe_step_keep.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp, vp]
+    L.hwe_set_time.argtypes = [vp, C.c_double]
     L.hwe_step_adjoint_kept.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp]
     L.hwe_max_dt.argtypes = [vp, vp, C.c_double, vp, vp]
     L.hwe_check_state.argtypes = [vp, vp, vp, vp]
@@ -59,8 +68,8 @@ def load_library():
     L.hwe_profile_end.argtypes = [vp, dp, C.POINTER(i32)]
     L.hwe_last_error.restype = C.c_char_p
     for name in ("hwe_opts_default", "hwe_mesh_init", "hwe_mesh_destroy", "hwe_mesh_info", "hwe_mesh_cell_perm",
-                 "hwe_step", "hwe_step_adjoint", "hwe_step_keep", "hwe_step_adjoint_kept", "hwe_max_dt",
-                 "hwe_check_state", "hwe_debug_recon", "hwe_debug_host_array", "hwe_profile_begin",
+                 "hwe_step", "hwe_step_adjoint", "hwe_step_keep", "hwe_step_adjoint_kept", "hwe_set_time",
+                 "hwe_max_dt", "hwe_check_state", "hwe_debug_recon", "hwe_debug_host_array", "hwe_profile_begin",
                  "hwe_profile_end"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -76,6 +85,6 @@ def check(status):
 def exported_symbols():
     """Names declared in include/hwe.h (for the export test)."""
     return ["hwe_opts_default", "hwe_mesh_init", "hwe_mesh_destroy", "hwe_mesh_info", "hwe_mesh_cell_perm",
-            "hwe_step", "hwe_step_adjoint", "hwe_step_keep", "hwe_step_adjoint_kept", "hwe_max_dt",
-            "hwe_check_state", "hwe_debug_recon", "hwe_debug_host_array", "hwe_profile_begin", "hwe_profile_end",
+            "hwe_step", "hwe_step_adjoint", "hwe_step_keep", "hwe_step_adjoint_kept", "hwe_set_time",
+            "hwe_max_dt", "hwe_check_state", "hwe_debug_recon", "hwe_debug_host_array", "hwe_profile_begin", "hwe_profile_end",
             "hwe_last_error"]

@@ -86,8 +86,34 @@ hwe_status hwe_opts_default(hwe_opts* o) {
   o->time_rule = 0;
   o->deriv_weight = 1.0;
   o->walls = 0;
+  o->n_regions = 0;
   return HWE_OK;
 }
+
+namespace {
+
+bool finite_value(double v) { return v == v && v < 1e300 && v > -1e300; }
+
+// Region list, prescribed states and the moving switch.
+bool regions_ok(const hwe_opts& o) {
+  if (o.n_regions < 0 || o.n_regions > HWE_MAX_REGIONS) return false;
+  if (o.n_regions > 0 && o.bc != HWE_BC_TRANSMISSIVE) return false;
+  for (int r = 0; r < o.n_regions; ++r) {
+    const hwe_region& g = o.regions[r];
+    if (g.kind < HWE_BND_TRANSMISSIVE || g.kind > HWE_BND_MOVING) return false;
+    if (g.kind == HWE_BND_WALL && o.eq != HWE_EULER) return false;
+    for (int k = 0; k < 4; ++k)
+      if (!finite_value(g.box[k])) return false;
+    if (!(g.box[0] <= g.box[1]) || !(g.box[2] <= g.box[3])) return false;
+  }
+  const int m = o.eq == HWE_EULER ? 4 : 1;
+  for (int a = 0; a < 2; ++a)
+    for (int q = 0; q < m; ++q)
+      if (!finite_value(o.bstate[a][q])) return false;
+  return finite_value(o.shock_x0) && finite_value(o.shock_speed);
+}
+
+}  // namespace
 
 hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tris, int64_t n_tris,
                          const hwe_opts* opts, hwe_mesh* out) {
@@ -100,7 +126,7 @@ hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tr
   if (o.eq < HWE_ADVECTION || o.eq > HWE_EULER || o.bc < 0 || o.bc > 1 || o.prec < 0 || o.prec > 1 ||
       o.positivity < 0 || o.positivity > 1 || (o.positivity && o.eq != HWE_EULER) || o.time_rule < 0 ||
       o.time_rule > 1 || !(o.deriv_weight > 0.0) || !(o.deriv_weight < 1e300) || o.walls < 0 || o.walls > 15 ||
-      (o.walls && (o.eq != HWE_EULER || o.bc != HWE_BC_TRANSMISSIVE))) {
+      (o.walls && (o.eq != HWE_EULER || o.bc != HWE_BC_TRANSMISSIVE)) || !regions_ok(o)) {
     set_error("invalid option value");
     return HWE_EINVAL;
   }
@@ -156,6 +182,15 @@ hwe_status hwe_mesh_info(hwe_mesh m, int64_t* n_cells, int64_t* n_edges, int32_t
   if (n_cells) *n_cells = m->h.N;
   if (n_edges) *n_edges = m->h.E;
   if (m_comp) *m_comp = m->h.m;
+  return HWE_OK;
+}
+
+hwe_status hwe_set_time(hwe_mesh m, double t) {
+  if (!m || !finite_value(t)) {
+    set_error("null mesh handle or non-finite time");
+    return HWE_EINVAL;
+  }
+  m->time = t;
   return HWE_OK;
 }
 
@@ -226,8 +261,8 @@ hwe_status check_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n, c
     set_error("output buffers overlap each other");
     return HWE_EINVAL;
   }
-  if (m->opts.walls) {
-    set_error("hwe_step_adjoint: meshes with reflective walls are not differentiated");
+  if (m->h.special_bnd) {
+    set_error("hwe_step_adjoint: meshes with reflective walls or prescribed boundary states are not differentiated");
     return HWE_EINVAL;
   }
   if (m->opts.positivity) {
@@ -355,6 +390,11 @@ hwe_status hwe_debug_host_array(hwe_mesh m, int32_t which, double* out) {
       return HWE_OK;
     case 4:
       for (size_t k = 0; k < h.nbr.size(); ++k) out[k] = double(h.nbr[k]);
+      return HWE_OK;
+    case 5:
+      // boundary kind of each face, -1 on interior faces
+      for (size_t k = 0; k < h.nbr.size(); ++k)
+        out[k] = h.nbr[k] >= 0 ? -1.0 : h.bnd_n[2 * h.NB + (-h.nbr[k] - 1)];
       return HWE_OK;
     default:
       set_error("unknown array id");

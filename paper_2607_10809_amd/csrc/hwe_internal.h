@@ -30,7 +30,9 @@ struct HostMesh {
   std::vector<double> mom;         // [3][N] central second moments Mxx, Mxy, Myy
   std::vector<int32_t> nbr;        // [3][N] neighbour across face f; -(b+1) for boundary face b
   std::vector<int32_t> nbr_back;   // [3][N] the neighbour's face index that points back (-1 on boundary)
-  std::vector<double> bnd_n;       // [3][NB] outward unit normal of boundary face b, then 1 on a wall (else 0)
+  std::vector<double> bnd_n;       // [4][NB] outward unit normal of boundary face b, its kind
+                                   // (hwe_bnd_kind, as a double) and the x of its midpoint
+  bool special_bnd = false;        // some boundary face is a wall or prescribed
   std::vector<double> p1;          // [55][N] Step-1 map (row-major 5 x 11 per cell)
   std::vector<double> p2;          // [9][N] Step-2 data
   std::vector<int32_t> cell_edge;  // [3][N] (edge << 1) | (cell is the edge's second cell)
@@ -38,7 +40,9 @@ struct HostMesh {
   std::vector<double> inv_area;    // [N]
   std::vector<double> gpc;         // [12][N] offsets (X, Y) from the centroid of the
                                    // 2 Gauss points of faces 0..2: row 4f+2g (X), 4f+2g+1 (Y)
-  std::vector<int32_t> ecell;      // [2][E] first cell (lower caller index), second cell or -1
+  std::vector<int32_t> ecell;      // [2][E] first cell (lower caller index), then the second cell, or
+                                   // on a boundary edge -1 (transmissive), -2 (wall) or -3 - b
+                                   // (prescribed state; b = the boundary face)
   std::vector<double> egeo;        // [11][E]
   double rmin = 0.0;               // smallest inradius
 };
@@ -88,6 +92,7 @@ constexpr int kRedBlocks = 1024;
 
 struct hwe_mesh_s {
   hwe_opts opts;
+  double time = 0.0;  // hwe_set_time: time of the next step's input state
   hwe::HostMesh h;
   hwe::DevMesh d;
 };

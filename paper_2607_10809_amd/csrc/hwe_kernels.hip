@@ -113,10 +113,11 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
 // the (side 0) lanes take the other side's sums and FP64 terms the same way.
 // On a reflective wall the second side is the first one's mirror image.
 template <int EQ, class Real, int TR>
-__global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, double dt,
+__global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, int NB, Params P, double dt,
                                                        const double* __restrict__ wbar,
                                                        const Real* __restrict__ R,
                                                        const int32_t* __restrict__ ecell,
+                                                       const double* __restrict__ bnd_n,
                                                        const double* __restrict__ enl,
                                                        const Real* __restrict__ egp, double* __restrict__ F,
                                                        Real* __restrict__ G) {
@@ -125,8 +126,9 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, do
   const int e = gid >> 2, side = (gid >> 1) & 1, g = gid & 1;
   const bool valid = e < E;
   const int ec = valid ? e : E - 1;
-  // second cell: -1 on a transmissive boundary, -2 on a reflective wall; a
-  // lane without a cell reads the edge's first cell
+  // second cell: -1 on a transmissive boundary, -2 on a reflective wall,
+  // -3 - b on prescribed boundary face b; a lane without a cell reads the
+  // edge's first cell
   const int cell = valid ? ecell[side * E + ec] : -1;
   const int cc = cell >= 0 ? cell : ecell[ec];
   const double nx = enl[ec], ny = enl[E + ec], len = enl[2 * E + ec];
@@ -136,6 +138,12 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, do
   Real dl[M], Wt[M], Wtt[M];
   edge_point<EQ, Real>(ec, cell, side, g, E, P, Wb, R, egp, dl, Wt, Wtt);
   const bool wall = cell == -2;
+  // a prescribed exterior is a flat cell holding the state (no offsets)
+  const bool presc = cell <= -3;
+  if (presc) {
+    const int b = -cell - 3;
+    prescribed_state<M>(P, bnd_n[2 * size_t(NB) + b], bnd_n[3 * size_t(NB) + b], Wb);
+  }
   if constexpr (EQ == EQ_EUL) {
     // the exterior of a wall is the interior with its momentum reflected: the
     // wall lane takes the first side's point values from its quad partner
@@ -165,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, do
   Real AH[M], AD[M], AT[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) AH[q] = AD[q] = AT[q] = Real(0);
-  if (cell >= 0 || wall) edge_nodes<EQ, Real, TR>(P, dt, Wb, Real(nx), Real(ny), dl, Wt, Wtt, AH, AD, AT);
+  if (cell >= 0 || wall || presc) edge_nodes<EQ, Real, TR>(P, dt, Wb, Real(nx), Real(ny), dl, Wt, Wtt, AH, AD, AT);
   double Hb[M];
   const double lam = side_terms<EQ>(P, Wb, nx, ny, Hb);
   // Gauss points (weights 1/2 each): combine lanes g = 0, 1
@@ -187,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, do
     Ho[q] = quad_perm<kQuadXor2>(Hb[q]);
   }
   const double lo = quad_perm<kQuadXor2>(lam);
-  const bool second = quad_perm<kQuadXor2>(cell) != -1;  // a cell or a wall on the other side
+  const bool second = quad_perm<kQuadXor2>(cell) != -1;  // a cell, wall or prescribed state on the other side
   if (!valid || side != 0) return;
   if (g == 0)
     edge_flux<EQ, Real>(e, E, len, second, Wb, Hb, lam, Wo, Ho, lo, AH, AD, OH, OD, F);
@@ -196,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, Params P, do
 }
 
 template <int EQ, class Real>
-__global__ __launch_bounds__(kBlock) void update_kernel(int N, int E, int NB, double dt,
+__global__ __launch_bounds__(kBlock) void update_kernel(int N, int E, int NB, Params P, double dt,
                                                          const double* __restrict__ wbar,
                                                          const double* __restrict__ bnd_n,
                                                          const int32_t* __restrict__ nbr,
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(int N, int E, int NB, do
                                                          double* __restrict__ wout, Real* __restrict__ gout) {
   const int i = xcd_block_id() * kBlock + threadIdx.x;
   if (i >= N) return;
-  update_point<EQ, Real>(i, N, E, NB, dt, wbar, bnd_n, nbr, cell_edge, nl, inv_area, F, G, wout, gout);
+  update_point<EQ, Real>(i, N, E, NB, P, dt, wbar, bnd_n, nbr, cell_edge, nl, inv_area, F, G, wout, gout);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -353,13 +361,13 @@ hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, cons
                      d.nbr, d.bnd_n, tbl, d.area, d.gpc, R);
   if (ev) hipEventRecord(ev[1], st);
   if (P.time_rule == 1)
-    hipLaunchKernelGGL((edge_kernel<EQ, Real, 1>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, P, dt,
-                       wbar_in, R, d.ecell, d.enl, egp, F, G);
+    hipLaunchKernelGGL((edge_kernel<EQ, Real, 1>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB, P,
+                       dt, wbar_in, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
   else
-    hipLaunchKernelGGL((edge_kernel<EQ, Real, 0>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, P, dt,
-                       wbar_in, R, d.ecell, d.enl, egp, F, G);
+    hipLaunchKernelGGL((edge_kernel<EQ, Real, 0>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB, P,
+                       dt, wbar_in, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
   if (ev) hipEventRecord(ev[2], st);
-  hipLaunchKernelGGL((update_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, NB, dt, wbar_in,
+  hipLaunchKernelGGL((update_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, NB, P, dt, wbar_in,
                      d.bnd_n, d.nbr, d.cell_edge, nl, d.inv_area, F, G, wbar_out, grad_out);
   if (ev) {
     hipEventRecord(ev[3], st);
@@ -396,6 +404,11 @@ Params params_of(const hwe_opts& o) {
   P.eps = o.eps;
   P.linear = o.linear_weights ? 1 : 0;
   P.time_rule = o.time_rule;
+  for (int a = 0; a < 2; ++a)
+    for (int q = 0; q < 4; ++q) P.bst[a][q] = o.bstate[a][q];
+  P.sx0 = o.shock_x0;
+  P.sv = o.shock_speed;
+  P.tb = 0.0;
   return P;
 }
 
@@ -474,7 +487,8 @@ void free_device(hwe_mesh_s* M) {
 
 hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,
                        double dt, void* R_keep, void* stream) {
-  const Params P = params_of(M->opts);
+  Params P = params_of(M->opts);
+  P.tb = M->time + 0.5 * dt;  // moving boundary states: the middle of the step
   hipStream_t st = static_cast<hipStream_t>(stream);
   const DevMesh& d = M->d;
   void* R = R_keep ? R_keep : d.R;
@@ -503,7 +517,8 @@ hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in
 }
 
 hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, void* R_out, void* stream) {
-  const Params P = params_of(M->opts);
+  Params P = params_of(M->opts);
+  P.tb = M->time;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const DevMesh& d = M->d;
   if (M->opts.prec == HWE_FP64) {

@@ -74,7 +74,26 @@ struct Params {
   int linear;      // 1: omega = gamma
   int positivity;  // 1: scaling limiter on the Euler reconstruction
   int time_rule;   // 0: 3-point Gauss-Lobatto in time, 1: 2-point Gauss-Legendre
+  // prescribed boundary states: A (kind 2), B (kind 3), or A where the face
+  // midpoint has x < sx0 + sv * tb, else B (kind 4); tb = the middle of the step
+  double bst[2][4];
+  double sx0, sv, tb;
 };
+
+// The prescribed state of a boundary face of kind 2, 3 or 4 (kind and midpoint
+// x as stored per boundary face), component by component with compile-time
+// indices so that the parameter block is never indexed at run time.
+template <int M>
+__host__ __device__ __forceinline__ void prescribed_state(const Params& P, double kind, double xm, double (&W)[M]) {
+  const bool a = kind == 2.0 || (kind == 4.0 && xm < P.sx0 + P.sv * P.tb);
+#pragma unroll
+  for (int q = 0; q < M; ++q) W[q] = a ? P.bst[0][q] : P.bst[1][q];
+}
+__host__ __device__ __forceinline__ double prescribed_component(const Params& P, double kind, double xm, int q) {
+  double W[4];
+  prescribed_state<4>(P, kind, xm, W);
+  return q == 0 ? W[0] : (q == 1 ? W[1] : (q == 2 ? W[2] : W[3]));
+}
 
 template <class T> struct SJ {  // spatial jet
   T c, x, y, xx, xy, yy;

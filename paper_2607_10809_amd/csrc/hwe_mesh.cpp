@@ -246,21 +246,27 @@ hwe_status fail(hwe_status s, const std::string& msg) {
 
 }  // namespace
 
-// A boundary face on a reflective wall: it lies on a side of the box (s = 0:
-// x = x0, 1: x = x1, 2: y = y0, 3: y = y1) whose bit is set in o.walls.
-static bool on_wall(const hwe_opts& o, const Tri& t, int f) {
-  if (!o.walls) return false;
+// Kind of a boundary face (hwe_bnd_kind): the first region of o.regions that
+// holds its midpoint, else a reflective wall when it lies on a side of the box
+// (s = 0: x = x0, 1: x = x1, 2: y = y0, 3: y = y1) whose bit is set in o.walls,
+// else transmissive.
+static int boundary_kind(const hwe_opts& o, const Tri& t, int f) {
   const int f1 = (f + 1) % 3;
   const double ex = t.x[f1] - t.x[f], ey = t.y[f1] - t.y[f];
   const double mx = 0.5 * (t.x[f] + t.x[f1]), my = 0.5 * (t.y[f] + t.y[f1]);
   const double tol = 1e-9 * std::max(o.box[1] - o.box[0], o.box[3] - o.box[2]);
+  for (int r = 0; r < o.n_regions; ++r) {
+    const double* b = o.regions[r].box;
+    if (mx >= b[0] - tol && mx <= b[1] + tol && my >= b[2] - tol && my <= b[3] + tol) return o.regions[r].kind;
+  }
+  if (!o.walls) return HWE_BND_TRANSMISSIVE;
   const bool on[4] = {std::fabs(mx - o.box[0]) < tol && std::fabs(ex) < tol,
                       std::fabs(mx - o.box[1]) < tol && std::fabs(ex) < tol,
                       std::fabs(my - o.box[2]) < tol && std::fabs(ey) < tol,
                       std::fabs(my - o.box[3]) < tol && std::fabs(ey) < tol};
   for (int s = 0; s < 4; ++s)
-    if (on[s] && ((o.walls >> s) & 1)) return true;
-  return false;
+    if (on[s] && ((o.walls >> s) & 1)) return HWE_BND_WALL;
+  return HWE_BND_TRANSMISSIVE;
 }
 
 hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* tris, int64_t n_tris,
@@ -417,7 +423,9 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
     double ex = t.x[f1] - t.x[f], ey = t.y[f1] - t.y[f];
     double len = std::hypot(ex, ey);
     h.ecell[e] = int32_t(inv[r.c0]);
-    h.ecell[E + e] = r.c1 >= 0 ? int32_t(inv[r.c1]) : (on_wall(o, t, f) ? -2 : -1);
+    // boundary edges: -1 transmissive, -2 wall; prescribed edges get -3 - b
+    // below, once the boundary faces are numbered
+    h.ecell[E + e] = r.c1 >= 0 ? int32_t(inv[r.c1]) : (boundary_kind(o, t, f) == HWE_BND_WALL ? -2 : -1);
     h.egeo[0 * E + e] = ey / len;
     h.egeo[1 * E + e] = -ex / len;
     h.egeo[2 * E + e] = len;
@@ -442,7 +450,7 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
   h.mom.assign(3 * N, 0);
   h.nbr.assign(3 * N, 0);
   h.nbr_back.assign(3 * N, -1);
-  h.bnd_n.assign(3 * std::max<int64_t>(h.NB, 1), 0);
+  h.bnd_n.assign(4 * std::max<int64_t>(h.NB, 1), 0);
   h.p1.assign(size_t(kP1) * N, 0);
   h.p2.assign(size_t(kP2) * N, 0);
   h.cell_edge.assign(3 * N, 0);
@@ -493,9 +501,13 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
       } else {
         // ghost: K0 mirrored across the face line
         h.nbr[f * N + i] = int32_t(-(bcount + 1));
+        const int kind = boundary_kind(o, t, f);
         h.bnd_n[bcount] = nx;
         h.bnd_n[h.NB + bcount] = ny;
-        h.bnd_n[2 * h.NB + bcount] = on_wall(o, t, f) ? 1.0 : 0.0;
+        h.bnd_n[2 * h.NB + bcount] = double(kind);
+        h.bnd_n[3 * h.NB + bcount] = t.x[f] + 0.5 * ex;
+        if (kind >= HWE_BND_STATE_A) h.ecell[E + (face_edge[3 * k + f] >> 1)] = int32_t(-3 - bcount);
+        if (kind != HWE_BND_TRANSMISSIVE) h.special_bnd = true;
         ++bcount;
         Tri gt;
         for (int v = 0; v < 3; ++v) {

@@ -128,16 +128,26 @@ __host__ __device__ __forceinline__ void recon_from_stencil(int i, int q, int N,
       dW[f] = S.Wn[f] - W0;
       Wsum += S.Wn[f];
     } else {
-      // ghost: K0 mirrored across the face, gradient columns reflected
+      // ghost: K0 mirrored across the face, gradient columns reflected; a
+      // prescribed face's ghost holds the prescribed state, flat
       const int b = -S.nbi[f] - 1;
       const Real nx = Real(bnd_n[b]), ny = Real(bnd_n[NB + b]);
-      dW[f] = 0.0;
-      Wsum += W0;
+      const double kind = bnd_n[2 * NB + b];
       const Real vn = V[0] * nx + Y[0] * ny;
-      V[f + 1] = V[0] - Real(2) * nx * vn;
-      Y[f + 1] = Y[0] - Real(2) * ny * vn;
+      if (kind >= 2.0) {
+        const double Wd = prescribed_component(P, kind, bnd_n[3 * NB + b], q);
+        dW[f] = Wd - W0;
+        Wsum += Wd;
+        V[f + 1] = Real(0);
+        Y[f + 1] = Real(0);
+      } else {
+        dW[f] = 0.0;
+        Wsum += W0;
+        V[f + 1] = V[0] - Real(2) * nx * vn;
+        Y[f + 1] = Y[0] - Real(2) * ny * vn;
+      }
       if constexpr (EQ == EQ_EUL) {
-        if ((q == 1 || q == 2) && bnd_n[2 * NB + b] != 0.0) {
+        if ((q == 1 || q == 2) && kind == 1.0) {
           // wall: m -> m - 2 (m.n) n in the average, and the rows of the two
           // momentum components mixed the same way
           constexpr int M = NComp<EQ>::m;
@@ -446,7 +456,7 @@ __host__ __device__ __forceinline__ void edge_value(int e, int E, bool second, c
 // over the closed cell, |K| Vbar = sum_e n_e|e| (Wface_e - Wbar_K + G_e) where
 // Wface_e = mean of the two cell averages, so a constant state gives exactly 0.
 template <int EQ, class Real>
-__host__ __device__ __forceinline__ void update_point(int i, int N, int E, int NB, double dt,
+__host__ __device__ __forceinline__ void update_point(int i, int N, int E, int NB, const Params& P, double dt,
                                                      const double* __restrict__ wbar,
                                                      const double* __restrict__ bnd_n,
                                                      const int32_t* __restrict__ nbr,
@@ -487,12 +497,20 @@ __host__ __device__ __forceinline__ void update_point(int i, int N, int E, int N
       fs[q] += second ? -Fe[q] : Fe[q];
       d[q] = 0.5 * (Wn - W0[q]);  // exactly 0 on a boundary face (Wn is the cell's own)
     }
-    if constexpr (EQ == EQ_EUL) {
-      if (nb[f] < 0) {
+    if (nb[f] < 0) {
+      const int b = -nb[f] - 1;
+      const double kind = bnd_n[2 * NB + b];
+      if (kind >= 2.0) {
+        // prescribed state: half the difference of the ghost average
+        double Wd[M];
+        prescribed_state<M>(P, kind, bnd_n[3 * NB + b], Wd);
+#pragma unroll
+        for (int q = 0; q < M; ++q) d[q] = 0.5 * (Wd[q] - W0[q]);
+      }
+      if constexpr (EQ == EQ_EUL) {
         // wall: the ghost average is the reflected one, half the difference is
         // -(m.n) n in the momentum components
-        const int b = -nb[f] - 1;
-        if (bnd_n[2 * NB + b] != 0.0) {
+        if (kind == 1.0) {
           const double bx = bnd_n[b], by = bnd_n[NB + b];
           const double mn = W0[1] * bx + W0[2] * by;
           d[1] = -mn * bx;

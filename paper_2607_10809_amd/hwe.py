@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BCS, EQUATIONS, PRECISIONS, HweOpts, check, load_library
+from ._lib import BCS, BND_KINDS, EQUATIONS, MAX_REGIONS, PRECISIONS, HweOpts, check, load_library
 
 
 def _ptr(t: torch.Tensor):
@@ -27,7 +27,11 @@ def _stream(stream=None):
 
 def make_opts(eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp64", adv=(1.0, 1.0),
               gas_gamma=1.4, lin_w=(0.94, 0.02, 0.02, 0.02), eps=1e-8, linear_weights=False, device=0,
-              positivity=False, time_rule=0, deriv_weight=1.0, walls=0) -> HweOpts:
+              positivity=False, time_rule=0, deriv_weight=1.0, walls=0, regions=(), states=(), shock=()) -> HweOpts:
+    """Options of a mesh handle.  regions: boundary regions, first match wins,
+    as (kind, (x0, x1, y0, y1)) with kind "transmissive", "wall", "A", "B" or
+    "moving"; states: the conservative states (A, B); shock: (x0, speed) of the
+    moving switch."""
     L = load_library()
     o = HweOpts()
     check(L.hwe_opts_default(C.byref(o)))
@@ -45,6 +49,18 @@ def make_opts(eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp
     o.time_rule = int(time_rule)
     o.deriv_weight = float(deriv_weight)
     o.walls = int(walls)
+    regions = list(regions)
+    if len(regions) > MAX_REGIONS:
+        raise ValueError(f"at most {MAX_REGIONS} boundary regions")
+    o.n_regions = len(regions)
+    for r, (kind, rect) in enumerate(regions):
+        o.regions[r].kind = BND_KINDS[kind] if isinstance(kind, str) else int(kind)
+        o.regions[r].box[:] = [float(v) for v in rect]
+    for a, st in enumerate(list(states)[:2]):
+        st = [float(v) for v in st]
+        o.bstate[a][:len(st)] = st
+    if shock:
+        o.shock_x0, o.shock_speed = float(shock[0]), float(shock[1])
     return o
 
 
@@ -109,6 +125,9 @@ class Mesh:
         eq = {0: "advection", 1: "burgers", 2: "euler"}[wl.eq]
         if getattr(wl, "walls", 0) and "walls" not in kw:
             kw["walls"] = wl.walls
+        for key in ("regions", "states", "shock"):
+            if getattr(wl, key, None) and key not in kw:
+                kw[key] = getattr(wl, key)
         return cls(wl.mesh.nodes, wl.mesh.tris, eq=eq, bc=bc, box=wl.mesh.box, precision=precision,
                    device=device, adv=wl.adv, **kw)
 
@@ -155,9 +174,16 @@ class Mesh:
             raise ValueError("state tensors must live on the mesh's device")
 
     # ------------------------------------------------------------ the step
-    def step(self, wbar, grad, dt, out=None, stream=None, keep=None):
-        """One step.  keep: a buffer from empty_recon() that receives the
-        step's reconstruction (for a later adjoint(..., recon=keep))."""
+    def set_time(self, t):
+        """Time of the state given to the next steps (moving boundary states)."""
+        check(self._L.hwe_set_time(self._h, float(t)))
+
+    def step(self, wbar, grad, dt, out=None, stream=None, keep=None, t=None):
+        """One step (from time t, if given).  keep: a buffer from empty_recon()
+        that receives the step's reconstruction (for a later
+        adjoint(..., recon=keep))."""
+        if t is not None:
+            self.set_time(t)
         self._check_state(wbar, grad)
         wo, go = out if out is not None else self.empty_state()
         self._check_state(wo, go)
@@ -179,14 +205,17 @@ class Mesh:
         if R.device != self.device:
             raise ValueError("recon must live on the mesh's device")
 
-    def run(self, wbar, grad, dt, nsteps, stream=None):
-        """nsteps steps of size dt with two ping-pong buffers; returns the final state."""
+    def run(self, wbar, grad, dt, nsteps, stream=None, t0=None):
+        """nsteps steps of size dt with two ping-pong buffers (from time t0,
+        if given); returns the final state."""
         a = (wbar, grad)
         if nsteps <= 0:
             return a
         b = self.empty_state()
         c = self.empty_state() if nsteps > 1 else None
         for k in range(nsteps):
+            if t0 is not None:
+                self.set_time(t0 + k * dt)
             dst = b if k % 2 == 0 else c
             hwe_step(self._h, a[0], a[1], dst[0], dst[1], dt, stream)
             a = dst
@@ -205,6 +234,7 @@ class Mesh:
                 if h <= 1e-14 * T:
                     break
                 nxt = 1 if cur != 1 else 2
+                self.set_time(t)
                 hwe_step(self._h, bufs[cur][0], bufs[cur][1], bufs[nxt][0], bufs[nxt][1], h, stream)
                 cur = nxt
                 t += h
@@ -252,7 +282,7 @@ class Mesh:
         return [ms[0], ms[1], ms[2]], n.value
 
     def host_array(self, which):
-        sizes = {0: (55, self.N), 1: (2, self.N), 2: (self.N,), 3: (3, self.N), 4: (3, self.N)}
+        sizes = {0: (55, self.N), 1: (2, self.N), 2: (self.N,), 3: (3, self.N), 4: (3, self.N), 5: (3, self.N)}
         out = np.empty(sizes[which])
         check(self._L.hwe_debug_host_array(self._h, int(which), out.ctypes.data_as(C.POINTER(C.c_double))))
         return out

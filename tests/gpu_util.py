@@ -26,13 +26,13 @@ def steps_to(T, dt):
     return n, (rem if rem > 1e-14 * T else 0.0)
 
 
-def gpu_run(mesh, state0, dt, nsteps, rem=0.0):
-    """Run the HIP path from a caller-order state; return caller-order numpy state."""
+def gpu_run(mesh, state0, dt, nsteps, rem=0.0, t0=0.0):
+    """Run the HIP path from a caller-order state at time t0; return caller-order numpy state."""
     import torch
     w, g = mesh.to_device(state0)
-    w, g = mesh.run(w, g, dt, nsteps)
+    w, g = mesh.run(w, g, dt, nsteps, t0=t0)
     if rem > 0.0:
-        w, g = mesh.step(w, g, rem)
+        w, g = mesh.step(w, g, rem, t=t0 + nsteps * dt)
     torch.cuda.synchronize()
     return mesh.to_host(w, g)
 

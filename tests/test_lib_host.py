@@ -105,6 +105,52 @@ def test_morton_permutation_and_geometry_match_the_oracle():
     assert np.median(step) < 2.0 * 3.0 / 9
 
 
+@pytest.mark.parametrize("make", ["double_mach", "wedge", "forward_step", "shu_osher", "shock_tube"])
+def test_boundary_kinds_match_the_oracle(make):
+    from paper_2607_10809_amd.hwe import Mesh
+    import workloads
+    wl = {"double_mach": lambda: workloads.double_mach_workload(n=12),
+          "wedge": lambda: workloads.wedge_workload(nx=32, ny=12),
+          "forward_step": lambda: workloads.forward_step_workload(n=10),
+          "shu_osher": lambda: workloads.shu_osher_workload(nx=60),
+          "shock_tube": lambda: workloads.shock_tube_workload("lax", nx=40)}[make]()
+    hm = Mesh.from_workload(wl, device=-1)
+    om = OracleMesh.from_workload(wl)
+    ok = om.face_kinds()                       # caller order, (N, 3)
+    lk = hm.host_array(5).astype(np.int64)     # internal order, (3, N)
+    assert np.array_equal(lk, ok[hm.perm].T)
+    assert (lk >= 0).sum() > 0
+
+
+def test_bad_boundary_regions_are_rejected():
+    from paper_2607_10809_amd._lib import HweError
+    from paper_2607_10809_amd.hwe import Mesh
+    box = (0.0, 1.0, 0.0, 1.0)
+    mesh = split_square_mesh(4, box, periodic=False)
+    good = (("A", (0.0, 0.0, 0.0, 1.0)),)
+    st = ((1.0, 0.0, 0.0, 2.5), (1.0, 0.0, 0.0, 2.5))
+    Mesh(mesh.nodes, mesh.tris, eq="euler", bc="transmissive", box=box, device=-1, regions=good, states=st)
+    from paper_2607_10809_amd.hwe import hwe_mesh_init, make_opts
+    o = make_opts("euler", "transmissive", box, device=-1, regions=good, states=st)
+    o.n_regions = 9                                                           # too many regions
+    with pytest.raises(HweError) as e:
+        hwe_mesh_init(mesh.nodes, mesh.tris, o)
+    assert e.value.status == -1
+    for kw in (dict(eq="euler", regions=((7, box),), states=st),              # unknown kind
+               dict(eq="burgers", regions=(("wall", box),)),                  # walls need Euler
+               dict(eq="euler", regions=(("A", (0.0, float("nan"), 0.0, 1.0)),), states=st),
+               dict(eq="euler", regions=(("A", (1.0, 0.0, 0.0, 1.0)),), states=st),   # x0 > x1
+               dict(eq="euler", regions=good, states=((float("inf"), 0.0, 0.0, 1.0), st[1])),
+               dict(eq="euler", regions=good, states=st, shock=(0.0, float("nan")))):
+        with pytest.raises(HweError) as e:
+            Mesh(mesh.nodes, mesh.tris, bc="transmissive", box=box, device=-1, **kw)
+        assert e.value.status == -1, kw
+    pm = split_square_mesh(4, box, periodic=True)
+    with pytest.raises(HweError) as e:                                        # regions need boundaries
+        Mesh(pm.nodes, pm.tris, eq="euler", bc="periodic", box=box, device=-1, regions=good, states=st)
+    assert e.value.status == -1
+
+
 def _apply_p1(hm, state_caller):
     """Apply the library's Step-1 map to a caller-order state (component 0)."""
     T = hm.host_array(0).reshape(5, 11, hm.N)
