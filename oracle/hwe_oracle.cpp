@@ -22,7 +22,8 @@
 //   time rule: 3-point Gauss-Lobatto, nodes {0, 1/2, 1} dt, weights {1,4,1}/6
 //   (a 2-point Gauss-Legendre rule is an option; the interface value is the
 //   Taylor polynomial at dt either way);
-//   edge rule: 2-point Gauss-Legendre; alpha from the two cell averages;
+//   edge rule: 2-point Gauss-Legendre (a 3-point rule is an option; the
+//   limiter then checks the 9 points); alpha from the two cell averages;
 //   systems: component-wise reconstruction of the conservative variables;
 //   periodic boundaries by exact translation across seams; transmissive
 //   boundaries by a mirrored ghost cell for the stencil and W_ext := W_int
@@ -116,8 +117,16 @@ template <class T> HD<T> operator/(const HD<T>& x, const HD<T>& y) { return x * 
 // [0, dt], nodes as fractions of dt): 3-point Gauss-Lobatto {0, 1/2, 1} with
 // weights {1, 4, 1}/6 (default), or 2-point Gauss-Legendre 1/2 -+ sqrt(3)/6
 // with weights 1/2.
-const double kGaussS[2] = {0.5 - 0.28867513459481288225, 0.5 + 0.28867513459481288225};  // 1/2 -+ sqrt(3)/6
-const double kGaussW[2] = {0.5, 0.5};
+// Gauss-Legendre rules on an edge, as fractions s of the way along it with
+// weights summing to one: 2 points (1/2 -+ sqrt(3)/6, weights 1/2) and 3 points
+// (1/2 -+ sqrt(15)/10 with weights 5/18, and 1/2 with weight 8/18).
+struct EdgeRule {
+  int n;
+  double s[3], w[3];
+};
+const EdgeRule kEdgeRules[2] = {
+    {2, {0.5 - 0.28867513459481288225, 0.5 + 0.28867513459481288225, 0.0}, {0.5, 0.5, 0.0}},
+    {3, {0.5 - 0.38729833462074168852, 0.5, 0.5 + 0.38729833462074168852}, {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0}}};
 struct TimeRule {
   int n;
   double node[3], w[3];
@@ -151,7 +160,10 @@ struct Opts {
   double reg_box[8][4];
   double bstate[2][4];  // states A and B (conservative variables)
   double shock_x0, shock_speed;
+  int edge_rule;  // Gauss-Legendre points per edge: 2 (default) or 3
 };
+
+inline const EdgeRule& edge_rule_of(const Opts& o) { return kEdgeRules[o.edge_rule == 3 ? 1 : 0]; }
 
 enum { kBndTrans = 0, kBndWall = 1, kBndStateA = 2, kBndStateB = 3, kBndMoving = 4 };
 
@@ -581,12 +593,14 @@ void positivity_scaling(const Mesh& M, int64_t k, Recon<T>& R) {
   const Opts& o = M.o;
   const Tri& t = M.tri[k];
   const double gm1 = o.gas_gamma - 1.0;
-  double xs[6], ys[6];
+  const EdgeRule& er = edge_rule_of(o);
+  const int np = 3 * er.n;
+  double xs[9], ys[9];
   for (int f = 0; f < 3; ++f) {
     int f1 = (f + 1) % 3;
-    for (int G = 0; G < 2; ++G) {
-      xs[2 * f + G] = t.x[f] + kGaussS[G] * (t.x[f1] - t.x[f]);
-      ys[2 * f + G] = t.y[f] + kGaussS[G] * (t.y[f1] - t.y[f]);
+    for (int G = 0; G < er.n; ++G) {
+      xs[er.n * f + G] = t.x[f] + er.s[G] * (t.x[f1] - t.x[f]);
+      ys[er.n * f + G] = t.y[f] + er.s[G] * (t.y[f1] - t.y[f]);
     }
   }
   auto pressure = [&](const T* W) { return T(gm1) * (W[3] - T(0.5) * (W[1] * W[1] + W[2] * W[2]) / W[0]); };
@@ -595,7 +609,7 @@ void positivity_scaling(const Mesh& M, int64_t k, Recon<T>& R) {
   const double eps = std::min(1e-13, std::min(val(Wb[0]), pbar));
   // density
   T rmin = T(1e300);
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < np; ++i) {
     T D[6];
     eval_recon(o, R, 0, xs[i], ys[i], D);
     if (val(D[0]) < val(rmin)) rmin = D[0];
@@ -603,7 +617,7 @@ void positivity_scaling(const Mesh& M, int64_t k, Recon<T>& R) {
   if (val(rmin) < eps) R.theta[0] = (Wb[0] - T(eps)) / (Wb[0] - rmin);
   // pressure
   T th = T(1.0);
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < np; ++i) {
     T W[4];
     for (int q = 0; q < 4; ++q) {
       T D[6];
@@ -713,9 +727,10 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
       T aG = spectral_radius(o, Wg, F.nx, F.ny);
       alpha = maxfirst(aK, aG);
     }
-    for (int G = 0; G < 2; ++G) {
-      double xg = t.x[f] + kGaussS[G] * (t.x[f1] - t.x[f]);
-      double yg = t.y[f] + kGaussS[G] * (t.y[f1] - t.y[f]);
+    const EdgeRule& er = edge_rule_of(o);
+    for (int G = 0; G < er.n; ++G) {
+      double xg = t.x[f] + er.s[G] * (t.x[f1] - t.x[f]);
+      double yg = t.y[f] + er.s[G] * (t.y[f1] - t.y[f]);
       T Di[6][4], De[6][4], tmp[6];
       for (int q = 0; q < m; ++q) {
         eval_recon(o, R[k], q, xg, yg, tmp);
@@ -750,7 +765,7 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
           T Hi = fi[q] * T(F.nx) + gi[q] * T(F.ny);
           T He = fe[q] * T(F.nx) + ge[q] * T(F.ny);
           T Hhat = T(0.5) * (He + Hi - alpha * (We[q] - Wi[q]));
-          Fsum[q] += Hhat * T(rule.w[sN] * kGaussW[G] * F.len);
+          Fsum[q] += Hhat * T(rule.w[sN] * er.w[G] * F.len);
         }
       }
       {  // tau = dt: interface value of eq. (timeflux) for the derivative averages
@@ -758,8 +773,8 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
         taylor(dt, Wi, We);
         for (int q = 0; q < m; ++q) {
           T What = T(0.5) * (Wi[q] + We[q]);
-          Vs[q] += What * T(F.nx * kGaussW[G] * F.len);
-          Ys[q] += What * T(F.ny * kGaussW[G] * F.len);
+          Vs[q] += What * T(F.nx * er.w[G] * F.len);
+          Ys[q] += What * T(F.ny * er.w[G] * F.len);
         }
       }
     }
@@ -975,6 +990,7 @@ struct or_opts {
   double reg_box[8][4];
   double bstate[2][4];
   double shock_x0, shock_speed;
+  int edge_rule;
 };
 
 void* or_mesh_new(const double* nodes, int64_t nn, const int32_t* tris, int64_t nt, const or_opts* o,
@@ -1002,6 +1018,7 @@ void* or_mesh_new(const double* nodes, int64_t nn, const int32_t* tris, int64_t 
   }
   for (int a = 0; a < 2; ++a)
     for (int i = 0; i < 4; ++i) M->o.bstate[a][i] = o->bstate[a][i];
+  M->o.edge_rule = o->edge_rule == 3 ? 3 : 2;
   M->o.shock_x0 = o->shock_x0;
   M->o.shock_speed = o->shock_speed;
   int st = build_mesh(*M, nodes, nn, tris, nt);

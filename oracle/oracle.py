@@ -13,7 +13,7 @@ _LIB = os.path.join(_HERE, "libhwe_oracle.so")
 
 OPTS_DEFAULT = dict(adv=(1.0, 1.0), gas_gamma=1.4, lin_w=(0.94, 0.02, 0.02, 0.02), eps=1e-8,
                     linear_only=0, positivity=0, time_rule=0, deriv_weight=1.0, walls=0,
-                    regions=(), states=((0.0,) * 4, (0.0,) * 4), shock=(0.0, 0.0))
+                    regions=(), states=((0.0,) * 4, (0.0,) * 4), shock=(0.0, 0.0), edge_rule=2)
 
 # boundary kinds of a region
 BND_KINDS = {"transmissive": 0, "wall": 1, "A": 2, "B": 3, "moving": 4}
@@ -25,7 +25,7 @@ class _Opts(C.Structure):
                 ("linear_only", C.c_int), ("positivity", C.c_int), ("time_rule", C.c_int),
                 ("deriv_weight", C.c_double), ("walls", C.c_int), ("nreg", C.c_int),
                 ("reg_kind", C.c_int * 8), ("reg_box", (C.c_double * 4) * 8), ("bstate", (C.c_double * 4) * 2),
-                ("shock_x0", C.c_double), ("shock_speed", C.c_double)]
+                ("shock_x0", C.c_double), ("shock_speed", C.c_double), ("edge_rule", C.c_int)]
 
 
 def build_oracle(force: bool = True) -> str:
@@ -105,6 +105,7 @@ def _opts(eq, bc=0, box=(0.0, 1.0, 0.0, 1.0), **kw):
         st = list(o["states"][a]) + [0.0] * (4 - len(o["states"][a]))
         s.bstate[a][:] = [float(v) for v in st]
     s.shock_x0, s.shock_speed = float(o["shock"][0]), float(o["shock"][1])
+    s.edge_rule = int(o["edge_rule"])
     return s
 
 

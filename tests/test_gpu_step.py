@@ -409,3 +409,29 @@ def test_bad_arguments_raise():
     with pytest.raises(HweError):                 # output aliases the input
         mesh.step(w, g, 0.01, out=(w, g))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replays_equal_eager_steps(prec):
+    """A captured 6-step sequence, replayed three times with eager steps and
+    synchronisations between the replays: each replay equals the eager run
+    from the same state bitwise (the step records no memset or allocation)."""
+    import torch
+    wl = vortex_workload(n=24)
+    m = _mesh(wl, prec)
+    w0, g0 = m.to_device(wl.state0)
+    dt = m.max_dt(w0, wl.cfl)
+    a = (w0.clone(), g0.clone())
+    b = m.empty_state()
+    graph = m.capture_steps(a, b, dt, 6)
+    state = (w0.clone(), g0.clone())
+    for rep in range(3):
+        a[0].copy_(state[0])
+        a[1].copy_(state[1])
+        graph.replay()
+        torch.cuda.synchronize()
+        ref = m.run(state[0], state[1], dt, 6)
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], ref[0]) and torch.equal(a[1], ref[1]), rep
+        state = m.run(ref[0], ref[1], dt, 3)          # eager work between the replays
+        torch.cuda.synchronize()

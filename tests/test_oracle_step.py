@@ -63,13 +63,14 @@ def _deep_interior(om, layers=2):
     return np.nonzero(ok)[0]
 
 
-@pytest.mark.parametrize("time_rule", [0, 1])
-def test_one_advection_step_is_exact_on_quadratics_with_linear_weights(time_rule):
-    """Either time rule integrates the quadratic-in-time linear flux exactly."""
+@pytest.mark.parametrize("time_rule,edge_rule", [(0, 2), (1, 2), (0, 3)])
+def test_one_advection_step_is_exact_on_quadratics_with_linear_weights(time_rule, edge_rule):
+    """Either time rule integrates the quadratic-in-time linear flux exactly,
+    and either edge rule the quadratic-in-space one."""
     box = (0.0, 1.0, 0.0, 1.0)
     mesh = split_square_mesh(8, box, jitter=0.25, seed=12, periodic=False)
     om = OracleMesh(mesh.nodes, mesh.tris, eq=0, bc=1, box=box, adv=(0.7, -0.4), linear_only=1,
-                    time_rule=time_rule)
+                    time_rule=time_rule, edge_rule=edge_rule)
     q = lambda x, y: 0.4 - 1.3 * x + 0.6 * y + 0.8 * x * x - 0.5 * x * y + 1.1 * y * y
     f = lambda x, y, t: q(x - 0.7 * t, y + 0.4 * t)[..., None]
     s0 = cell_average_states(mesh, f, 0.0)
@@ -186,6 +187,26 @@ def test_time_rules_differ_only_at_fifth_order_in_dt():
         d.append(np.abs(a[0] - b[0]).max())
     assert d[0] > 0 and d[1] > 0
     assert 20 < d[0] / d[1] < 50, d                   # ~2^5
+
+
+def test_edge_rules_agree_on_advection_and_differ_at_fourth_order_on_burgers():
+    """Linear advection: the flux along an edge is a quadratic polynomial, which
+    the 2- and 3-point Gauss-Legendre rules both integrate exactly, so the
+    steps agree to round-off.  Burgers: the flux is quartic along the edge and
+    the 2-point rule's error (the 4th derivative term) makes the one-step
+    results differ by O(h^4) at a fixed CFL number."""
+    wl = advection_workload(n=16, jitter=0.2)
+    a, b = OracleMesh.from_workload(wl), OracleMesh.from_workload(wl, edge_rule=3)
+    dt = a.max_dt(wl.state0, 0.3)
+    sa, sb = a.run(wl.state0, dt, 10), b.run(wl.state0, dt, 10)
+    assert np.abs(sa - sb).max() <= 1e-13 * np.abs(sa).max()
+    d = []
+    for n in (24, 48):
+        wl = burgers_workload(n=n, box=(-2.0, 2.0, -2.0, 2.0), jitter=0.1)
+        a, b = OracleMesh.from_workload(wl), OracleMesh.from_workload(wl, edge_rule=3)
+        dt = 0.1 * 4.0 / n
+        d.append(np.abs(a.step(wl.state0, dt)[0] - b.step(wl.state0, dt)[0]).max())
+    assert d[1] > 0 and 10 < d[0] / d[1] < 24, d          # ~2^4
 
 
 @pytest.mark.parametrize("eq", [0, 1, 2])
