@@ -134,6 +134,12 @@ typedef struct {
                              variables (m of the 4 entries used) */
   double shock_x0;        /* HWE_BND_MOVING: switch position at t = 0 */
   double shock_speed;     /* and its speed in x */
+  int32_t edge_rule;      /* Gauss-Legendre points per edge in the flux and
+                             interface-value integrals of eqs. (fx)/(flux) and
+                             (derave2d2): 2 (default; exact for cubics along the
+                             edge) or 3 (exact for quintics).  3 is not
+                             combined with the positivity limiter (HWE_EINVAL) */
+  int32_t pad_rule;
 } hwe_opts;
 
 /* Fill *o with the paper's defaults: linear weights 0.94/0.02/0.02/0.02
@@ -243,8 +249,10 @@ hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, voi
  * zero-mean basis X, Y, X^2-Mxx, XY-Mxy, Y^2-Myy; columns: dW1..dW3, V0..V3,
  * Y0..Y3), 1 = centroid [2][N], 2 = area [N], 3 = moments [3][N],
  * 4 = neighbours [3][N] (as double; negative = boundary), 5 = boundary kind
- * of each face [3][N] (hwe_bnd_kind as double; -1 = interior face).  out is
- * host double with room for the stated size. */
+ * of each face [3][N] (hwe_bnd_kind as double; -1 = interior face), 6 = the
+ * factored p1 map of the device tables [41][N] (rows 3j + c: the dW columns;
+ * 15 + 5k + j: Z; 25 + 8k + v: Q on V0..V3, Y0..Y3; the map's V and Y columns
+ * are Z^T Q).  out is host double with room for the stated size. */
 hwe_status hwe_debug_host_array(hwe_mesh m, int32_t which, double* out);
 
 /* Per-kernel timing for measurement tools.  hwe_profile_begin arms HIP events

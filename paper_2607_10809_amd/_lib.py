@@ -28,7 +28,8 @@ class HweOpts(C.Structure):
                 ("positivity", C.c_int32), ("time_rule", C.c_int32), ("deriv_weight", C.c_double),
                 ("walls", C.c_int32), ("n_regions", C.c_int32), ("pad_regions", C.c_int32),
                 ("regions", HweRegion * MAX_REGIONS), ("bstate", (C.c_double * 4) * 2),
-                ("shock_x0", C.c_double), ("shock_speed", C.c_double)]
+                ("shock_x0", C.c_double), ("shock_speed", C.c_double), ("edge_rule", C.c_int32),
+                ("pad_rule", C.c_int32)]
 
 
 class HweError(RuntimeError):

@@ -40,7 +40,9 @@ template <int M> __device__ __forceinline__ size_t slot_index(int i, int sl, int
   return size_t(i) * (12 * M) + size_t((sl * 3 + fl) * M + q);
 }
 
-template <int EQ, class Real, int TR>
+// GP: Gauss points per edge (2, or 3 for the 3-point rule; egp holds 2 GP rows
+// per side).
+template <int EQ, class Real, int TR, int GP>
 __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_cell_kernel(
     int N, int E, int NB, Params P, double dt, const double* __restrict__ wbar, const Real* __restrict__ grad,
     const double* __restrict__ lw, const Real* __restrict__ lg, const Real* __restrict__ R,
@@ -105,31 +107,39 @@ __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_cell_ke
     } else {
       normal_flux_jt<EQ>(P, WK, nx, ny, lF, len, lWf);
     }
-    // seeds of each Gauss-point lane (Gauss weights 1/2)
-    Real sAH[M], sAD[M], sAT[M];
-#pragma unroll
-    for (int q = 0; q < M; ++q) {
-      if (nb >= 0) {
-        sAH[q] = Real(0.25 * len * lF[q]);
-        sAD[q] = Real(0.25 * len * sigma * alpha * lF[q]);
-        sAT[q] = Real(0.25 * lG[q]);
-      } else {
-        sAH[q] = Real(0.5 * len * lF[q]);
-        sAD[q] = Real(0);
-        sAT[q] = Real(0.5 * lG[q]);
-      }
-    }
     Real a[6][M];
     load_record<6 * M>(R + size_t(ic) * (6 * M), &a[0][0]);
     double s = 0.0;
+    auto point = [&](int g) {
+      // seeds of Gauss point g (weight wg; 1/2 each with 2 points)
+      const double wg = GP == 2 ? 0.5 : (g == 1 ? 8.0 / 18.0 : 5.0 / 18.0);
+      Real sAH[M], sAD[M], sAT[M];
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      const Real X = egp[(4 * side + 2 * g) * sE + e];
-      const Real Y = egp[(4 * side + 2 * g + 1) * sE + e];
+      for (int q = 0; q < M; ++q) {
+        if (nb >= 0) {
+          sAH[q] = Real(wg * (0.5 * len * lF[q]));
+          sAD[q] = Real(wg * (0.5 * len * sigma * alpha * lF[q]));
+          sAT[q] = Real(wg * (0.5 * lG[q]));
+        } else {
+          sAH[q] = Real(wg * (len * lF[q]));
+          sAD[q] = Real(0);
+          sAT[q] = Real(wg * lG[q]);
+        }
+      }
+      const Real X = egp[(2 * GP * side + 2 * g) * sE + e];
+      const Real Y = egp[(2 * GP * side + 2 * g + 1) * sE + e];
       Real ADg[M];
       edge_lane_rev<EQ, Real, TR>(P, dt, a, WK, X, Y, Real(nx), Real(ny), sAH, sAD, sAT, la, lWf, ADg);
 #pragma unroll
-      for (int q = 0; q < M; ++q) s += 0.5 * lF[q] * double(ADg[q]);
+      for (int q = 0; q < M; ++q) s += wg * lF[q] * double(ADg[q]);
+    };
+    if constexpr (GP == 2) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) point(g);
+    } else {
+      // kept rolled: unrolling three point reversals spills
+#pragma unroll 1
+      for (int g = 0; g < GP; ++g) point(g);
     }
     if (valid) sface[f * sN + ic] = s;
   }
@@ -267,14 +277,21 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
   const HostMesh& h = M->h;
   const DevMesh& d = M->d;
   const int N = int(h.N), E = int(h.E), NB = int(h.NB);
-  if (P.time_rule == 1)
-    hipLaunchKernelGGL((adj_cell_kernel<EQ, Real, 1>), dim3(grid_for(4 * int64_t(N))), dim3(kBlock), 0, st, N, E, NB, P,
-                       dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl,
-                       d.area, d.slots, d.sface);
-  else
-    hipLaunchKernelGGL((adj_cell_kernel<EQ, Real, 0>), dim3(grid_for(4 * int64_t(N))), dim3(kBlock), 0, st, N, E, NB, P,
-                       dt, wbar, grad, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl,
-                       d.area, d.slots, d.sface);
+  const dim3 grid(grid_for(4 * int64_t(N)));
+#define HWE_ADJ_CELL(TRV, GPV)                                                                                     \
+  hipLaunchKernelGGL((adj_cell_kernel<EQ, Real, TRV, GPV>), grid, dim3(kBlock), 0, st, N, E, NB, P, dt, wbar, grad, \
+                     lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl, d.area, d.slots, d.sface)
+  if (M->opts.edge_rule == 3) {
+    if (P.time_rule == 1)
+      HWE_ADJ_CELL(1, 3);
+    else
+      HWE_ADJ_CELL(0, 3);
+  } else if (P.time_rule == 1) {
+    HWE_ADJ_CELL(1, 2);
+  } else {
+    HWE_ADJ_CELL(0, 2);
+  }
+#undef HWE_ADJ_CELL
   hipLaunchKernelGGL((adj_gather_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg,
                      d.nbr, d.nbr_back, d.cell_edge, d.enl, d.inv_area, nl, d.slots, d.sface, lw_out, lg_out);
   hipError_t err = hipGetLastError();

@@ -558,16 +558,8 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int q, int N, int NB, 
       Y[f + 1] = Y[0] - Real(2) * gny[f] * vn;
     }
   }
-  const Real d0 = Real(dW[0]), d1 = Real(dW[1]), d2 = Real(dW[2]);
   Real c[5];
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    const Real* t = tb + (kTblP1 + j * 11) * kTile;
-    Real s = t[0] * d0 + t[kTile] * d1 + t[2 * kTile] * d2;
-#pragma unroll
-    for (int l = 0; l < 4; ++l) s += t[(3 + l) * kTile] * V[l] + t[(7 + l) * kTile] * Y[l];
-    c[j] = s;
-  }
+  step1_apply<Real>(tb, Real(dW[0]), Real(dW[1]), Real(dW[2]), V, Y, c);
   Real bl[3], cl[3], pdx[3], pdy[3], piv[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
@@ -679,17 +671,24 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int q, int N, int NB, 
     lY[f + 1] += lcl[f] - pdy[f] * piv[f] * lt;
     ldW[f] += double(piv[f] * lt);
   }
-  // Step 1 reverse
+  // Step 1 reverse: c = Md dW + Z^T u, u = Q v
+  Real lu[2] = {Real(0), Real(0)};
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
-    const Real* t = tb + (kTblP1 + j * 11) * kTile;
+    const Real* t = tb + (kTblMd + 3 * j) * kTile;
     ldW[0] += double(t[0] * lc[j]);
     ldW[1] += double(t[kTile] * lc[j]);
     ldW[2] += double(t[2 * kTile] * lc[j]);
+    lu[0] += tb[(kTblZ + j) * kTile] * lc[j];
+    lu[1] += tb[(kTblZ + 5 + j) * kTile] * lc[j];
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const Real* t = tb + (kTblQ + 8 * k) * kTile;
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
-      lV[l] += t[(3 + l) * kTile] * lc[j];
-      lY[l] += t[(7 + l) * kTile] * lc[j];
+      lV[l] += t[l * kTile] * lu[k];
+      lY[l] += t[(4 + l) * kTile] * lu[k];
     }
   }
   // stencil inputs -> slots

@@ -87,6 +87,7 @@ hwe_status hwe_opts_default(hwe_opts* o) {
   o->deriv_weight = 1.0;
   o->walls = 0;
   o->n_regions = 0;
+  o->edge_rule = 2;
   return HWE_OK;
 }
 
@@ -126,7 +127,8 @@ hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tr
   if (o.eq < HWE_ADVECTION || o.eq > HWE_EULER || o.bc < 0 || o.bc > 1 || o.prec < 0 || o.prec > 1 ||
       o.positivity < 0 || o.positivity > 1 || (o.positivity && o.eq != HWE_EULER) || o.time_rule < 0 ||
       o.time_rule > 1 || !(o.deriv_weight > 0.0) || !(o.deriv_weight < 1e300) || o.walls < 0 || o.walls > 15 ||
-      (o.walls && (o.eq != HWE_EULER || o.bc != HWE_BC_TRANSMISSIVE)) || !regions_ok(o)) {
+      (o.walls && (o.eq != HWE_EULER || o.bc != HWE_BC_TRANSMISSIVE)) || !regions_ok(o) ||
+      (o.edge_rule != 2 && o.edge_rule != 3) || (o.edge_rule == 3 && o.positivity)) {
     set_error("invalid option value");
     return HWE_EINVAL;
   }
@@ -390,6 +392,9 @@ hwe_status hwe_debug_host_array(hwe_mesh m, int32_t which, double* out) {
       return HWE_OK;
     case 4:
       for (size_t k = 0; k < h.nbr.size(); ++k) out[k] = double(h.nbr[k]);
+      return HWE_OK;
+    case 6:
+      std::memcpy(out, h.p1f.data(), h.p1f.size() * sizeof(double));
       return HWE_OK;
     case 5:
       // boundary kind of each face, -1 on interior faces

@@ -14,6 +14,10 @@ void set_error(const std::string& msg);
 
 // Number of double entries of the per-cell Step-1 map (5 coefficients x 11 inputs).
 constexpr int kP1 = 55;
+// The factored Step-1 map of the device tables: rows kP1Md + 3j + c (the map's
+// dW columns, 5 x 3), kP1Z + 5k + j (the null-space basis, 2 x 5) and
+// kP1Q + 8k + v (the reduced solution on V0..V3, Y0..Y3, 2 x 8); 41 rows.
+constexpr int kP1Md = 0, kP1Z = 15, kP1Q = 25, kP1F = 41;
 // Per-cell Step-2 data: (dx, dy, 1/(1 + dx^2 + dy^2)) for each of the three faces.
 constexpr int kP2 = 9;
 // Per-edge geometry: nx, ny, length, then the Gauss-point offsets (X, Y) from the
@@ -33,7 +37,8 @@ struct HostMesh {
   std::vector<double> bnd_n;       // [4][NB] outward unit normal of boundary face b, its kind
                                    // (hwe_bnd_kind, as a double) and the x of its midpoint
   bool special_bnd = false;        // some boundary face is a wall or prescribed
-  std::vector<double> p1;          // [55][N] Step-1 map (row-major 5 x 11 per cell)
+  std::vector<double> p1;          // [55][N] Step-1 map (row-major 5 x 11 per cell; host tests)
+  std::vector<double> p1f;         // [41][N] factored Step-1 map (device tables)
   std::vector<double> p2;          // [9][N] Step-2 data
   std::vector<int32_t> cell_edge;  // [3][N] (edge << 1) | (cell is the edge's second cell)
   std::vector<double> nl;          // [6][N] outward normal times length: x of faces 0..2, then y
@@ -44,6 +49,9 @@ struct HostMesh {
                                    // on a boundary edge -1 (transmissive), -2 (wall) or -3 - b
                                    // (prescribed state; b = the boundary face)
   std::vector<double> egeo;        // [11][E]
+  std::vector<double> egp3;        // [12][E] with the 3-point edge rule: offsets (X, Y) from the
+                                   // centroid of the first cell of points 0..2 (rows 2g, 2g+1),
+                                   // then from the second cell's (rows 6 + 2g, 7 + 2g)
   double rmin = 0.0;               // smallest inradius
 };
 
@@ -63,7 +71,7 @@ struct DevMesh {
   double* inv_area = nullptr;
   double* gpc = nullptr;    // [12][N] (limiter only)
   double* enl = nullptr;    // [3][E] edge normal and length (FP64 in both precisions)
-  double* egp = nullptr;    // [8][E] Gauss-point offsets (FP64 path)
+  double* egp = nullptr;    // [8][E] Gauss-point offsets (FP64 path); [12][E] with the 3-point rule
   // FP32 copies for the mixed path
   float* tblf = nullptr;
   float* nlf = nullptr;

@@ -14,6 +14,8 @@
 //                   normal flux; lanes are then combined with cross-lane
 //                   shuffles into the local Lax-Friedrichs edge flux F_e and the
 //                   edge integral of the interface value at t_n + dt.
+//   edge3_kernel  : the same with the 3-point edge rule, eight work-items per
+//                   edge (one idle lane per side).
 //   update_kernel : one work-item per cell gathers its three edges: eq. (flx)
 //                   accumulated in FP64, and the Green-Gauss derivative
 //                   averages, eq. (derave2d2), written in a form that is exactly
@@ -203,6 +205,109 @@ __global__ __launch_bounds__(kBlock) void edge_kernel(int E, int N, int NB, Para
     edge_value<EQ, Real>(e, E, second, AT, OT, G);
 }
 
+// The 3-point edge rule: eight work-items per edge, (side, Gauss point g =
+// 0..2) plus one idle lane per side (g = 3), so that the sums over the points
+// stay within a quad (DPP) and the two sides meet across a 4-lane shuffle.
+// Weights 5/18, 8/18, 5/18 at 1/2 -+ sqrt(15)/10 and 1/2 along the edge.
+template <int EQ, class Real, int TR>
+__global__ __launch_bounds__(kBlock) void edge3_kernel(int E, int N, int NB, Params P, double dt,
+                                                        const double* __restrict__ wbar,
+                                                        const Real* __restrict__ R,
+                                                        const int32_t* __restrict__ ecell,
+                                                        const double* __restrict__ bnd_n,
+                                                        const double* __restrict__ enl,
+                                                        const Real* __restrict__ egp, double* __restrict__ F,
+                                                        Real* __restrict__ G) {
+  constexpr int M = NComp<EQ>::m;
+  const int gid = xcd_block_id() * kBlock + threadIdx.x;
+  const int e = gid >> 3, side = (gid >> 2) & 1, g = gid & 3;
+  const bool valid = e < E;
+  const int ec = valid ? e : E - 1;
+  const int cell = valid ? ecell[side * E + ec] : -1;
+  const int cc = cell >= 0 ? cell : ecell[ec];
+  const double nx = enl[ec], ny = enl[E + ec], len = enl[2 * E + ec];
+  const bool point = g < 3;
+  double Wb[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) Wb[q] = wbar[q * size_t(N) + cc];
+  Real dl[M], Wt[M], Wtt[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) dl[q] = Wt[q] = Wtt[q] = Real(0);
+  if (cell >= 0 && point) {
+    const Real X = egp[(6 * side + 2 * g) * size_t(E) + ec];
+    const Real Y = egp[(6 * side + 2 * g + 1) * size_t(E) + ec];
+    edge_point_at<EQ, Real>(cell, P, Wb, R, X, Y, dl, Wt, Wtt);
+  }
+  const bool wall = cell == -2;
+  const bool presc = cell <= -3;
+  if (presc) {
+    const int b = -cell - 3;
+    prescribed_state<M>(P, bnd_n[2 * size_t(NB) + b], bnd_n[3 * size_t(NB) + b], Wb);
+  }
+  if constexpr (EQ == EQ_EUL) {
+    // a wall lane takes the first side's values at its point, momentum reflected
+    if (__ballot(wall) != 0) {
+      Real pdl[M], pWt[M], pWtt[M];
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        pdl[q] = __shfl_xor(dl[q], 4);
+        pWt[q] = __shfl_xor(Wt[q], 4);
+        pWtt[q] = __shfl_xor(Wtt[q], 4);
+      }
+      if (wall) {
+        const Real rx = Real(nx), ry = Real(ny);
+        reflect_momentum(rx, ry, pdl);
+        reflect_momentum(rx, ry, pWt);
+        reflect_momentum(rx, ry, pWtt);
+        reflect_momentum(nx, ny, Wb);
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          dl[q] = pdl[q];
+          Wt[q] = pWt[q];
+          Wtt[q] = pWtt[q];
+        }
+      }
+    }
+  }
+  Real AH[M], AD[M], AT[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) AH[q] = AD[q] = AT[q] = Real(0);
+  if (point && (cell >= 0 || wall || presc))
+    edge_nodes<EQ, Real, TR>(P, dt, Wb, Real(nx), Real(ny), dl, Wt, Wtt, AH, AD, AT);
+  const Real wg = g == 1 ? Real(8.0 / 18.0) : (point ? Real(5.0 / 18.0) : Real(0));
+  double Hb[M];
+  const double lam = side_terms<EQ>(P, Wb, nx, ny, Hb);
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    AH[q] *= wg;
+    AD[q] *= wg;
+    AT[q] *= wg;
+    AH[q] += quad_perm<kQuadXor1>(AH[q]);
+    AD[q] += quad_perm<kQuadXor1>(AD[q]);
+    AT[q] += quad_perm<kQuadXor1>(AT[q]);
+    AH[q] += quad_perm<kQuadXor2>(AH[q]);
+    AD[q] += quad_perm<kQuadXor2>(AD[q]);
+    AT[q] += quad_perm<kQuadXor2>(AT[q]);
+  }
+  Real OH[M], OD[M], OT[M];
+  double Wo[M], Ho[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    OH[q] = __shfl_xor(AH[q], 4);
+    OD[q] = __shfl_xor(AD[q], 4);
+    OT[q] = __shfl_xor(AT[q], 4);
+    Wo[q] = __shfl_xor(Wb[q], 4);
+    Ho[q] = __shfl_xor(Hb[q], 4);
+  }
+  const double lo = __shfl_xor(lam, 4);
+  const bool second = __shfl_xor(cell, 4) != -1;
+  if (!valid || side != 0) return;
+  if (g == 0)
+    edge_flux<EQ, Real>(e, E, len, second, Wb, Hb, lam, Wo, Ho, lo, AH, AD, OH, OD, F);
+  else if (g == 1)
+    edge_value<EQ, Real>(e, E, second, AT, OT, G);
+}
+
 template <int EQ, class Real>
 __global__ __launch_bounds__(kBlock) void update_kernel(int N, int E, int NB, Params P, double dt,
                                                          const double* __restrict__ wbar,
@@ -360,12 +465,20 @@ hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, cons
   hipLaunchKernelGGL((recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * Mc)), dim3(kBlock), 0, st, N, NB, P, wbar_in, grad_in,
                      d.nbr, d.bnd_n, tbl, d.area, d.gpc, R);
   if (ev) hipEventRecord(ev[1], st);
-  if (P.time_rule == 1)
+  if (M->opts.edge_rule == 3) {
+    if (P.time_rule == 1)
+      hipLaunchKernelGGL((edge3_kernel<EQ, Real, 1>), dim3(grid_for(8 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB,
+                         P, dt, wbar_in, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
+    else
+      hipLaunchKernelGGL((edge3_kernel<EQ, Real, 0>), dim3(grid_for(8 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB,
+                         P, dt, wbar_in, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
+  } else if (P.time_rule == 1) {
     hipLaunchKernelGGL((edge_kernel<EQ, Real, 1>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB, P,
                        dt, wbar_in, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
-  else
+  } else {
     hipLaunchKernelGGL((edge_kernel<EQ, Real, 0>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB, P,
                        dt, wbar_in, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
+  }
   if (ev) hipEventRecord(ev[2], st);
   hipLaunchKernelGGL((update_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, NB, P, dt, wbar_in,
                      d.bnd_n, d.nbr, d.cell_edge, nl, d.inv_area, F, G, wbar_out, grad_out);
@@ -420,7 +533,8 @@ static std::vector<double> tiled_tables(const HostMesh& h) {
   std::vector<double> t(size_t(tiles) * kTblRows * kTile, 0.0);
   for (int i = 0; i < N; ++i) {
     double* col = t.data() + tbl_col(i);
-    for (int k = 0; k < 55; ++k) col[(kTblP1 + k) * kTile] = h.p1[size_t(k) * N + i];
+    static_assert(kTblMd == kP1Md && kTblZ == kP1Z && kTblQ == kP1Q && kTblP2 == kP1F, "table rows");
+    for (int k = 0; k < kP1F; ++k) col[k * kTile] = h.p1f[size_t(k) * N + i];
     for (int k = 0; k < 9; ++k) col[(kTblP2 + k) * kTile] = h.p2[size_t(k) * N + i];
     for (int k = 0; k < 3; ++k) col[(kTblMom + k) * kTile] = h.mom[size_t(k) * N + i];
   }
@@ -453,11 +567,17 @@ hwe_status upload_mesh(hwe_mesh_s* M) {
   if (M->opts.prec == HWE_FP64) {
     HWE_TRY(dev_copy(&d.tbl, tiled.data(), tiled.size()));
     HWE_TRY(dev_copy(&d.nl, h.nl.data(), h.nl.size()));
-    HWE_TRY(dev_copy(&d.egp, h.egeo.data() + 3 * E, 8 * E));
+    if (M->opts.edge_rule == 3)
+      HWE_TRY(dev_copy(&d.egp, h.egp3.data(), h.egp3.size()));
+    else
+      HWE_TRY(dev_copy(&d.egp, h.egeo.data() + 3 * E, 8 * E));
   } else {
     HWE_TRY(dev_copy_f32(&d.tblf, tiled));
     HWE_TRY(dev_copy_f32(&d.nlf, h.nl));
-    HWE_TRY(dev_copy_f32(&d.egpf, std::vector<double>(h.egeo.begin() + 3 * E, h.egeo.end())));
+    if (M->opts.edge_rule == 3)
+      HWE_TRY(dev_copy_f32(&d.egpf, h.egp3));
+    else
+      HWE_TRY(dev_copy_f32(&d.egpf, std::vector<double>(h.egeo.begin() + 3 * E, h.egeo.end())));
   }
   const size_t rs = M->opts.prec == HWE_FP64 ? sizeof(double) : sizeof(float);
   HWE_TRY(dev_alloc(&d.R, 6 * m * N * rs));

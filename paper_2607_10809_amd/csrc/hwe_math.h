@@ -49,12 +49,16 @@ template <int CTRL> __device__ __forceinline__ double quad_perm(double v) {
 
 // Per-cell reconstruction tables, tiled: cells are grouped in tiles of kTile
 // consecutive cells; a tile stores kTblRows rows of kTile values (row-major),
-// so the tables of one tile are one contiguous block.  Rows: the 5 x 11 Step-1
-// map (row-major), the Step-2 data (dx, dy, 1/(1 + d.d) per face) and the
-// central second moments (Mxx, Mxy, Myy).  The table of cell i starts at
-// (i / kTile) * kTblRows * kTile + i % kTile.
+// so the tables of one tile are one contiguous block.  The table of cell i
+// starts at (i / kTile) * kTblRows * kTile + i % kTile.
 constexpr int kTile = 64;
-constexpr int kTblP1 = 0, kTblP2 = 55, kTblMom = 64, kTblRows = 67;
+// Rows: the Step-1 map in factored form, c = Md dW + Z^T (Q v) with v = (V0..V3,
+// Y0..Y3) (kTblMd: Md, 5 x 3; kTblZ: Z, 2 x 5, the null-space basis of the
+// three average constraints; kTblQ: Q, 2 x 8, the reduced least-squares
+// solution) -- 41 numbers in place of the 55 of the 5 x 11 map -- then the
+// Step-2 data (dx, dy, 1/(w^2 + d.d)) per face and the central second moments
+// (Mxx, Mxy, Myy).
+constexpr int kTblMd = 0, kTblZ = 15, kTblQ = 25, kTblP2 = 41, kTblMom = 50, kTblRows = 53;
 __host__ __device__ __forceinline__ size_t tbl_col(int i) {
   return size_t(i / kTile) * (kTblRows * kTile) + size_t(i % kTile);
 }

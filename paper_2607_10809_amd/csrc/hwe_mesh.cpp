@@ -127,8 +127,12 @@ void apply_qt(const double* a, int rows, int cols, const double* tau, double* y)
 // Step-1 map for one cell.  Inputs are in K0's frame, lengths scaled by
 // h = sqrt(|K0|) and areas by |K0|:  d[l] (neighbour centroid offsets),
 // dm[l] (neighbour moments minus K0's moments), ar[l] = |Kl| / |K0|.
-// Output: M (5 x 11, row-major) in the scaled variables; false if singular.
-bool step1_map(const double d[3][2], const double dm[3][3], const double ar[3], double M[5][11]) {
+// Output: M (5 x 11, row-major) in the scaled variables, and its factored form
+// for the device tables: the derivative-average columns of M are Z^T Q with Z
+// (2 x 5) the null-space basis of the constraints and Q (2 x 8) the reduced
+// least-squares solution applied to (V0..V3, Y0..Y3); false if singular.
+bool step1_map(const double d[3][2], const double dm[3][3], const double ar[3], double M[5][11], double Zo[2][5],
+               double Qo[2][8]) {
   // constraint matrix C (3 x 5), stored transposed column-major: Ct is 5 x 3
   double Ct[5 * 3];
   for (int l = 0; l < 3; ++l) {
@@ -212,6 +216,18 @@ bool step1_map(const double d[3][2], const double dm[3][3], const double ar[3], 
       for (int r = 0; r < 6; ++r) s -= Mb[j][r] * AP[r];
       Md[j][c] = s;
     }
+  }
+  for (int k = 0; k < 2; ++k) {
+    for (int j = 0; j < 5; ++j) Zo[k][j] = Z[k][j];
+    double v0 = 0, y0 = 0;
+    for (int l = 0; l < 3; ++l) {
+      Qo[k][1 + l] = Bp[k][l] * ar[l];
+      Qo[k][5 + l] = Bp[k][3 + l] * ar[l];
+      v0 += Bp[k][l];
+      y0 += Bp[k][3 + l];
+    }
+    Qo[k][0] = v0;
+    Qo[k][4] = y0;
   }
   // assemble the 11 input columns: dW1..3, V0, V1..3, Y0, Y1..3 where the
   // scaled right-hand sides are b_x,l = ar_l V_l + V0 (times h, applied by the caller)
@@ -414,6 +430,9 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
   const int64_t E = n_edges;
   h.ecell.assign(2 * E, -1);
   h.egeo.assign(size_t(kEG) * E, 0.0);
+  const bool rule3 = o.edge_rule == 3;
+  if (rule3) h.egp3.assign(12 * size_t(E), 0.0);
+  const double gs3[3] = {0.5 - std::sqrt(15.0) / 10.0, 0.5, 0.5 + std::sqrt(15.0) / 10.0};
   std::vector<int32_t> face_edge(3 * N, -1);  // caller face slot -> edge index << 1 | second
   const double gs[2] = {0.5 - std::sqrt(3.0) / 6.0, 0.5 + std::sqrt(3.0) / 6.0};
   for (int64_t e = 0; e < E; ++e) {
@@ -440,6 +459,17 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
         h.egeo[(8 + 2 * g) * E + e] = py + sy - G[r.c1].cy;
       }
     }
+    if (rule3)
+      for (int g = 0; g < 3; ++g) {
+        double px = t.x[f] + gs3[g] * ex, py = t.y[f] + gs3[g] * ey;
+        h.egp3[(2 * g) * E + e] = px - G[r.c0].cx;
+        h.egp3[(2 * g + 1) * E + e] = py - G[r.c0].cy;
+        if (r.c1 >= 0) {
+          double sx = shift[6 * r.c1 + 2 * r.f1], sy = shift[6 * r.c1 + 2 * r.f1 + 1];
+          h.egp3[(6 + 2 * g) * E + e] = px + sx - G[r.c1].cx;
+          h.egp3[(7 + 2 * g) * E + e] = py + sy - G[r.c1].cy;
+        }
+      }
     face_edge[3 * r.c0 + r.f0] = int32_t(e << 1);
     if (r.c1 >= 0) face_edge[3 * r.c1 + r.f1] = int32_t((e << 1) | 1);
   }
@@ -452,6 +482,7 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
   h.nbr_back.assign(3 * N, -1);
   h.bnd_n.assign(4 * std::max<int64_t>(h.NB, 1), 0);
   h.p1.assign(size_t(kP1) * N, 0);
+  h.p1f.assign(size_t(kP1F) * N, 0);
   h.p2.assign(size_t(kP2) * N, 0);
   h.cell_edge.assign(3 * N, 0);
   h.nl.assign(6 * N, 0);
@@ -541,7 +572,8 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
     }
     rmin = std::min(rmin, 2.0 * g0.A / per);
     double Ms[5][11];
-    if (!step1_map(d, dm, ar, Ms)) {
+    double Zs[2][5], Qs[2][8];
+    if (!step1_map(d, dm, ar, Ms, Zs, Qs)) {
       std::ostringstream s;
       s << "rank-deficient Step-1 least squares at triangle " << k;
       return fail(HWE_ESINGULAR, s.str());
@@ -555,7 +587,11 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
         if (c >= 3) v *= hs;
         h.p1[size_t(j * 11 + c) * N + i] = v;
       }
+      for (int c = 0; c < 3; ++c) h.p1f[size_t(kP1Md + 3 * j + c) * N + i] = Ms[j][c] * sj;
+      for (int k = 0; k < 2; ++k) h.p1f[size_t(kP1Z + 5 * k + j) * N + i] = Zs[k][j] * sj;
     }
+    for (int k = 0; k < 2; ++k)
+      for (int c = 0; c < 8; ++c) h.p1f[size_t(kP1Q + 8 * k + c) * N + i] = Qs[k][c] * hs;
   }
   h.rmin = rmin;
   return HWE_OK;

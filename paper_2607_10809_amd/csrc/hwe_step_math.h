@@ -100,6 +100,28 @@ __host__ __device__ __forceinline__ Stencil<Real> gather_stencil(int i, int q, i
   return S;
 }
 
+// Step 1 from the factored table (tb: the cell's column, row k at
+// tb[k * kTile]): u = Q (V0..V3, Y0..Y3), then c = Md (dW1..dW3) + Z^T u.
+template <class Real>
+__host__ __device__ __forceinline__ void step1_apply(const Real* __restrict__ tb, Real d0, Real d1, Real d2,
+                                                    const Real (&V)[4], const Real (&Y)[4], Real (&c)[5]) {
+  Real u[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const Real* t = tb + (kTblQ + 8 * k) * kTile;
+    Real s = Real(0);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) s += t[l * kTile] * V[l] + t[(4 + l) * kTile] * Y[l];
+    u[k] = s;
+  }
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const Real* t = tb + (kTblMd + 3 * j) * kTile;
+    c[j] = t[0] * d0 + t[kTile] * d1 + t[2 * kTile] * d2 + tb[(kTblZ + j) * kTile] * u[0] +
+           tb[(kTblZ + 5 + j) * kTile] * u[1];
+  }
+}
+
 // Reconstruction of component q of cell i (Sec. 2.2) from its stencil.
 // Writes the six coefficients a0..a5 of R - Wbar (monomials about the centroid).
 // tb: the cell's column of the tiled geometry table (row k at tb[k * kTile]).
@@ -167,17 +189,9 @@ __host__ __device__ __forceinline__ void recon_from_stencil(int i, int q, int N,
       }
     }
   }
-  // Step 1: c = P1 (dW1..3, V0..3, Y0..3); W differences formed in FP64
-  const Real d0 = Real(dW[0]), d1 = Real(dW[1]), d2 = Real(dW[2]);
+  // Step 1: c = Md dW + Z^T (Q v); W differences formed in FP64
   Real c[5];
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    const Real* t = tb + (kTblP1 + j * 11) * kTile;
-    Real s = t[0] * d0 + t[kTile] * d1 + t[2 * kTile] * d2;
-#pragma unroll
-    for (int l = 0; l < 4; ++l) s += t[(3 + l) * kTile] * V[l] + t[(7 + l) * kTile] * Y[l];
-    c[j] = s;
-  }
+  step1_apply<Real>(tb, Real(dW[0]), Real(dW[1]), Real(dW[2]), V, Y, c);
   // Step 2: linear candidates on {K0, K_l}
   Real bl[3], cl[3];
 #pragma unroll
@@ -317,23 +331,19 @@ __host__ __device__ __forceinline__ void positivity_theta(double gam, const doub
 
 // ------------------------------------------------------------------ edge lane
 // One side (0: the edge's first cell, 1: its second) at one Gauss point, in two
-// parts.  edge_point: the reconstruction's offset d = W - Wbar at the point and
-// its time derivatives W_t, W_tt by the Lax-Wendroff procedure (zeros when
-// cell < 0).  egp: [8][E] Gauss-point offsets from the centroids (side 0
-// points 0, 1; side 1 points 0, 1).
+// parts.  edge_point_at: the reconstruction's offset d = W - Wbar at the point
+// (X, Y) from the cell's centroid and its time derivatives W_t, W_tt by the
+// Lax-Wendroff procedure.  edge_point: the same at Gauss point g of the
+// 2-point rule (zeros when cell < 0), egp: [8][E] Gauss-point offsets from the
+// centroids (side 0 points 0, 1; side 1 points 0, 1).
 template <int EQ, class Real>
-__host__ __device__ __forceinline__ void edge_point(int e, int cell, int side, int g, int E, const Params& P,
-                                                   const double (&Wbd)[NComp<EQ>::m], const Real* __restrict__ R,
-                                                   const Real* __restrict__ egp, Real (&dl)[NComp<EQ>::m],
-                                                   Real (&Wt)[NComp<EQ>::m], Real (&Wtt)[NComp<EQ>::m]) {
+__host__ __device__ __forceinline__ void edge_point_at(int cell, const Params& P,
+                                                      const double (&Wbd)[NComp<EQ>::m], const Real* __restrict__ R,
+                                                      Real X, Real Y, Real (&dl)[NComp<EQ>::m],
+                                                      Real (&Wt)[NComp<EQ>::m], Real (&Wtt)[NComp<EQ>::m]) {
   constexpr int M = NComp<EQ>::m;
-#pragma unroll
-  for (int q = 0; q < M; ++q) dl[q] = Wt[q] = Wtt[q] = Real(0);
-  if (cell < 0) return;
   Real ac[6][M];
   load_record<6 * M>(R + size_t(cell) * (6 * M), &ac[0][0]);
-  const Real X = egp[(4 * side + 2 * g) * E + e];
-  const Real Y = egp[(4 * side + 2 * g + 1) * E + e];
   Real D[6][M];
 #pragma unroll
   for (int q = 0; q < M; ++q) {
@@ -347,6 +357,20 @@ __host__ __device__ __forceinline__ void edge_point(int e, int cell, int side, i
     D[5][q] = Real(2) * a5;
   }
   lax_wendroff<EQ, Real>(P, D, Wt, Wtt);
+}
+
+template <int EQ, class Real>
+__host__ __device__ __forceinline__ void edge_point(int e, int cell, int side, int g, int E, const Params& P,
+                                                   const double (&Wbd)[NComp<EQ>::m], const Real* __restrict__ R,
+                                                   const Real* __restrict__ egp, Real (&dl)[NComp<EQ>::m],
+                                                   Real (&Wt)[NComp<EQ>::m], Real (&Wtt)[NComp<EQ>::m]) {
+  constexpr int M = NComp<EQ>::m;
+#pragma unroll
+  for (int q = 0; q < M; ++q) dl[q] = Wt[q] = Wtt[q] = Real(0);
+  if (cell < 0) return;
+  const Real X = egp[(4 * side + 2 * g) * E + e];
+  const Real Y = egp[(4 * side + 2 * g + 1) * E + e];
+  edge_point_at<EQ, Real>(cell, P, Wbd, R, X, Y, dl, Wt, Wtt);
 }
 
 // edge_nodes: the time integrals, over the nodes of the time rule TR (0:

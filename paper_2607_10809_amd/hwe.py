@@ -27,7 +27,8 @@ def _stream(stream=None):
 
 def make_opts(eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp64", adv=(1.0, 1.0),
               gas_gamma=1.4, lin_w=(0.94, 0.02, 0.02, 0.02), eps=1e-8, linear_weights=False, device=0,
-              positivity=False, time_rule=0, deriv_weight=1.0, walls=0, regions=(), states=(), shock=()) -> HweOpts:
+              positivity=False, time_rule=0, deriv_weight=1.0, walls=0, regions=(), states=(), shock=(),
+              edge_rule=2) -> HweOpts:
     """Options of a mesh handle.  regions: boundary regions, first match wins,
     as (kind, (x0, x1, y0, y1)) with kind "transmissive", "wall", "A", "B" or
     "moving"; states: the conservative states (A, B); shock: (x0, speed) of the
@@ -61,6 +62,7 @@ def make_opts(eq="euler", bc="periodic", box=(0.0, 1.0, 0.0, 1.0), precision="fp
         o.bstate[a][:len(st)] = st
     if shock:
         o.shock_x0, o.shock_speed = float(shock[0]), float(shock[1])
+    o.edge_rule = int(edge_rule)
     return o
 
 
@@ -241,6 +243,29 @@ class Mesh:
                 steps += 1
         return bufs[cur][0], bufs[cur][1], steps
 
+    def capture_steps(self, a, b, dt, nsteps):
+        """Record nsteps (even) steps of size dt that ping-pong between the
+        state buffers a and b (a -> b -> a ...) into a HIP graph; replaying it
+        advances the state held in a by nsteps steps.  The launches are
+        recorded once, so the mesh must not depend on the time (no moving
+        boundary switch)."""
+        if nsteps <= 0 or nsteps % 2:
+            raise ValueError("nsteps must be positive and even")
+        if any(self.opts.regions[r].kind == BND_KINDS["moving"] for r in range(self.opts.n_regions)):
+            raise ValueError("a captured step cannot follow a moving boundary switch")
+        self._check_state(*a)
+        self._check_state(*b)
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for k in range(nsteps):
+                    src, dst = (a, b) if k % 2 == 0 else (b, a)
+                    hwe_step(self._h, src[0], src[1], dst[0], dst[1], dt, s)
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        return g
+
     def adjoint(self, wbar, grad, lam_wbar, lam_grad, dt, out=None, stream=None, recon=None):
         """J^T lam at the state (wbar, grad).  recon: the buffer that
         step(wbar, grad, ..., keep=recon) filled; skips the reconstruction."""
@@ -282,7 +307,7 @@ class Mesh:
         return [ms[0], ms[1], ms[2]], n.value
 
     def host_array(self, which):
-        sizes = {0: (55, self.N), 1: (2, self.N), 2: (self.N,), 3: (3, self.N), 4: (3, self.N), 5: (3, self.N)}
+        sizes = {0: (55, self.N), 1: (2, self.N), 2: (self.N,), 3: (3, self.N), 4: (3, self.N), 5: (3, self.N), 6: (41, self.N)}
         out = np.empty(sizes[which])
         check(self._L.hwe_debug_host_array(self._h, int(which), out.ctypes.data_as(C.POINTER(C.c_double))))
         return out

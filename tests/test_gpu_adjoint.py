@@ -71,15 +71,16 @@ def test_dot_product_against_oracle_jvp(case):
         assert abs(a - b) <= 1e-11 * scale
 
 
-@pytest.mark.parametrize("time_rule,wd", [(1, 1.0), (1, 0.3)])
-def test_dot_product_variants(time_rule, wd):
-    """The adjoint with the Gauss-Legendre time rule and weighted Step-2 rows."""
+@pytest.mark.parametrize("time_rule,wd,er", [(1, 1.0, 2), (1, 0.3, 2), (0, 1.0, 3), (1, 0.3, 3)])
+def test_dot_product_variants(time_rule, wd, er):
+    """The adjoint with the Gauss-Legendre time rule, weighted Step-2 rows and
+    the 3-point edge rule."""
     rng = np.random.default_rng(17)
     wl = vortex_workload(n=24)
-    om = OracleMesh.from_workload(wl, time_rule=time_rule, deriv_weight=wd)
+    om = OracleMesh.from_workload(wl, time_rule=time_rule, deriv_weight=wd, edge_rule=er)
     s0 = _perturbed(wl, rng)
     dt = om.max_dt(s0, 0.3)
-    mesh = _mesh(wl, time_rule=time_rule, deriv_weight=wd)
+    mesh = _mesh(wl, time_rule=time_rule, deriv_weight=wd, edge_rule=er)
     for _ in range(2):
         v = rng.normal(size=s0.shape)
         lam = rng.normal(size=s0.shape)
@@ -87,7 +88,7 @@ def test_dot_product_variants(time_rule, wd):
         vj = _gpu_vjp(mesh, s0, lam, dt)
         a, b = float(np.sum(vj * v)), float(np.sum(lam * jv))
         scale = float(np.abs(vj * v).sum())
-        print(f"time rule {time_rule}, weight {wd}: <J^T l, v> = {a}, <l, J v> = {b}", flush=True)
+        print(f"time rule {time_rule}, weight {wd}, edge rule {er}: <J^T l, v> = {a}, <l, J v> = {b}", flush=True)
         assert abs(a - b) <= 1e-11 * scale
 
 

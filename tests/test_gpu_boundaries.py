@@ -48,6 +48,8 @@ CASES = {
     "wedge": (lambda: wedge_workload(nx=48, ny=24), {}, 12, 150),
     "forward_step": (lambda: forward_step_workload(n=20), {"positivity": 1}, 30, 300),
     "moving_shock": (lambda: moving_shock_workload(nx=60), {}, 40, 150),
+    "double_mach_edge3": (lambda: double_mach_workload(n=12), {"edge_rule": 3}, 30, 120),
+    "shu_osher_edge3": (lambda: shu_osher_workload(nx=120), {"edge_rule": 3}, 40, 200),
 }
 
 

@@ -66,7 +66,8 @@ def test_error_statuses():
     for bad_opts in (dict(eq="euler", gas_gamma=0.5), dict(eq="burgers", time_rule=2),
                      dict(eq="burgers", deriv_weight=0.0), dict(eq="burgers", deriv_weight=float("nan")),
                      dict(eq="burgers", positivity=True), dict(eq="burgers", walls=4),
-                     dict(eq="euler", walls=16)):
+                     dict(eq="euler", walls=16), dict(eq="burgers", edge_rule=4),
+                     dict(eq="euler", edge_rule=3, positivity=True)):
         with pytest.raises(HweError) as e:   # bad options
             Mesh(mesh.nodes, mesh.tris, bc="transmissive", box=box, device=-1, **bad_opts)
         assert e.value.status == -1, bad_opts
@@ -149,6 +150,22 @@ def test_bad_boundary_regions_are_rejected():
     with pytest.raises(HweError) as e:                                        # regions need boundaries
         Mesh(pm.nodes, pm.tris, eq="euler", bc="periodic", box=box, device=-1, regions=good, states=st)
     assert e.value.status == -1
+
+
+def test_factored_step1_tables_equal_the_map():
+    """The device tables hold the Step-1 map as Md (dW columns), Z and Q with
+    the V and Y columns equal to Z^T Q."""
+    mesh = split_square_mesh(8, (0.0, 1.0, 0.0, 1.0), jitter=0.25, seed=4, periodic=False)
+    hm = _host_mesh(mesh)
+    P1 = hm.host_array(0).reshape(5, 11, hm.N)
+    F = hm.host_array(6)
+    Md = F[0:15].reshape(5, 3, hm.N)
+    Z = F[15:25].reshape(2, 5, hm.N)
+    Q = F[25:41].reshape(2, 8, hm.N)
+    assert np.array_equal(Md, P1[:, 0:3])
+    ZQ = np.einsum("kjn,kvn->jvn", Z, Q)
+    scale = np.abs(P1[:, 3:]).max(axis=(0, 1))
+    assert (np.abs(ZQ - P1[:, 3:]).max(axis=(0, 1)) / scale).max() <= 1e-13
 
 
 def _apply_p1(hm, state_caller):
