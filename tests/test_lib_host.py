@@ -219,3 +219,21 @@ def test_step1_map_agrees_with_the_oracle_least_squares():
         # constant term: Wbar - c3 Mxx - c4 Mxy - c5 Myy
         a0 = s[0, 0, k] - c[2, i] * mom[0, i] - c[3, i] * mom[1, i] - c[4, i] * mom[2, i]
         assert np.isclose(a0, p[0], rtol=1e-12)
+
+
+def test_set_time_and_capture_refusals():
+    """hwe_set_time takes finite times only; a captured step sequence refuses
+    meshes whose boundary switch moves with time (host-side checks)."""
+    from paper_2607_10809_amd._lib import HweError
+    from paper_2607_10809_amd.hwe import Mesh
+    import workloads
+    wl = workloads.double_mach_workload(n=6)
+    hm = Mesh.from_workload(wl, device=-1)
+    hm.set_time(0.05)
+    with pytest.raises(HweError) as e:
+        hm.set_time(float("nan"))
+    assert e.value.status == -1
+    with pytest.raises(ValueError):
+        hm.capture_steps(None, None, 1e-3, 4)           # moving switch: launches would be frozen
+    with pytest.raises(ValueError):
+        hm.capture_steps(None, None, 1e-3, 3)           # odd step count
