@@ -72,6 +72,25 @@ def measured_traffic(kernel):
     return None
 
 
+def measured_valu_busy(kernel):
+    """Fraction of VALU issue slots busy for ``kernel`` from the committed counter
+    summary (SQ_INSTS_VALU x 4 cycles over the kernel's duration), or None when
+    the kernel sources have changed since the counters were taken."""
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"source digest: `([0-9a-f]+)`", text)
+    if not m or m.group(1) != source_digest():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip().strip("`") for c in line.split("|")]
+        if len(cells) > 8 and cells[1] == kernel and cells[8].endswith("%"):
+            return round(float(cells[8][:-1]) / 100.0, 2)
+    return None
+
+
 def copy_bandwidth(nbytes=1 << 30, reps=20):
     """Device-to-device copy rate (bytes read + written per second) of a 1 GiB buffer."""
     import torch
@@ -350,7 +369,8 @@ def main():
                                "GBps": round(kb[n] / (t * 1e-3) / 1e9, 1)}
                            for n, t in zip(names, leg["kernel_ms"])}
     # roofline of the dominant FP64 kernel: recon and update are bound by HBM,
-    # the edge kernel by FP64 VALU issue (57% busy against 31% of HBM)
+    # the edge kernel by FP64 VALU issue (two thirds of the issue slots busy
+    # against a third of HBM)
     dom = names[int(np.argmax(f64["kernel_ms"]))]
     t_dom = f64["kernel_ms"][names.index(dom)] * 1e-3
     gbps = kb64[dom] / t_dom / 1e9
@@ -364,9 +384,20 @@ def main():
                     "frac": round(gbps / HBM_PEAK_GBS, 4)}
     roofline.update({"traffic": measured_traffic(f"{dom}_kernel<2, double>"), "kernel": f"{dom}_kernel<2, double>",
                      "per_launch_bytes": int(kb64[dom]), "source_digest": source_digest()})
+    if dom == "edge":
+        roofline["valu_busy"] = measured_valu_busy("edge_kernel<2, double>")
     if copy_gbps:
         roofline["measured_copy_GBps"] = round(copy_gbps, 1)
         roofline["hbm_frac_of_copy"] = round(gbps / copy_gbps, 4)
+    # the HBM-bound reconstruction kernel, reported beside the dominant one
+    t_rec = f64["kernel_ms"][0] * 1e-3
+    rec_gbps = kb64["recon"] / t_rec / 1e9
+    roofline["hbm_kernel"] = {"kernel": "recon_kernel<2, double>", "bound": "hbm", "achieved": round(rec_gbps, 1),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(rec_gbps / HBM_PEAK_GBS, 4),
+                              "traffic": measured_traffic("recon_kernel<2, double>"),
+                              "per_launch_bytes": int(kb64["recon"])}
+    if copy_gbps:
+        roofline["hbm_kernel"]["frac_of_copy"] = round(rec_gbps / copy_gbps, 4)
     step_bytes = sum(kb64.values())
     out = {
         "metric": "cell-steps/s FP64 vs FP32 + adjoint/forward time ratio, Euler 204,800 tris",
