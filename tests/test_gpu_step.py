@@ -17,7 +17,8 @@ sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 from gpu_util import gpu_run, gpu_run_to, rel_l1, rel_max  # noqa: E402
 
 from oracle import OracleMesh  # noqa: E402
-from workloads import (GAMMA_GAS, advection_workload, burgers_workload, riemann_workload, split_square_mesh,  # noqa: E402
+from workloads import (GAMMA_GAS, advection_workload, burgers_workload, density_wave_workload, riemann_workload,  # noqa: E402
+                       split_square_mesh,
                        vortex_workload)
 
 pytestmark = pytest.mark.gpu
@@ -461,3 +462,22 @@ def test_graph_replays_equal_eager_steps(prec):
         assert torch.equal(a[0], ref[0]) and torch.equal(a[1], ref[1]), rep
         state = m.run(ref[0], ref[1], dt, 3)          # eager work between the replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_third_order_convergence_on_the_gpu(prec):
+    """The GPU path on the Euler density wave (Example 4.2's smooth flow) at
+    three mesh sizes: third-order L1 convergence of the density, as the
+    oracle's own pin shows (the mixed path's FP32 rounding stays well below
+    these error levels)."""
+    errs = []
+    for n in (8, 16, 32):
+        wl = density_wave_workload(n=n, T=0.25)
+        om = OracleMesh.from_workload(wl)
+        dt = om.max_dt(wl.state0, 0.3)
+        s = gpu_run_to(_mesh(wl, prec), wl.state0, wl.T, dt)
+        area = om.geometry()["area"]
+        errs.append(float(np.sum(np.abs(s[0, 0] - wl.exact_state(wl.T)[0, 0]) * area) / np.sum(area)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    _say(f"density wave on the GPU ({prec}): L1 {errs}, orders {orders}")
+    assert (orders > 2.6).all()
