@@ -244,6 +244,22 @@ hwe_status hwe_check_state(hwe_mesh m, const double* wbar, int32_t* flags_dev, v
  * R(x,y) - Wbar = a0 + a1 X + a2 Y + a3 X^2 + a4 XY + a5 Y^2. */
 hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, void* R_out, void* stream);
 
+/* Edge stage only (Sec. 2.1, eqs. (fx), (flux), (tay), (tayext), and the
+ * interface value of eq. (timeflux)) for kernel-level tests, from a
+ * reconstruction R in the layout of hwe_debug_recon and the cell averages
+ * wbar of the same state, with step size dt:
+ *  F_out : device double [E][m]: |e| times the time and Gauss-point average of
+ *          the local Lax-Friedrichs normal flux through edge e, oriented out of
+ *          its first cell (hwe_debug_host_array 8); the first cell's average
+ *          changes by -dt/|K| F_e, the second's by +dt/|K| F_e (eq. (flx));
+ *  G_out : device [E][m] of double (FP64) or float (MIXED): the Gauss-point
+ *          average of the two sides' offsets W - Wbar at t_n + dt, halved, so
+ *          that the interface value at the edge is (Wbar_1 + Wbar_2)/2 + G_e.
+ * Edges are in the library's order; hwe_debug_host_array 7 gives each cell's
+ * edges.  Outputs must not overlap the inputs or each other. */
+hwe_status hwe_debug_edge(hwe_mesh m, const void* R, const double* wbar, double dt, double* F_out, void* G_out,
+                          void* stream);
+
 /* Host copy of a precomputed per-cell array for host-logic tests (works for
  * host-only handles).  which: 0 = p1 map [55][N] (rows: c1..c5 of the
  * zero-mean basis X, Y, X^2-Mxx, XY-Mxy, Y^2-Myy; columns: dW1..dW3, V0..V3,
@@ -252,7 +268,10 @@ hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, voi
  * of each face [3][N] (hwe_bnd_kind as double; -1 = interior face), 6 = the
  * factored p1 map of the device tables [41][N] (rows 3j + c: the dW columns;
  * 15 + 5k + j: Z; 25 + 8k + v: Q on V0..V3, Y0..Y3; the map's V and Y columns
- * are Z^T Q).  out is host double with room for the stated size. */
+ * are Z^T Q), 7 = each cell's edges [3][N] (edge index << 1 | 1 when the cell
+ * is the edge's second cell), 8 = each edge's cells [2][E] (first, second; a
+ * negative second entry marks a boundary edge).  out is host double with room
+ * for the stated size. */
 hwe_status hwe_debug_host_array(hwe_mesh m, int32_t which, double* out);
 
 /* Per-kernel timing for measurement tools.  hwe_profile_begin arms HIP events

@@ -64,13 +64,15 @@ def load_library():
     L.hwe_max_dt.argtypes = [vp, vp, C.c_double, vp, vp]
     L.hwe_check_state.argtypes = [vp, vp, vp, vp]
     L.hwe_debug_recon.argtypes = [vp, vp, vp, vp, vp]
+    L.hwe_debug_edge.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp]
     L.hwe_debug_host_array.argtypes = [vp, i32, dp]
     L.hwe_profile_begin.argtypes = [vp, i32]
     L.hwe_profile_end.argtypes = [vp, dp, C.POINTER(i32)]
     L.hwe_last_error.restype = C.c_char_p
     for name in ("hwe_opts_default", "hwe_mesh_init", "hwe_mesh_destroy", "hwe_mesh_info", "hwe_mesh_cell_perm",
                  "hwe_step", "hwe_step_adjoint", "hwe_step_keep", "hwe_step_adjoint_kept", "hwe_set_time",
-                 "hwe_max_dt", "hwe_check_state", "hwe_debug_recon", "hwe_debug_host_array", "hwe_profile_begin",
+                 "hwe_max_dt", "hwe_check_state", "hwe_debug_recon", "hwe_debug_edge", "hwe_debug_host_array",
+                 "hwe_profile_begin",
                  "hwe_profile_end"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -87,5 +89,6 @@ def exported_symbols():
     """Names declared in include/hwe.h (for the export test)."""
     return ["hwe_opts_default", "hwe_mesh_init", "hwe_mesh_destroy", "hwe_mesh_info", "hwe_mesh_cell_perm",
             "hwe_step", "hwe_step_adjoint", "hwe_step_keep", "hwe_step_adjoint_kept", "hwe_set_time",
-            "hwe_max_dt", "hwe_check_state", "hwe_debug_recon", "hwe_debug_host_array", "hwe_profile_begin", "hwe_profile_end",
+            "hwe_max_dt", "hwe_check_state", "hwe_debug_recon", "hwe_debug_edge", "hwe_debug_host_array",
+            "hwe_profile_begin", "hwe_profile_end",
             "hwe_last_error"]

@@ -346,6 +346,27 @@ hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, voi
   return launch_recon(m, wbar, grad, R_out, stream);
 }
 
+hwe_status hwe_debug_edge(hwe_mesh m, const void* R, const double* wbar, double dt, double* F_out, void* G_out,
+                          void* stream) {
+  hwe_status s = need_device(m);
+  if (s != HWE_OK) return s;
+  if ((s = check_dt(dt)) != HWE_OK) return s;
+  if (!R || !wbar || !F_out || !G_out) {
+    set_error("null pointer");
+    return HWE_EINVAL;
+  }
+  const size_t N = size_t(m->h.N), E = size_t(m->h.E), mm = size_t(m->h.m);
+  const size_t rb = 6 * mm * N * real_size(m), wb = mm * N * sizeof(double);
+  const size_t fb = mm * E * sizeof(double), gb = mm * E * real_size(m);
+  if (overlaps(F_out, fb, G_out, gb) || overlaps(F_out, fb, R, rb) || overlaps(F_out, fb, wbar, wb) ||
+      overlaps(G_out, gb, R, rb) || overlaps(G_out, gb, wbar, wb)) {
+    set_error("output buffers overlap the inputs or each other");
+    return HWE_EINVAL;
+  }
+  if ((s = set_dev(m)) != HWE_OK) return s;
+  return launch_edge(m, R, wbar, dt, F_out, G_out, stream);
+}
+
 hwe_status hwe_profile_begin(hwe_mesh m, int32_t n_steps) {
   hwe_status s = need_device(m);
   if (s != HWE_OK) return s;
@@ -395,6 +416,12 @@ hwe_status hwe_debug_host_array(hwe_mesh m, int32_t which, double* out) {
       return HWE_OK;
     case 6:
       std::memcpy(out, h.p1f.data(), h.p1f.size() * sizeof(double));
+      return HWE_OK;
+    case 7:
+      for (size_t k = 0; k < h.cell_edge.size(); ++k) out[k] = double(h.cell_edge[k]);
+      return HWE_OK;
+    case 8:
+      for (size_t k = 0; k < h.ecell.size(); ++k) out[k] = double(h.ecell[k]);
       return HWE_OK;
     case 5:
       // boundary kind of each face, -1 on interior faces

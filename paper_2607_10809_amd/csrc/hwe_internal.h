@@ -120,6 +120,8 @@ void free_device(hwe_mesh_s* M);
 hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out,
                        void* grad_out, double dt, void* R_keep, void* stream);
 hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, void* R_out, void* stream);
+hwe_status launch_edge(hwe_mesh_s* M, const void* R, const double* wbar, double dt, double* F_out, void* G_out,
+                       void* stream);
 // R_n (may be null): the reconstruction of state n kept by a step; null
 // recomputes it into the handle's scratch.
 hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_n, const void* R_n, const double* lw,

@@ -448,6 +448,28 @@ hwe_status dev_alloc(void** dst, size_t bytes) {
 
 unsigned grid_for(int64_t items) { return unsigned((items + kBlock - 1) / kBlock); }
 
+// The edge stage: the kernel for the mesh's edge rule and the time rule.
+template <int EQ, class Real>
+void edge_impl(hwe_mesh_s* M, const Params& P, double dt, const double* wbar, const Real* R, const Real* egp,
+               double* F, Real* G, hipStream_t st) {
+  const DevMesh& d = M->d;
+  const int N = int(M->h.N), E = int(M->h.E), NB = int(M->h.NB);
+  if (M->opts.edge_rule == 3) {
+    if (P.time_rule == 1)
+      hipLaunchKernelGGL((edge3_kernel<EQ, Real, 1>), dim3(grid_for(8 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB,
+                         P, dt, wbar, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
+    else
+      hipLaunchKernelGGL((edge3_kernel<EQ, Real, 0>), dim3(grid_for(8 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB,
+                         P, dt, wbar, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
+  } else if (P.time_rule == 1) {
+    hipLaunchKernelGGL((edge_kernel<EQ, Real, 1>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB, P,
+                       dt, wbar, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
+  } else {
+    hipLaunchKernelGGL((edge_kernel<EQ, Real, 0>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB, P,
+                       dt, wbar, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
+  }
+}
+
 template <int EQ, class Real>
 hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, const Real* grad_in, double* wbar_out,
                      Real* grad_out, double dt, hipStream_t st, const Real* tbl, const Real* nl,
@@ -465,20 +487,7 @@ hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, cons
   hipLaunchKernelGGL((recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * Mc)), dim3(kBlock), 0, st, N, NB, P, wbar_in, grad_in,
                      d.nbr, d.bnd_n, tbl, d.area, d.gpc, R);
   if (ev) hipEventRecord(ev[1], st);
-  if (M->opts.edge_rule == 3) {
-    if (P.time_rule == 1)
-      hipLaunchKernelGGL((edge3_kernel<EQ, Real, 1>), dim3(grid_for(8 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB,
-                         P, dt, wbar_in, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
-    else
-      hipLaunchKernelGGL((edge3_kernel<EQ, Real, 0>), dim3(grid_for(8 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB,
-                         P, dt, wbar_in, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
-  } else if (P.time_rule == 1) {
-    hipLaunchKernelGGL((edge_kernel<EQ, Real, 1>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB, P,
-                       dt, wbar_in, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
-  } else {
-    hipLaunchKernelGGL((edge_kernel<EQ, Real, 0>), dim3(grid_for(4 * int64_t(E))), dim3(kBlock), 0, st, E, N, NB, P,
-                       dt, wbar_in, R, d.ecell, d.bnd_n, d.enl, egp, F, G);
-  }
+  edge_impl<EQ, Real>(M, P, dt, wbar_in, R, egp, F, G, st);
   if (ev) hipEventRecord(ev[2], st);
   hipLaunchKernelGGL((update_kernel<EQ, Real>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, E, NB, P, dt, wbar_in,
                      d.bnd_n, d.nbr, d.cell_edge, nl, d.inv_area, F, G, wbar_out, grad_out);
@@ -657,6 +666,34 @@ hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, voi
     case HWE_BURGERS: return recon_impl<EQ_BUR, float>(M, P, wbar, g, R, st, d.tblf);
     default: return recon_impl<EQ_EUL, float>(M, P, wbar, g, R, st, d.tblf);
   }
+}
+
+hwe_status launch_edge(hwe_mesh_s* M, const void* R, const double* wbar, double dt, double* F_out, void* G_out,
+                       void* stream) {
+  Params P = params_of(M->opts);
+  P.tb = M->time + 0.5 * dt;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevMesh& d = M->d;
+  if (M->opts.prec == HWE_FP64) {
+    auto r = static_cast<const double*>(R);
+    auto g = static_cast<double*>(G_out);
+    switch (M->opts.eq) {
+      case HWE_ADVECTION: edge_impl<EQ_ADV, double>(M, P, dt, wbar, r, d.egp, F_out, g, st); break;
+      case HWE_BURGERS: edge_impl<EQ_BUR, double>(M, P, dt, wbar, r, d.egp, F_out, g, st); break;
+      default: edge_impl<EQ_EUL, double>(M, P, dt, wbar, r, d.egp, F_out, g, st);
+    }
+  } else {
+    auto r = static_cast<const float*>(R);
+    auto g = static_cast<float*>(G_out);
+    switch (M->opts.eq) {
+      case HWE_ADVECTION: edge_impl<EQ_ADV, float>(M, P, dt, wbar, r, d.egpf, F_out, g, st); break;
+      case HWE_BURGERS: edge_impl<EQ_BUR, float>(M, P, dt, wbar, r, d.egpf, F_out, g, st); break;
+      default: edge_impl<EQ_EUL, float>(M, P, dt, wbar, r, d.egpf, F_out, g, st);
+    }
+  }
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return hip_fail(err, "kernel launch");
+  return HWE_OK;
 }
 
 hwe_status launch_max_dt(hwe_mesh_s* M, const double* wbar, double cfl, double* dt_dev, void* stream) {

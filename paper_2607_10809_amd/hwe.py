@@ -296,6 +296,17 @@ class Mesh:
         check(self._L.hwe_debug_recon(self._h, _ptr(wbar), _ptr(grad), _ptr(R), _stream(stream)))
         return R.permute(1, 2, 0)
 
+    def debug_edge(self, recon, wbar, dt, stream=None):
+        """The edge stage alone from a reconstruction (the (N, 6, m) record of
+        empty_recon / step(..., keep=)): (F, G), each (E, m) in the library's
+        edge order; F float64, G of the mesh's real type."""
+        self._check_recon(recon)
+        F = torch.empty((self.E, self.m), dtype=torch.float64, device=self.device)
+        G = torch.empty((self.E, self.m), dtype=self.gdtype, device=self.device)
+        check(self._L.hwe_debug_edge(self._h, _ptr(recon), _ptr(wbar), float(dt), _ptr(F), _ptr(G),
+                                     _stream(stream)))
+        return F, G
+
     def profile_begin(self, n_steps):
         check(self._L.hwe_profile_begin(self._h, int(n_steps)))
 
@@ -307,7 +318,8 @@ class Mesh:
         return [ms[0], ms[1], ms[2]], n.value
 
     def host_array(self, which):
-        sizes = {0: (55, self.N), 1: (2, self.N), 2: (self.N,), 3: (3, self.N), 4: (3, self.N), 5: (3, self.N), 6: (41, self.N)}
+        sizes = {0: (55, self.N), 1: (2, self.N), 2: (self.N,), 3: (3, self.N), 4: (3, self.N), 5: (3, self.N), 6: (41, self.N), 7: (3, self.N),
+                 8: (2, self.E)}
         out = np.empty(sizes[which])
         check(self._L.hwe_debug_host_array(self._h, int(which), out.ctypes.data_as(C.POINTER(C.c_double))))
         return out

@@ -505,3 +505,52 @@ def test_caller_order_does_not_change_the_result():
         err = rel_max(b, a[:, :, perm])
         _say(f"renumbered caller order ({prec}): rel max {err:.2e}")
         assert err <= tol
+
+
+@pytest.mark.parametrize("case,prec", [("vortex", "fp64"), ("vortex", "mixed"), ("double_mach", "fp64")])
+def test_debug_edge_reproduces_the_step(case, prec):
+    """hwe_debug_edge (the edge stage alone, from a kept reconstruction): the
+    update assembled on the host from its fluxes and interface values equals
+    the step's result (cell averages; derivative averages on the periodic
+    mesh, where no ghost term enters)."""
+    import torch
+    from workloads import double_mach_workload
+    wl = vortex_workload(n=24) if case == "vortex" else double_mach_workload(n=12)
+    m = _mesh(wl, prec)
+    om = OracleMesh.from_workload(wl)
+    geo = om.geometry()
+    dt = om.max_dt(wl.state0, wl.cfl)
+    w, g = m.to_device(wl.state0)
+    R = m.empty_recon()
+    m.set_time(0.0)
+    wo, go = m.step(w, g, dt, keep=R)
+    F, G = m.debug_edge(R, w, dt)
+    torch.cuda.synchronize()
+    F, G = F.cpu().numpy(), G.cpu().numpy().astype(np.float64)
+    W = w.cpu().numpy()
+    ce = m.host_array(7).astype(np.int64)             # [3][N] internal order
+    nbr = m.host_array(4).astype(np.int64)
+    perm = m.perm
+    area = geo["area"][perm]
+    nl = geo["normal"][perm] * geo["length"][perm][..., None]   # (N, 3, 2): outward normal x length
+    e, side = ce >> 1, ce & 1
+    sgn = np.where(side == 1, -1.0, 1.0)
+    fs = sum(sgn[f][None, :] * F[e[f]].T for f in range(3))
+    W_new = W - dt / area[None, :] * fs
+    err_w = float(np.abs(W_new - wo.cpu().numpy()).max() / np.abs(W_new).max())
+    msg = f"{case} {prec}: cell averages from debug_edge vs step {err_w:.1e}"
+    assert err_w <= (1e-14 if prec == "fp64" else 1e-6)
+    if case == "vortex":
+        vs = np.zeros_like(W)
+        ys = np.zeros_like(W)
+        for f in range(3):
+            Wn = W[:, nbr[f]]
+            gq = G[e[f]].T + 0.5 * (Wn - W)
+            vs += nl[:, f, 0][None, :] * gq
+            ys += nl[:, f, 1][None, :] * gq
+        got = go.cpu().numpy().astype(np.float64)
+        err_g = max(float(np.abs(vs / area - got[0]).max() / np.abs(got[0]).max()),
+                    float(np.abs(ys / area - got[1]).max() / np.abs(got[1]).max()))
+        msg += f", derivative averages {err_g:.1e}"
+        assert err_g <= (1e-12 if prec == "fp64" else 1e-5)
+    _say(msg)
