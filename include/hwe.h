@@ -206,7 +206,8 @@ hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n
  *  recon_out : device, caller-owned, [N][6][m] of double (FP64) or float
  *              (MIXED): per cell and component the coefficients a0..a5 of
  *              R - Wbar in the monomial basis about the cell centroid (the
- *              layout of hwe_debug_recon); must not overlap the state buffers.
+ *              layout of hwe_debug_recon); 16-byte aligned (it is read as
+ *              whole 16-byte records); must not overlap the state buffers.
  *
  * hwe_step_adjoint_kept: hwe_step_adjoint with recon_n = the buffer that
  * hwe_step_keep wrote for the same (wbar_n, grad_n) on this handle; the
@@ -256,7 +257,8 @@ hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, voi
  *          average of the two sides' offsets W - Wbar at t_n + dt, halved, so
  *          that the interface value at the edge is (Wbar_1 + Wbar_2)/2 + G_e.
  * Edges are in the library's order; hwe_debug_host_array 7 gives each cell's
- * edges.  Outputs must not overlap the inputs or each other. */
+ * edges.  R, F_out and G_out must be 16-byte aligned (whole records are moved
+ * with 16-byte accesses); outputs must not overlap the inputs or each other. */
 hwe_status hwe_debug_edge(hwe_mesh m, const void* R, const double* wbar, double dt, double* F_out, void* G_out,
                           void* stream);
 

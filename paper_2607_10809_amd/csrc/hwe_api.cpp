@@ -95,6 +95,10 @@ namespace {
 
 bool finite_value(double v) { return v == v && v < 1e300 && v > -1e300; }
 
+// Buffers read or written as whole records (a cell's reconstruction, an edge's
+// flux) are moved with 16-byte accesses.
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 // Region list, prescribed states and the moving switch.
 bool regions_ok(const hwe_opts& o) {
   if (o.n_regions < 0 || o.n_regions > HWE_MAX_REGIONS) return false;
@@ -285,8 +289,8 @@ hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, doub
 
 hwe_status hwe_step_keep(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,
                          double dt, void* recon_out, void* stream) {
-  if (!recon_out) {
-    set_error("null reconstruction buffer");
+  if (!recon_out || !aligned16(recon_out)) {
+    set_error("null or misaligned reconstruction buffer (16-byte alignment required)");
     return HWE_EINVAL;
   }
   hwe_status s = check_step(m, wbar_in, grad_in, wbar_out, grad_out, dt, recon_out);
@@ -304,8 +308,8 @@ hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n
 hwe_status hwe_step_adjoint_kept(hwe_mesh m, const double* wbar_n, const void* grad_n, const void* recon_n,
                                  const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n,
                                  void* lam_grad_n, double dt, void* stream) {
-  if (!recon_n) {
-    set_error("null reconstruction buffer");
+  if (!recon_n || !aligned16(recon_n)) {
+    set_error("null or misaligned reconstruction buffer (16-byte alignment required)");
     return HWE_EINVAL;
   }
   hwe_status s = check_adjoint(m, wbar_n, grad_n, recon_n, lam_wbar_np1, lam_grad_np1, lam_wbar_n, lam_grad_n, dt);
@@ -348,6 +352,10 @@ hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, voi
 
 hwe_status hwe_debug_edge(hwe_mesh m, const void* R, const double* wbar, double dt, double* F_out, void* G_out,
                           void* stream) {
+  if ((R && !aligned16(R)) || (F_out && !aligned16(F_out)) || (G_out && !aligned16(G_out))) {
+    set_error("misaligned record buffer (16-byte alignment required)");
+    return HWE_EINVAL;
+  }
   hwe_status s = need_device(m);
   if (s != HWE_OK) return s;
   if ((s = check_dt(dt)) != HWE_OK) return s;

@@ -13,11 +13,13 @@
 // Step 1 (quadratic p1 on {K0, K1, K2, K3}): the three neighbour averages are
 // equality constraints, the six union derivative integrals
 //   int_{Kl + K0} p_x = |Kl| Vbar_l + |K0| Vbar_0,  int_{Kl + K0} p_y = |Kl| Ybar_l + |K0| Ybar_0
-// are matched in the least-squares sense.  The solution is linear in the data,
-// so each cell stores the 5 x 11 matrix mapping
+// are matched in the least-squares sense.  The solution is linear in the data:
+// a 5 x 11 matrix maps
 //   (dW1, dW2, dW3, V0, V1, V2, V3, Y0, Y1, Y2, Y3),  dWl = Wbar_l - Wbar_0,
 // to (c1..c5).  It is computed by the null-space method: Householder QR of the
-// constraint matrix, then a 2 x 2 least-squares problem on its null space.
+// constraint matrix, then a 2 x 2 least-squares problem on its null space.  The
+// device tables keep it factored: the dW columns (5 x 3), the null-space basis
+// Z (2 x 5) and the reduced solution Q (2 x 8) with the V, Y columns = Z^T Q.
 //
 // Step 2 (linear p_{l+1} on {K0, Kl}): with p = Wbar_0 + b X + c Y the K0 average
 // holds exactly, and the rows  [dx dy] (b, c) = dWl,  b = Vbar_l,  c = Ybar_l

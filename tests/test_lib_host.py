@@ -86,6 +86,12 @@ def test_error_statuses():
     st = L.hwe_step_adjoint_kept(m.handle, C.c_void_p(16), C.c_void_p(32), C.c_void_p(), C.c_void_p(48),
                                  C.c_void_p(64), C.c_void_p(80), C.c_void_p(96), C.c_double(0.1), C.c_void_p())
     assert st == -1
+    st = L.hwe_step_keep(m.handle, C.c_void_p(16), C.c_void_p(32), C.c_void_p(48), C.c_void_p(64),
+                         C.c_double(0.1), C.c_void_p(4104), C.c_void_p())
+    assert st == -1                             # reconstruction buffer not 16-byte aligned
+    st = L.hwe_debug_edge(m.handle, C.c_void_p(4096), C.c_void_p(16), C.c_double(0.1), C.c_void_p(8200),
+                          C.c_void_p(9000), C.c_void_p())
+    assert st == -1                             # flux buffer not 16-byte aligned
     assert m.N == 32 and m.m == 1
 
 
