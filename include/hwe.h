@@ -152,10 +152,11 @@ hwe_status hwe_opts_default(hwe_opts* o);
  *  tris  : host int32 [n_tris][3] vertex indices, any orientation
  *  Periodic meshes are tori: triangles may reference nodes across the seams
  *  and are unwrapped by minimal image about their first vertex.
- * Precomputes geometry, the 2-point Gauss-Legendre points of every edge, the
- * face-neighbour stencils {K0, K1, K2, K3} of Step 1 (Fig. 1; ghost mirror cells
- * on transmissive boundaries) and, per cell, the linear maps of the
- * constrained least-squares problems of Steps 1 and 2.  Copies the inputs;
+ * Precomputes geometry, the Gauss-Legendre points of every edge (2, or 3 with
+ * opts.edge_rule = 3), the face-neighbour stencils {K0, K1, K2, K3} of Step 1
+ * (Fig. 1; ghost mirror cells on non-periodic boundaries), the boundary kind
+ * of every boundary face (opts.walls, opts.regions) and, per cell, the linear
+ * maps of the constrained least-squares problems of Steps 1 and 2.  Copies the inputs;
  * the caller keeps ownership.  Returns HWE_EMESH or HWE_ESINGULAR for bad
  * meshes, HWE_EHIP / HWE_ENOMEM for device failures.  *out is valid only on
  * HWE_OK. */
@@ -179,7 +180,9 @@ hwe_status hwe_mesh_cell_perm(hwe_mesh m, int64_t* perm_host);
  *  wbar_in, grad_in   : device, state at t_n (layouts above); read only
  *  wbar_out, grad_out : device, state at t_n + dt; must not overlap the inputs
  * Time rule: 3-point Gauss-Lobatto (0, dt/2, dt; weights 1/6, 4/6, 1/6) whose
- * last node also gives the interface value of eq. (timeflux). */
+ * last node also gives the interface value of eq. (timeflux), or the option
+ * of opts.time_rule; edge rule as opts.edge_rule.  Boundary states that move
+ * with time are evaluated at (time set by hwe_set_time) + dt/2. */
 hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out,
                     void* grad_out, double dt, void* stream);
 
