@@ -137,8 +137,8 @@ typedef struct {
   int32_t edge_rule;      /* Gauss-Legendre points per edge in the flux and
                              interface-value integrals of eqs. (fx)/(flux) and
                              (derave2d2): 2 (default; exact for cubics along the
-                             edge) or 3 (exact for quintics).  3 is not
-                             combined with the positivity limiter (HWE_EINVAL) */
+                             edge) or 3 (exact for quintics); the positivity
+                             limiter then checks the 9 points */
   int32_t pad_rule;
 } hwe_opts;
 

@@ -132,7 +132,7 @@ hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tr
       o.positivity < 0 || o.positivity > 1 || (o.positivity && o.eq != HWE_EULER) || o.time_rule < 0 ||
       o.time_rule > 1 || !(o.deriv_weight > 0.0) || !(o.deriv_weight < 1e300) || o.walls < 0 || o.walls > 15 ||
       (o.walls && (o.eq != HWE_EULER || o.bc != HWE_BC_TRANSMISSIVE)) || !regions_ok(o) ||
-      (o.edge_rule != 2 && o.edge_rule != 3) || (o.edge_rule == 3 && o.positivity)) {
+      (o.edge_rule != 2 && o.edge_rule != 3)) {
     set_error("invalid option value");
     return HWE_EINVAL;
   }

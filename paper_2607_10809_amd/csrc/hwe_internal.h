@@ -43,8 +43,9 @@ struct HostMesh {
   std::vector<int32_t> cell_edge;  // [3][N] (edge << 1) | (cell is the edge's second cell)
   std::vector<double> nl;          // [6][N] outward normal times length: x of faces 0..2, then y
   std::vector<double> inv_area;    // [N]
-  std::vector<double> gpc;         // [12][N] offsets (X, Y) from the centroid of the
-                                   // 2 Gauss points of faces 0..2: row 4f+2g (X), 4f+2g+1 (Y)
+  std::vector<double> gpc;         // [6G][N] offsets (X, Y) from the centroid of the G Gauss
+                                   // points (2, or 3 with the 3-point rule) of faces 0..2:
+                                   // row 2(Gf+g) (X), 2(Gf+g)+1 (Y) (limiter only)
   std::vector<int32_t> ecell;      // [2][E] first cell (lower caller index), then the second cell, or
                                    // on a boundary edge -1 (transmissive), -2 (wall) or -3 - b
                                    // (prescribed state; b = the boundary face)

@@ -42,7 +42,8 @@ constexpr int kBlock = 256;
 // For Euler a block covers exactly one table tile (64 cells x 4 components):
 // the tile's tables are one contiguous block, staged into LDS with 16-byte
 // loads that are all in flight together, while the stencil gathers proceed.
-template <int EQ, class Real>
+// NPT: the limiter's points per cell (6, or 9 with the 3-point edge rule).
+template <int EQ, class Real, int NPT>
 __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, const double* __restrict__ wbar,
                                                         const Real* __restrict__ grad,
                                                         const int32_t* __restrict__ nbr,
@@ -88,14 +89,14 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
         for (int j = 0; j < 6; ++j) all[c][j] = __shfl(a[j], lane0 + c);
         Wb[c] = __shfl(w0, lane0 + c);
       }
-      double px[6], py[6];
+      double px[NPT], py[NPT];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
+      for (int k = 0; k < NPT; ++k) {
         px[k] = gpc[(2 * k) * size_t(N) + ic];
         py[k] = gpc[(2 * k + 1) * size_t(N) + ic];
       }
       double th[4];
-      positivity_theta<Real>(P.gam, Wb, all, px, py, th);
+      positivity_theta<Real, NPT>(P.gam, Wb, all, px, py, th);
       const Real tq = Real(th[q]);
 #pragma unroll
       for (int j = 0; j < 6; ++j) a[j] *= tq;
@@ -448,6 +449,21 @@ hwe_status dev_alloc(void** dst, size_t bytes) {
 
 unsigned grid_for(int64_t items) { return unsigned((items + kBlock - 1) / kBlock); }
 
+// The reconstruction launch: the limiter checks the edge rule's points.
+template <int EQ, class Real>
+void recon_launch(hwe_mesh_s* M, const Params& P, const double* wbar, const Real* grad, const Real* tbl, Real* R,
+                  hipStream_t st) {
+  const DevMesh& d = M->d;
+  const int N = int(M->h.N), NB = int(M->h.NB);
+  const dim3 grid(grid_for(int64_t(N) * NComp<EQ>::m));
+  if (M->opts.edge_rule == 3 && P.positivity)
+    hipLaunchKernelGGL((recon_kernel<EQ, Real, 9>), grid, dim3(kBlock), 0, st, N, NB, P, wbar, grad, d.nbr, d.bnd_n,
+                       tbl, d.area, d.gpc, R);
+  else
+    hipLaunchKernelGGL((recon_kernel<EQ, Real, 6>), grid, dim3(kBlock), 0, st, N, NB, P, wbar, grad, d.nbr, d.bnd_n,
+                       tbl, d.area, d.gpc, R);
+}
+
 // The edge stage: the kernel for the mesh's edge rule and the time rule.
 template <int EQ, class Real>
 void edge_impl(hwe_mesh_s* M, const Params& P, double dt, const double* wbar, const Real* R, const Real* egp,
@@ -484,8 +500,7 @@ hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, cons
   hipEvent_t* ev = nullptr;
   if (d.prof_n < d.prof_cap) ev = reinterpret_cast<hipEvent_t*>(&M->d.prof_ev[4 * size_t(d.prof_n)]);
   if (ev) hipEventRecord(ev[0], st);
-  hipLaunchKernelGGL((recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * Mc)), dim3(kBlock), 0, st, N, NB, P, wbar_in, grad_in,
-                     d.nbr, d.bnd_n, tbl, d.area, d.gpc, R);
+  recon_launch<EQ, Real>(M, P, wbar_in, grad_in, tbl, R, st);
   if (ev) hipEventRecord(ev[1], st);
   edge_impl<EQ, Real>(M, P, dt, wbar_in, R, egp, F, G, st);
   if (ev) hipEventRecord(ev[2], st);
@@ -507,8 +522,7 @@ hwe_status recon_impl(hwe_mesh_s* M, const Params& P, const double* wbar, const 
   const DevMesh& d = M->d;
   const int N = int(h.N), NB = int(h.NB);
   constexpr int Mc = NComp<EQ>::m;
-  hipLaunchKernelGGL((recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * Mc)), dim3(kBlock), 0, st, N, NB, P, wbar, grad, d.nbr,
-                     d.bnd_n, tbl, d.area, d.gpc, R);
+  recon_launch<EQ, Real>(M, P, wbar, grad, tbl, R, st);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return hip_fail(err, "kernel launch");
   return HWE_OK;

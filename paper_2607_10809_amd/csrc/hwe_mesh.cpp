@@ -489,7 +489,8 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
   h.cell_edge.assign(3 * N, 0);
   h.nl.assign(6 * N, 0);
   h.inv_area.assign(N, 0);
-  h.gpc.assign(12 * N, 0);
+  const int gpf = o.edge_rule == 3 ? 3 : 2;  // limiter points per face
+  h.gpc.assign(size_t(6 * gpf) * N, 0);
   double rmin = 1e300;
   int64_t bcount = 0;
   for (int64_t i = 0; i < N; ++i) {
@@ -515,10 +516,10 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
       double nx = ey / len, ny = -ex / len;
       h.nl[f * N + i] = nx * len;
       h.nl[(3 + f) * N + i] = ny * len;
-      for (int g = 0; g < 2; ++g) {
-        const double sg = g == 0 ? 0.5 - std::sqrt(3.0) / 6.0 : 0.5 + std::sqrt(3.0) / 6.0;
-        h.gpc[(4 * f + 2 * g) * N + i] = t.x[f] + sg * ex - g0.cx;
-        h.gpc[(4 * f + 2 * g + 1) * N + i] = t.y[f] + sg * ey - g0.cy;
+      for (int g = 0; g < gpf; ++g) {
+        const double sg = gpf == 3 ? gs3[g] : (g == 0 ? 0.5 - std::sqrt(3.0) / 6.0 : 0.5 + std::sqrt(3.0) / 6.0);
+        h.gpc[(2 * (gpf * f + g)) * N + i] = t.x[f] + sg * ex - g0.cx;
+        h.gpc[(2 * (gpf * f + g) + 1) * N + i] = t.y[f] + sg * ey - g0.cy;
       }
       h.cell_edge[f * N + i] = face_edge[3 * k + f];
       int64_t s = mate[3 * k + f];

@@ -274,23 +274,24 @@ __host__ __device__ __forceinline__ void store_coeffs(int i, int q, int N, const
 
 // Positivity-preserving scaling of the Euler reconstruction of one cell (the
 // scale limiter of Zhang and Shu cited in Sec. 3), in FP64.  a[q][0..5]: the
-// coefficients of R - Wbar per component, px/py: the six edge Gauss points of
-// the cell relative to its centroid.  With eps = min(1e-13, rho_bar, p_bar):
+// coefficients of R - Wbar per component, px/py: the NP edge Gauss points of
+// the cell (3 faces x 2, or x 3 with the 3-point edge rule) relative to its
+// centroid.  With eps = min(1e-13, rho_bar, p_bar):
 // theta_rho scales the density part so that rho >= eps at the points; then t
 // is the smallest root in [0, 1] of p(Wbar + t (W - Wbar)) = eps over the
 // points where p < eps, solved through
 //   g(t) = 2 rho(t) (E(t) - eps/(gamma-1)) - |m(t)|^2 = A t^2 + B t + C.
 // Results: theta[0] = theta_rho t, theta[1..3] = t (1 where inactive).
-template <class Real>
+template <class Real, int NP>
 __host__ __device__ __forceinline__ void positivity_theta(double gam, const double (&Wb)[4], const Real (&a)[4][6],
-                                                         const double (&px)[6], const double (&py)[6],
+                                                         const double (&px)[NP], const double (&py)[NP],
                                                          double (&theta)[4]) {
   const double gm1 = gam - 1.0;
   const double pbar = gm1 * (Wb[3] - 0.5 * (Wb[1] * Wb[1] + Wb[2] * Wb[2]) / Wb[0]);
   const double eps = fmin(1e-13, fmin(Wb[0], pbar));
-  double d[6][4];
+  double d[NP][4];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < NP; ++k) {
     const double X = px[k], Y = py[k];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -299,13 +300,13 @@ __host__ __device__ __forceinline__ void positivity_theta(double gam, const doub
   }
   double rmin = 1e300;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) rmin = fmin(rmin, Wb[0] + d[k][0]);
+  for (int k = 0; k < NP; ++k) rmin = fmin(rmin, Wb[0] + d[k][0]);
   const double th_rho = rmin < eps ? (Wb[0] - eps) / (Wb[0] - rmin) : 1.0;
   double t = 1.0;
   const double Ep = Wb[3] - eps / gm1;
   const double C = 2.0 * Wb[0] * Ep - (Wb[1] * Wb[1] + Wb[2] * Wb[2]);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < NP; ++k) {
     const double dr = th_rho * d[k][0], d1 = d[k][1], d2 = d[k][2], dE = d[k][3];
     const double r = Wb[0] + dr, m1 = Wb[1] + d1, m2 = Wb[2] + d2, En = Wb[3] + dE;
     const double p = gm1 * (En - 0.5 * (m1 * m1 + m2 * m2) / r);

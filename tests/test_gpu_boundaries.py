@@ -50,6 +50,8 @@ CASES = {
     "moving_shock": (lambda: moving_shock_workload(nx=60), {}, 40, 150),
     "double_mach_edge3": (lambda: double_mach_workload(n=12), {"edge_rule": 3}, 30, 120),
     "shu_osher_edge3": (lambda: shu_osher_workload(nx=120), {"edge_rule": 3}, 40, 200),
+    # the limiter with the 3-point edge rule checks the nine edge points
+    "blast_wave_edge3": (lambda: blast_wave_workload(nx=160), {"positivity": 1, "edge_rule": 3}, 30, 150),
 }
 
 

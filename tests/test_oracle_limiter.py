@@ -1,0 +1,86 @@
+"""Oracle pins for the scaling (positivity) limiter on the Euler reconstruction,
+with the 2- and 3-point edge rules.  The limiter scales R - Wbar about the cell
+average, first the density, then the whole state, by the largest factors in
+[0, 1] that keep density and pressure >= eps = min(1e-13, rho_bar, p_bar) at
+the cell's edge Gauss points; its definition fixes what to check:
+
+* after limiting, density and pressure are >= eps (to rounding) at every edge
+  point of the rule in use, in every cell;
+* a cell whose unlimited reconstruction is admissible at those points keeps
+  theta = 1 (the limiter is inactive);
+* a cell scaled for its pressure touches the bound: its smallest pressure over
+  the points is eps (the scaling is the largest admissible one);
+* the scaling is about the average, so the cell averages are untouched.
+"""
+import numpy as np
+import pytest
+
+from oracle import OracleMesh
+from workloads import riemann_workload
+
+pytestmark = pytest.mark.usefixtures("oracle_lib")
+
+GAMMA = 1.4
+RULES = {2: [0.5 - np.sqrt(3.0) / 6.0, 0.5 + np.sqrt(3.0) / 6.0],
+         3: [0.5 - np.sqrt(15.0) / 10.0, 0.5, 0.5 + np.sqrt(15.0) / 10.0]}
+
+
+def _near_vacuum_state():
+    """The four-quadrant data with its low-density quadrant thinned a thousandfold
+    and seeded random derivative averages of the size of the averages over a
+    cell: many reconstructions undershoot below zero at their edge points."""
+    wl = riemann_workload(n=24)
+    s = wl.state0.copy()
+    low = s[0, 0] < 0.2
+    s[:, :, low] *= 1e-3
+    rng = np.random.default_rng(41)
+    h = 1.0 / 24
+    s[1:] = rng.normal(size=s[1:].shape) * np.abs(s[0])[None] / h
+    return wl, s
+
+
+def _edge_points(V, rule):
+    pts = []
+    for f in range(3):
+        a, b = V[f], V[(f + 1) % 3]
+        for t in RULES[rule]:
+            pts.append(a + t * (b - a))
+    return np.array(pts)
+
+
+def _pressure(W):
+    return (GAMMA - 1.0) * (W[..., 3] - 0.5 * (W[..., 1] ** 2 + W[..., 2] ** 2) / W[..., 0])
+
+
+@pytest.mark.parametrize("rule", [2, 3])
+def test_limiter_bounds_activity_and_touching(rule):
+    wl, s = _near_vacuum_state()
+    lim = OracleMesh.from_workload(wl, positivity=1, edge_rule=rule)
+    raw = OracleMesh.from_workload(wl, edge_rule=rule)
+    V = lim.cell_vertices()
+    active = touching = 0
+    for k in range(lim.N):
+        pts = _edge_points(V[k], rule)
+        Wl = lim.eval_recon(s, k, pts)[:, :, 0]          # (points, 4) limited values
+        Wr = raw.eval_recon(s, k, pts)[:, :, 0]
+        th = lim.recon_theta(s, k)
+        Wb = s[0, :, k]
+        eps = min(1e-13, Wb[0], _pressure(Wb[None, :])[0])
+        scale = max(Wb[0], Wb[3])
+        assert Wl[:, 0].min() >= eps - 1e-12 * scale, k
+        assert _pressure(Wl).min() >= eps - 1e-12 * scale, k
+        if Wr[:, 0].min() >= eps and _pressure(Wr).min() >= eps:
+            assert np.all(th == 1.0), k
+        else:
+            active += 1
+            if th[1] < 1.0:                               # scaled for the pressure
+                touching += 1
+                assert abs(_pressure(Wl).min() - eps) <= 1e-9 * _pressure(Wb[None, :])[0], k
+    print(f"{rule}-point rule: {active} limited cells, {touching} scaled for the pressure", flush=True)
+    assert active > 10 and touching > 0
+    # the scaling is about the average: the limited quadratic still has the
+    # cell average W-bar (the edge-midpoint rule integrates quadratics exactly)
+    for k in range(lim.N):
+        mids = np.array([0.5 * (V[k, f] + V[k, (f + 1) % 3]) for f in range(3)])
+        avg = lim.eval_recon(s, k, mids)[:, :, 0].mean(axis=0)
+        assert np.abs(avg - s[0, :, k]).max() <= 1e-12 * np.abs(s[0, :, k]).max(), k
