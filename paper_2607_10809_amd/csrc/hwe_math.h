@@ -99,6 +99,17 @@ __host__ __device__ __forceinline__ double prescribed_component(const Params& P,
   return q == 0 ? W[0] : (q == 1 ? W[1] : (q == 2 ? W[2] : W[3]));
 }
 
+// 1/x for the FP32 bulk of the mixed path: the hardware reciprocal (within an
+// ulp of the quotient); FP64 keeps the correctly rounded division.
+__host__ __device__ __forceinline__ float recip(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+__host__ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <class T> struct SJ {  // spatial jet
   T c, x, y, xx, xy, yy;
 };
@@ -118,7 +129,7 @@ template <class T> __host__ __device__ __forceinline__ SJ<T> sj_mul(const SJ<T>&
 }
 template <class T> __host__ __device__ __forceinline__ SJ<T> sj_recip(const SJ<T>& a) {
   SJ<T> r;
-  T r1 = T(1) / a.c, r2 = r1 * r1, r3 = r2 * r1;
+  T r1 = recip(a.c), r2 = r1 * r1, r3 = r2 * r1;
   r.c = r1;
   r.x = -a.x * r2;
   r.y = -a.y * r2;
@@ -279,7 +290,7 @@ __host__ __device__ __forceinline__ void normal_flux_delta(const Params& P, cons
   } else {
     const T rho1 = b.w[0] + d[0];
     const T mx1 = b.w[1] + d[1], my1 = b.w[2] + d[2];
-    const T ir = T(1) / rho1;
+    const T ir = recip(rho1);
     const T du = (d[1] - b.u * d[0]) * ir;
     const T dv = (d[2] - b.v * d[0]) * ir;
     const T dke = T(0.5) * (d[1] * b.u + mx1 * du + d[2] * b.v + my1 * dv);
