@@ -2,19 +2,21 @@
 //
 //   hwe_step_adjoint(state_n, lam_{n+1}) = J(state_n)^T lam_{n+1}
 //
-// Three launches on the caller's stream, none with atomics:
+// Four launches on the caller's stream, none with atomics:
 //   1. the forward reconstruction kernel (R of every cell at state_n), skipped
 //      when the caller hands in the R that a step kept for this state;
-//   2. adj_cell_kernel, four work-items per cell.  Work-items 0-2 take the
-//      cell's faces: from the cell's and the neighbour's lam_{n+1} they form the
+//   2. adj_face_kernel, three work-items per cell (21 cells per wave), one per
+//      face: from the cell's and the neighbour's lam_{n+1} it forms the
 //      adjoints of the edge flux F_e and of the interface-value integral G_e,
-//      then reverse the cell's own side of the edge (Lax-Wendroff, Taylor
-//      extrapolation, offset-form normal flux at both Gauss points) and the
-//      flux base terms.  The four work-items sum their results with cross-lane
-//      shuffles; work-item q then reverses the reconstruction of component q
-//      (Steps 1-6, including the nonlinear-weight derivatives) into four
-//      stencil "slots" (the cell itself and its three neighbours).
-//   3. adj_gather_kernel, one work-item per (cell, component): its own slot, the slots its
+//      then reverses the cell's own side of the edge (Lax-Wendroff, Taylor
+//      extrapolation, offset-form normal flux at the Gauss points) and the
+//      flux base terms; the three sum their results with cross-lane shuffles
+//      and the first writes the cell's coefficient adjoints;
+//   3. adj_recon_kernel, one work-item per (cell, component q): the reverse of
+//      the reconstruction of component q (Steps 1-6, including the
+//      nonlinear-weight derivatives) into four stencil "slots" (the cell
+//      itself and its three neighbours);
+//   4. adj_gather_kernel, one work-item per (cell, component): its own slot, the slots its
 //      neighbours wrote for it, the Green-Gauss terms of the derivative
 //      averages and the derivative of the flux viscosity alpha (only on the
 //      cell whose spectral radius the max selected).
@@ -31,7 +33,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-template <class T> __device__ __forceinline__ T xshfl(T v, int mask) { return __shfl_xor(v, mask); }
 
 // Stencil-slot adjoints, cell-major: cell i's record holds 4 slots (itself,
 // then its neighbours across faces 0-2) x 3 fields (Wbar, V, Y) x M components,
@@ -42,19 +43,21 @@ template <int M> __device__ __forceinline__ size_t slot_index(int i, int sl, int
 
 // GP: Gauss points per edge (2, or 3 for the 3-point rule; egp holds 2 GP rows
 // per side).
+constexpr int kFaceCells = 21;  // cells per wave in adj_face_kernel (63 of 64 lanes)
+
 template <int EQ, class Real, int TR, int GP>
-__global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_cell_kernel(
-    int N, int E, int NB, Params P, double dt, const double* __restrict__ wbar, const Real* __restrict__ grad,
-    const double* __restrict__ lw, const Real* __restrict__ lg, const Real* __restrict__ R,
-    const int32_t* __restrict__ nbr, const int32_t* __restrict__ cell_edge,
-    const double* __restrict__ enl, const Real* __restrict__ egp, const double* __restrict__ inv_area,
-    const Real* __restrict__ nl, const double* __restrict__ bnd_n, const Real* __restrict__ tbl,
-    const double* __restrict__ area,
-    double* __restrict__ slots, double* __restrict__ sface) {
+__global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_face_kernel(
+    int N, int E, Params P, double dt, const double* __restrict__ wbar, const double* __restrict__ lw,
+    const Real* __restrict__ lg, const Real* __restrict__ R, const int32_t* __restrict__ nbr,
+    const int32_t* __restrict__ cell_edge, const double* __restrict__ enl, const Real* __restrict__ egp,
+    const double* __restrict__ inv_area, const Real* __restrict__ nl, Real* __restrict__ lacell,
+    double* __restrict__ lwcell, double* __restrict__ sface) {
   constexpr int M = NComp<EQ>::m;
   const int gid = xcd_block_id() * kBlock + threadIdx.x;
-  const int i = gid >> 2, lane = gid & 3;
-  const bool valid = i < N;
+  const int wv = gid >> 6, wl = gid & 63;
+  const int c = wl / 3, lane = wl - 3 * c;                 // lane = the face
+  const int i = wv * kFaceCells + c;
+  const bool valid = wl < 3 * kFaceCells && i < N;
   const int ic = valid ? i : N - 1;
   const size_t sN = size_t(N), sE = size_t(E);
   Real la[6][M];
@@ -65,7 +68,7 @@ __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_cell_ke
 #pragma unroll
     for (int j = 0; j < 6; ++j) la[j][q] = Real(0);
   }
-  if (lane < 3) {
+  {
     const int f = lane;
     // the face's edge and neighbour (nbr < 0: boundary face, no neighbour); the
     // neighbour's loads read the cell itself there and are not used
@@ -143,36 +146,48 @@ __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_cell_ke
     }
     if (valid) sface[f * sN + ic] = s;
   }
-  // sum over the cell's lanes
+  // sum over the cell's three lanes into its first
+  const int s1 = wl + 1 < 64 ? wl + 1 : wl, s2 = wl + 2 < 64 ? wl + 2 : wl;
 #pragma unroll
   for (int q = 0; q < M; ++q) {
-    lWf[q] += xshfl(lWf[q], 1);
-    lWf[q] += xshfl(lWf[q], 2);
+    const double a1 = __shfl(lWf[q], s1), a2 = __shfl(lWf[q], s2);
+    lWf[q] = (lWf[q] + a1) + a2;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      la[j][q] += xshfl(la[j][q], 1);
-      la[j][q] += xshfl(la[j][q], 2);
+      const Real b1 = __shfl(la[j][q], s1), b2 = __shfl(la[j][q], s2);
+      la[j][q] = (la[j][q] + b1) + b2;
     }
   }
-  if (lane < M && valid) {
-    const int q = lane;
-    Real laq[6];
+  if (valid && lane == 0) {
+    store_record<6 * M>(lacell + size_t(i) * (6 * M), &la[0][0]);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) laq[j] = la[j][0];
-    if constexpr (M == 4) {
-#pragma unroll
-      for (int j = 0; j < 6; ++j) laq[j] = q == 0 ? la[j][0] : (q == 1 ? la[j][1] : (q == 2 ? la[j][2] : la[j][3]));
-    }
-    double lwq = lWf[0];
-    if constexpr (M == 4) lwq = q == 0 ? lWf[0] : (q == 1 ? lWf[1] : (q == 2 ? lWf[2] : lWf[3]));
-    double slot[4][3];
-    recon_rev<EQ, Real>(i, q, N, NB, P, wbar, grad, nbr, bnd_n, tbl + tbl_col(i), area, laq, slot);
-    slot[0][0] += lwq;
-#pragma unroll
-    for (int sl = 0; sl < 4; ++sl)
-#pragma unroll
-      for (int fl = 0; fl < 3; ++fl) slots[slot_index<M>(i, sl, fl, q)] = slot[sl][fl];
+    for (int q = 0; q < M; ++q) lwcell[size_t(i) * M + q] = lWf[q];
   }
+}
+
+// One work-item per (cell, component q): the reverse of the reconstruction of
+// component q (Steps 1-6, with the nonlinear-weight derivatives) from the
+// coefficient adjoints the face kernel summed, into the cell's stencil slots.
+template <int EQ, class Real>
+__global__ __launch_bounds__(kBlock) void adj_recon_kernel(
+    int N, int NB, Params P, const double* __restrict__ wbar, const Real* __restrict__ grad,
+    const int32_t* __restrict__ nbr, const double* __restrict__ bnd_n, const Real* __restrict__ tbl,
+    const double* __restrict__ area, const Real* __restrict__ lacell, const double* __restrict__ lwcell,
+    double* __restrict__ slots) {
+  constexpr int M = NComp<EQ>::m;
+  const int gid = xcd_block_id() * kBlock + threadIdx.x;
+  const int i = gid / M, q = gid - (gid / M) * M;
+  if (i >= N) return;
+  Real laq[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) laq[j] = lacell[(size_t(i) * 6 + j) * M + q];
+  double slot[4][3];
+  recon_rev<EQ, Real>(i, q, N, NB, P, wbar, grad, nbr, bnd_n, tbl + tbl_col(i), area, laq, slot);
+  slot[0][0] += lwcell[size_t(i) * M + q];
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+    for (int fl = 0; fl < 3; ++fl) slots[slot_index<M>(i, sl, fl, q)] = slot[sl][fl];
 }
 
 // One work-item per (cell, component q).  Every load is issued before the
@@ -277,10 +292,12 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
   const HostMesh& h = M->h;
   const DevMesh& d = M->d;
   const int N = int(h.N), E = int(h.E), NB = int(h.NB);
-  const dim3 grid(grid_for(4 * int64_t(N)));
-#define HWE_ADJ_CELL(TRV, GPV)                                                                                     \
-  hipLaunchKernelGGL((adj_cell_kernel<EQ, Real, TRV, GPV>), grid, dim3(kBlock), 0, st, N, E, NB, P, dt, wbar, grad, \
-                     lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, tbl, d.area, d.slots, d.sface)
+  const int64_t waves = (int64_t(N) + kFaceCells - 1) / kFaceCells;
+  const dim3 grid(unsigned((waves * 64 + kBlock - 1) / kBlock));
+  Real* lacell = static_cast<Real*>(d.lacell);
+#define HWE_ADJ_CELL(TRV, GPV)                                                                                      \
+  hipLaunchKernelGGL((adj_face_kernel<EQ, Real, TRV, GPV>), grid, dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg, R, \
+                     d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, lacell, d.lwcell, d.sface)
   if (M->opts.edge_rule == 3) {
     if (P.time_rule == 1)
       HWE_ADJ_CELL(1, 3);
@@ -292,6 +309,8 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
     HWE_ADJ_CELL(0, 2);
   }
 #undef HWE_ADJ_CELL
+  hipLaunchKernelGGL((adj_recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0, st, N,
+                     NB, P, wbar, grad, d.nbr, d.bnd_n, tbl, d.area, lacell, d.lwcell, d.slots);
   hipLaunchKernelGGL((adj_gather_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg,
                      d.nbr, d.nbr_back, d.cell_edge, d.enl, d.inv_area, nl, d.slots, d.sface, lw_out, lg_out);
   hipError_t err = hipGetLastError();

@@ -86,6 +86,10 @@ struct DevMesh {
   // adjoint scratch: stencil-slot adjoints [N][4][3][m] and per-face scalars [3][N]
   double* slots = nullptr;
   double* sface = nullptr;
+  // adjoint scratch: per-cell coefficient adjoints [N][6][m] (Real) and
+  // flux-base adjoints [N][m] (double) handed from the face to the recon kernel
+  void* lacell = nullptr;
+  double* lwcell = nullptr;
   // reductions
   double* red = nullptr;   // [kRedBlocks]
   int32_t* redi = nullptr; // [kRedBlocks]

@@ -608,6 +608,8 @@ hwe_status upload_mesh(hwe_mesh_s* M) {
   HWE_TRY(dev_alloc(&d.G, m * E * rs));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.slots), 12 * m * N * sizeof(double)));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.sface), 3 * N * sizeof(double)));
+  HWE_TRY(dev_alloc(&d.lacell, 6 * m * N * rs));
+  HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.lwcell), m * N * sizeof(double)));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.red), kRedBlocks * sizeof(double)));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.redi), kRedBlocks * sizeof(int32_t)));
 #undef HWE_TRY
@@ -620,7 +622,7 @@ void free_device(hwe_mesh_s* M) {
   hipSetDevice(d.device);
   hipDeviceSynchronize();
   void* ptrs[] = {d.nbr, d.cell_edge, d.ecell, d.nbr_back, d.bnd_n, d.area, d.tbl, d.nl, d.inv_area,
-                  d.gpc, d.enl, d.egp, d.tblf, d.nlf, d.egpf, d.R, d.F, d.G, d.slots, d.sface,
+                  d.gpc, d.enl, d.egp, d.tblf, d.nlf, d.egpf, d.R, d.F, d.G, d.slots, d.sface, d.lacell, d.lwcell,
                   d.red, d.redi};
   for (void* p : ptrs)
     if (p) hipFree(p);
