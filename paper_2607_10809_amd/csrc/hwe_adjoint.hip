@@ -15,7 +15,8 @@
 //   3. adj_recon_kernel, one work-item per (cell, component q): the reverse of
 //      the reconstruction of component q (Steps 1-6, including the
 //      nonlinear-weight derivatives) into four stencil "slots" (the cell
-//      itself and its three neighbours);
+//      itself and its three neighbours); for Euler each block stages its
+//      table tile through LDS, as the forward reconstruction does;
 //   4. adj_gather_kernel, one work-item per (cell, component): its own slot, the slots its
 //      neighbours wrote for it, the Green-Gauss terms of the derivative
 //      averages and the derivative of the flux viscosity alpha (only on the
@@ -175,14 +176,33 @@ __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
     const double* __restrict__ area, const Real* __restrict__ lacell, const double* __restrict__ lwcell,
     double* __restrict__ slots) {
   constexpr int M = NComp<EQ>::m;
-  const int gid = xcd_block_id() * kBlock + threadIdx.x;
+  const int blk = xcd_block_id();
+  const int gid = blk * kBlock + threadIdx.x;
   const int i = gid / M, q = gid - (gid / M) * M;
-  if (i >= N) return;
   Real laq[6];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) laq[j] = lacell[(size_t(i) * 6 + j) * M + q];
   double slot[4][3];
-  recon_rev<EQ, Real>(i, q, N, NB, P, wbar, grad, nbr, bnd_n, tbl + tbl_col(i), area, laq, slot);
+  if constexpr (EQ == EQ_EUL) {
+    // one block per table tile, staged through LDS as in the forward reconstruction
+    static_assert(kBlock == kTile * 4, "one Euler block per table tile");
+    using Copy = TileCopy<Real, kBlock>;
+    __shared__ uint4 stage[Copy::kStage];
+    Copy tile;
+    tile.load(tbl, blk, threadIdx.x);
+    const int ic = i < N ? i : N - 1;
+    const Stencil<Real> S = gather_stencil<EQ, Real>(ic, q, N, wbar, grad, nbr);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) laq[j] = lacell[(size_t(ic) * 6 + j) * M + q];
+    tile.store(stage, threadIdx.x);
+    __syncthreads();
+    if (i >= N) return;
+    recon_rev<EQ, Real>(i, NB, P, S, bnd_n, reinterpret_cast<const Real*>(stage) + (i % kTile), area, laq, slot);
+  } else {
+    if (i >= N) return;
+    const Stencil<Real> S = gather_stencil<EQ, Real>(i, q, N, wbar, grad, nbr);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) laq[j] = lacell[(size_t(i) * 6 + j) * M + q];
+    recon_rev<EQ, Real>(i, NB, P, S, bnd_n, tbl + tbl_col(i), area, laq, slot);
+  }
   slot[0][0] += lwcell[size_t(i) * M + q];
 #pragma unroll
   for (int sl = 0; sl < 4; ++sl)

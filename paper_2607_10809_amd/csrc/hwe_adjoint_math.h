@@ -516,30 +516,26 @@ __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double d
 // f; field 0 = Wbar, 1 = V, 2 = Y).  Ghost (mirror) neighbours are folded back
 // into slot 0.
 template <int EQ, class Real>
-__host__ __device__ __forceinline__ void recon_rev(int i, int q, int N, int NB, const Params& P,
-                                                  const double* __restrict__ wbar, const Real* __restrict__ grad,
-                                                  const int32_t* __restrict__ nbr, const double* __restrict__ bnd_n,
-                                                  const Real* __restrict__ tb, const double* __restrict__ area,
-                                                  const Real (&la)[6], double (&slot)[4][3]) {
-  constexpr int M = NComp<EQ>::m;
-  const size_t sN = size_t(N);
-  // ---- forward recomputation
-  const double W0 = wbar[q * sN + i];
+__host__ __device__ __forceinline__ void recon_rev(int i, int NB, const Params& P, const Stencil<Real>& S,
+                                                  const double* __restrict__ bnd_n, const Real* __restrict__ tb,
+                                                  const double* __restrict__ area, const Real (&la)[6],
+                                                  double (&slot)[4][3]) {
+  // ---- forward recomputation from the gathered stencil (gather_stencil)
+  const double W0 = S.W0;
   double Wsum = W0, dW[3];
   Real V[4], Y[4];
   int nb[3];
-  V[0] = grad[q * sN + i];
-  Y[0] = grad[(M + q) * sN + i];
   Real gnx[3], gny[3];
   double Wn[3];
 #pragma unroll
-  for (int f = 0; f < 3; ++f) nb[f] = nbr[f * sN + i];
+  for (int f = 0; f < 4; ++f) {
+    V[f] = S.V[f];
+    Y[f] = S.Y[f];
+  }
 #pragma unroll
-  for (int f = 0; f < 3; ++f) {  // every gather before any use; a ghost face reads the cell itself
-    const int c = nb[f] >= 0 ? nb[f] : i;
-    Wn[f] = wbar[q * sN + c];
-    V[f + 1] = grad[q * sN + c];
-    Y[f + 1] = grad[(M + q) * sN + c];
+  for (int f = 0; f < 3; ++f) {
+    nb[f] = S.nbi[f];
+    Wn[f] = S.Wn[f];
   }
 #pragma unroll
   for (int f = 0; f < 3; ++f) {

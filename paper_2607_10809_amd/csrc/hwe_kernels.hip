@@ -57,23 +57,15 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
   const int i = gid / M, q = gid - (gid / M) * M;
   if constexpr (EQ == EQ_EUL) {
     static_assert(kBlock == kTile * 4, "one Euler block per table tile");
-    constexpr int kChunks = kTblRows * kTile * int(sizeof(Real)) / 16;
-    constexpr int kFull = kChunks / kBlock, kRest = kChunks - kFull * kBlock;
-    __shared__ uint4 stage[(kFull + 1) * kBlock];  // the last row is partly padding
-    const uint4* src = reinterpret_cast<const uint4*>(tbl + size_t(blk) * (kTblRows * kTile));
-    const int t = threadIdx.x;
-    uint4 buf[kFull];
-#pragma unroll
-    for (int r = 0; r < kFull; ++r) buf[r] = src[t + r * kBlock];
-    // lanes past the tile's end reload an earlier chunk (in bounds) into the padding
-    const uint4 rest = src[t + kFull * kBlock - (t < kRest ? 0 : kBlock)];
+    using Copy = TileCopy<Real, kBlock>;
+    __shared__ uint4 stage[Copy::kStage];
+    Copy tile;
+    tile.load(tbl, blk, threadIdx.x);
     // all four component lanes of a cell stay active for the limiter's shuffles
     const bool valid = i < N;
     const int ic = valid ? i : N - 1;
     const Stencil<Real> S = gather_stencil<EQ, Real>(ic, q, N, wbar, grad, nbr);
-#pragma unroll
-    for (int r = 0; r < kFull; ++r) stage[t + r * kBlock] = buf[r];
-    stage[t + kFull * kBlock] = rest;
+    tile.store(stage, threadIdx.x);
     __syncthreads();
     const Real* tb = reinterpret_cast<const Real*>(stage) + (i % kTile);
     Real a[6];

@@ -68,6 +68,33 @@ __host__ __device__ __forceinline__ void store_record(T* __restrict__ dst, const
   }
 }
 
+// ------------------------------------------------------------------ table tiles
+// A block of kThreads work-items copies one tile of the tiled reconstruction
+// table (kTblRows rows of kTile values) into LDS with 16-byte loads.  load()
+// only issues the global loads, so independent gathers can be issued before
+// store() waits for them.  The stage holds (kFull + 1) * kThreads chunks; the
+// lanes past the tile's end reload an earlier chunk (in bounds) into the
+// padding.  Tables are allocated in whole tiles.
+template <class Real, int kThreads> struct TileCopy {
+  static constexpr int kChunks = kTblRows * kTile * int(sizeof(Real)) / 16;
+  static constexpr int kFull = kChunks / kThreads, kRest = kChunks - kFull * kThreads;
+  static constexpr int kStage = (kFull + 1) * kThreads;
+  static_assert(kTblRows * kTile * sizeof(Real) % 16 == 0, "a tile is a whole number of 16-byte chunks");
+  uint4 buf[kFull];
+  uint4 rest;
+  __device__ __forceinline__ void load(const Real* __restrict__ tbl, int tile, int t) {
+    const uint4* src = reinterpret_cast<const uint4*>(tbl + size_t(tile) * (kTblRows * kTile));
+#pragma unroll
+    for (int r = 0; r < kFull; ++r) buf[r] = src[t + r * kThreads];
+    rest = src[t + kFull * kThreads - (t < kRest ? 0 : kThreads)];
+  }
+  __device__ __forceinline__ void store(uint4* stage, int t) const {
+#pragma unroll
+    for (int r = 0; r < kFull; ++r) stage[t + r * kThreads] = buf[r];
+    stage[t + kFull * kThreads] = rest;
+  }
+};
+
 // ------------------------------------------------------------------ Steps 1-6
 // The stencil of component q of cell i: its own average and derivative
 // averages and its three face neighbours'.  All loads are issued before any
