@@ -230,6 +230,37 @@ def adjoint_leg(wl, nsteps=200, ckpt=20, precision="fp64"):
             "step_us": fs * 1e3, "adjoint_step_us": as_ * 1e3, "per_step_ratio": as_ / fs}
 
 
+def mixed_error_leg(wl):
+    """Error of the mixed path against the FP64 path: both run the vortex to its
+    final time T with the same fixed step (the FP64 mesh's CFL step, last step
+    clipped); relative max norms per (block, component) of the cell averages
+    and of the derivative averages."""
+    import torch
+    from paper_2607_10809_amd.hwe import Mesh
+    res, dt = {}, None
+    for prec in ("fp64", "mixed"):
+        mesh = Mesh.from_workload(wl, precision=prec)
+        w, g = mesh.to_device(wl.state0)
+        if dt is None:
+            dt = mesh.max_dt(w, wl.cfl)
+        n = int(np.floor(wl.T / dt + 1e-12))
+        rem = wl.T - n * dt
+        w, g = mesh.run(w, g, dt, n)
+        if rem > 1e-14 * wl.T:
+            w, g = mesh.step(w, g, rem, t=n * dt)
+        torch.cuda.synchronize()
+        res[prec] = mesh.to_host(w, g)
+        del mesh
+    a, b = res["mixed"], res["fp64"]
+
+    def rel(x, y):
+        den = np.abs(y).max(axis=-1)
+        return float((np.abs(x - y).max(axis=-1) / np.where(den == 0, 1.0, den)).max())
+
+    return {"T": wl.T, "steps": n + (1 if rem > 1e-14 * wl.T else 0), "dt": dt,
+            "wbar_rel_max": rel(a[:1], b[:1]), "grad_rel_max": rel(a[1:], b[1:]), "bound_wbar": 2e-5}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -345,8 +376,10 @@ def main():
     log(f"FP64: {f64['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {f64['kernel_ms']}")
     mix = gpu_leg(wl, args.steps, args.warmup, "mixed")
     log(f"mixed: {mix['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {mix['kernel_ms']}")
-    adj = adjm = c4 = copy_gbps = None
+    adj = adjm = c4 = copy_gbps = merr = None
     if not args.forward_only:
+        log("mixed vs FP64 at T ...")
+        merr = mixed_error_leg(wl)
         if not args.no_c4:
             log("980,000-triangle Riemann leg ...")
             c4 = c4_leg(200, 10)
@@ -416,7 +449,7 @@ def main():
                                f"+-0.1h jitter seed 3 ({N} triangles)", "cells": N, "edges": E,
                    "dt": f64["dt"], "parallelism": "1 GPU"},
         "mixed": {"value": value_mixed, "ms_per_step": mix["ms"] / args.steps, "dtype": "f32 bulk + f64 averages/weights",
-                  "speedup_vs_fp64": value_mixed / value},
+                  "speedup_vs_fp64": value_mixed / value, "error_vs_fp64": merr},
         "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": {"fp64": adj, "mixed": adjm,
                     "workload": "misfit 0.5|rho(T)-rho_target|^2, 200 steps, checkpoint every 20, same mesh"},
