@@ -192,9 +192,12 @@ hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, doub
  * Same layouts and precision as hwe_step; outputs must not overlap inputs.
  * Non-smooth points: d|x| = sign(x) dx with sign(0) = 0; the max of the two
  * spectral radii in the flux viscosity takes the edge's first cell (the one
- * with the lower caller index) on ties.  Returns HWE_EINVAL for meshes built
- * with opts.positivity = 1 (the limiter is not differentiated) or with
- * reflective walls. */
+ * with the lower caller index) on ties.  Every boundary kind is
+ * differentiated: a prescribed or moving boundary state is a constant of the
+ * step (evaluated, as in hwe_step, at the time set by hwe_set_time + dt/2, so
+ * set the time of step n before its adjoint), a reflective wall's exterior is
+ * the mirrored interior.  Returns HWE_EINVAL for meshes built with
+ * opts.positivity = 1 (the limiter is not differentiated). */
 hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n,
                             const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n,
                             void* lam_grad_n, double dt, void* stream);
@@ -225,8 +228,8 @@ hwe_status hwe_step_adjoint_kept(hwe_mesh m, const double* wbar_n, const void* g
                                  const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n,
                                  void* lam_grad_n, double dt, void* stream);
 
-/* Time of the state handed to the following hwe_step / hwe_step_keep calls on
- * this handle (default 0).  Only HWE_BND_MOVING faces depend on it: a step
+/* Time of the state handed to the following hwe_step / hwe_step_keep /
+ * hwe_step_adjoint / hwe_step_adjoint_kept calls on this handle (default 0).  Only HWE_BND_MOVING faces depend on it: a step
  * from time t with size dt evaluates them at t + dt/2.  Host-side; the value is
  * taken when a step is launched. */
 hwe_status hwe_set_time(hwe_mesh m, double t);

@@ -9,7 +9,8 @@ of every recomputed step (hwe_step_keep), then walks it backwards with the
 adjoint that reuses them (hwe_step_adjoint_kept).  The last state of a
 segment is never stepped during the recomputation, so its reconstruction is
 rebuilt by the adjoint itself.  The time step is a constant (not
-differentiated).
+differentiated); step k runs from time t0 + k dt (read by moving boundary
+states).
 """
 from __future__ import annotations
 
@@ -18,7 +19,7 @@ import torch
 
 class Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, wbar0, grad0, mesh, dt, n_steps, ckpt):
+    def forward(ctx, wbar0, grad0, mesh, dt, n_steps, ckpt, t0):
         if ckpt <= 0:
             raise ValueError("ckpt must be positive")
         if mesh.opts.positivity:
@@ -28,17 +29,17 @@ class Rollout(torch.autograd.Function):
         bufs = [mesh.empty_state(), mesh.empty_state()]
         for k in range(n_steps):
             nxt = bufs[k % 2]
-            mesh.step(cur[0], cur[1], dt, out=nxt)
+            mesh.step(cur[0], cur[1], dt, out=nxt, t=t0 + k * dt)
             cur = nxt
             if (k + 1) % ckpt == 0 and k + 1 < n_steps:
                 checkpoints.append((cur[0].clone(), cur[1].clone()))
-        ctx.mesh, ctx.dt, ctx.n_steps, ctx.ckpt = mesh, dt, n_steps, ckpt
+        ctx.mesh, ctx.dt, ctx.n_steps, ctx.ckpt, ctx.t0 = mesh, dt, n_steps, ckpt, t0
         ctx.checkpoints = checkpoints
         return cur[0].clone(), cur[1].clone()
 
     @staticmethod
     def backward(ctx, lw, lg):
-        mesh, dt, n, ckpt = ctx.mesh, ctx.dt, ctx.n_steps, ctx.ckpt
+        mesh, dt, n, ckpt, t0 = ctx.mesh, ctx.dt, ctx.n_steps, ctx.ckpt, ctx.t0
         lam = (lw.contiguous().to(torch.float64), lg.contiguous().to(mesh.gdtype))
         nseg = len(ctx.checkpoints)
         out = [mesh.empty_state(), mesh.empty_state()]
@@ -50,17 +51,18 @@ class Rollout(torch.autograd.Function):
             # recompute the states of the segment, keeping each step's reconstruction
             states = [ctx.checkpoints[s]]
             for k in range(length - 1):
-                states.append(mesh.step(states[-1][0], states[-1][1], dt, keep=recon[k]))
+                states.append(mesh.step(states[-1][0], states[-1][1], dt, keep=recon[k], t=t0 + (start + k) * dt))
             for k in reversed(range(length)):
                 dst = out[flip]
                 flip ^= 1
                 R = recon[k] if k < length - 1 else None
-                mesh.adjoint(states[k][0], states[k][1], lam[0], lam[1], dt, out=dst, recon=R)
+                mesh.adjoint(states[k][0], states[k][1], lam[0], lam[1], dt, out=dst, recon=R, t=t0 + (start + k) * dt)
                 lam = dst
             ctx.checkpoints[s] = None
-        return lam[0].clone(), lam[1].clone(), None, None, None, None
+        return lam[0].clone(), lam[1].clone(), None, None, None, None, None
 
 
-def rollout(mesh, wbar0, grad0, dt, n_steps, ckpt=20):
-    """Final state after n_steps steps; differentiable with respect to (wbar0, grad0)."""
-    return Rollout.apply(wbar0, grad0, mesh, float(dt), int(n_steps), int(ckpt))
+def rollout(mesh, wbar0, grad0, dt, n_steps, ckpt=20, t0=0.0):
+    """Final state after n_steps steps from time t0; differentiable with
+    respect to (wbar0, grad0)."""
+    return Rollout.apply(wbar0, grad0, mesh, float(dt), int(n_steps), int(ckpt), float(t0))

@@ -46,14 +46,15 @@ template <int M> __device__ __forceinline__ size_t slot_index(int i, int sl, int
 // per side).
 constexpr int kFaceCells = 21;  // cells per wave in adj_face_kernel (63 of 64 lanes)
 
-template <int EQ, class Real, int TR, int GP>
+template <int EQ, class Real, int TR, int GP, bool SB>
 __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_face_kernel(
-    int N, int E, Params P, double dt, const double* __restrict__ wbar, const double* __restrict__ lw,
+    int N, int E, int NB, Params P, double dt, const double* __restrict__ wbar, const double* __restrict__ lw,
     const Real* __restrict__ lg, const Real* __restrict__ R, const int32_t* __restrict__ nbr,
     const int32_t* __restrict__ cell_edge, const double* __restrict__ enl, const Real* __restrict__ egp,
-    const double* __restrict__ inv_area, const Real* __restrict__ nl, Real* __restrict__ lacell,
-    double* __restrict__ lwcell, double* __restrict__ sface) {
+    const double* __restrict__ inv_area, const Real* __restrict__ nl, const double* __restrict__ bnd_n,
+    Real* __restrict__ lacell, double* __restrict__ lwcell, double* __restrict__ sface) {
   constexpr int M = NComp<EQ>::m;
+  constexpr bool kWall = SB && EQ == EQ_EUL;
   const int gid = xcd_block_id() * kBlock + threadIdx.x;
   const int wv = gid >> 6, wl = gid & 63;
   const int c = wl / 3, lane = wl - 3 * c;                 // lane = the face
@@ -97,45 +98,109 @@ __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_face_ke
       lG[q] = has ? nlx * (iaK * lgxK - ian * lgxn) + nly * (iaK * lgyK - ian * lgyn)
                   : iaK * (nlx * lgxK + nly * lgyK);
     }
-    double alpha = 0.0;
+    // SB: a boundary face may be a reflective wall (exterior: the mirror image
+    // T Wbar_K, T reflecting the momentum about the face) or hold a prescribed
+    // state Wx; both give the two-sided flux with the cell as side 0
+    bool presc = false, wall = false;
+    double Wx[M], bx = 0.0, by = 0.0;
+#pragma unroll
+    for (int q = 0; q < M; ++q) Wx[q] = WK[q];
+    if constexpr (SB) {
+      if (!has) {
+        const int b = -nbv - 1;
+        const double kind = bnd_n[2 * size_t(NB) + b];
+        presc = kind >= 2.0;
+        if (presc) prescribed_state<M>(P, kind, bnd_n[3 * size_t(NB) + b], Wx);
+        if constexpr (kWall) {
+          wall = kind == 1.0;
+          bx = bnd_n[b];
+          by = bnd_n[NB + b];
+          if (wall) reflect_momentum(nx, ny, Wx);
+        }
+      }
+    }
+    double alpha = 0.0, la0 = 0.0, la1 = 0.0;
     if (nb >= 0) {
-      const double la0 = side ? spectral_radius<EQ>(P, Wn, nx, ny) : spectral_radius<EQ>(P, WK, nx, ny);
-      const double la1 = side ? spectral_radius<EQ>(P, WK, nx, ny) : spectral_radius<EQ>(P, Wn, nx, ny);
+      la0 = side ? spectral_radius<EQ>(P, Wn, nx, ny) : spectral_radius<EQ>(P, WK, nx, ny);
+      la1 = side ? spectral_radius<EQ>(P, WK, nx, ny) : spectral_radius<EQ>(P, Wn, nx, ny);
+      alpha = la0 >= la1 ? la0 : la1;
+    } else if (SB && (presc || wall)) {
+      la0 = spectral_radius<EQ>(P, WK, nx, ny);
+      la1 = spectral_radius<EQ>(P, Wx, nx, ny);
       alpha = la0 >= la1 ? la0 : la1;
     }
     // flux base terms:  d/dWbar_K of |e| 1/2 (H(Wbar_K) + sigma alpha Wbar_K) . lF
-    if (nb >= 0) {
+    if (nb >= 0 || (SB && (presc || wall))) {
       normal_flux_jt<EQ>(P, WK, nx, ny, lF, 0.5 * len, lWf);
 #pragma unroll
       for (int q = 0; q < M; ++q) lWf[q] += 0.5 * len * sigma * alpha * lF[q];
+      if constexpr (kWall) {
+        if (wall) {
+          // |e| 1/2 (H(T Wbar_K) - alpha T Wbar_K), mapped back through T
+          double t[M];
+#pragma unroll
+          for (int q = 0; q < M; ++q) t[q] = 0.0;
+          normal_flux_jt<EQ>(P, Wx, nx, ny, lF, 0.5 * len, t);
+#pragma unroll
+          for (int q = 0; q < M; ++q) t[q] -= 0.5 * len * alpha * lF[q];
+          reflect_momentum(nx, ny, t);
+#pragma unroll
+          for (int q = 0; q < M; ++q) lWf[q] += t[q];
+        }
+      }
     } else {
       normal_flux_jt<EQ>(P, WK, nx, ny, lF, len, lWf);
     }
+    // the wall's mirror terms take T lF and T lG
+    double TlF[M], TlG[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      TlF[q] = lF[q];
+      TlG[q] = lG[q];
+    }
+    if constexpr (kWall) {
+      reflect_momentum(nx, ny, TlF);
+      reflect_momentum(nx, ny, TlG);
+    }
+    double lWT[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) lWT[q] = 0.0;
+    double sT = 0.0;
     Real a[6][M];
     load_record<6 * M>(R + size_t(ic) * (6 * M), &a[0][0]);
     double s = 0.0;
     auto point = [&](int g) {
       // seeds of Gauss point g (weight wg; 1/2 each with 2 points)
       const double wg = GP == 2 ? 0.5 : (g == 1 ? 8.0 / 18.0 : 5.0 / 18.0);
-      Real sAH[M], sAD[M], sAT[M];
+      Real sAH[M], sAD[M], sAT[M], sAHw[M];
 #pragma unroll
       for (int q = 0; q < M; ++q) {
-        if (nb >= 0) {
+        if (nb >= 0 || (SB && presc)) {
           sAH[q] = Real(wg * (0.5 * len * lF[q]));
           sAD[q] = Real(wg * (0.5 * len * sigma * alpha * lF[q]));
           sAT[q] = Real(wg * (0.5 * lG[q]));
+        } else if (kWall && wall) {
+          // the exterior offsets are T d: its AD and AT terms come back through T
+          sAH[q] = Real(wg * (0.5 * len * lF[q]));
+          sAD[q] = Real(wg * (0.5 * len * alpha * (lF[q] - TlF[q])));
+          sAT[q] = Real(wg * (0.5 * (lG[q] + TlG[q])));
         } else {
           sAH[q] = Real(wg * (len * lF[q]));
           sAD[q] = Real(0);
           sAT[q] = Real(wg * lG[q]);
         }
+        sAHw[q] = wall ? sAH[q] : Real(0);
       }
       const Real X = egp[(2 * GP * side + 2 * g) * sE + e];
       const Real Y = egp[(2 * GP * side + 2 * g + 1) * sE + e];
       Real ADg[M];
-      edge_lane_rev<EQ, Real, TR>(P, dt, a, WK, X, Y, Real(nx), Real(ny), sAH, sAD, sAT, la, lWf, ADg);
+      edge_lane_rev<EQ, Real, TR, kWall>(P, dt, a, WK, X, Y, Real(nx), Real(ny), sAH, sAD, sAT, la, lWf, ADg, Wx,
+                                         sAHw, lWT);
 #pragma unroll
-      for (int q = 0; q < M; ++q) s += wg * lF[q] * double(ADg[q]);
+      for (int q = 0; q < M; ++q) {
+        s += wg * lF[q] * double(ADg[q]);
+        sT += wg * TlF[q] * double(ADg[q]);
+      }
     };
     if constexpr (GP == 2) {
 #pragma unroll
@@ -144,6 +209,43 @@ __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_face_ke
       // kept rolled: unrolling three point reversals spills
 #pragma unroll 1
       for (int g = 0; g < GP; ++g) point(g);
+    }
+    if constexpr (SB) {
+      if (presc || wall) {
+        // the flux viscosity on the branch the max took (a prescribed state is
+        // constant): d alpha . (-|e|/2) lF . ((W_ext - Wbar_K) + (AD_ext - AD_K))
+        double jb = (wall ? sT : 0.0) - s;
+#pragma unroll
+        for (int q = 0; q < M; ++q) jb += lF[q] * (Wx[q] - WK[q]);
+        const double sc = -0.5 * len * jb;
+        if (la0 >= la1) {
+          spectral_radius_grad<EQ>(P, WK, nx, ny, sc, lWf);
+        } else if (kWall && wall) {
+          double t[M];
+#pragma unroll
+          for (int q = 0; q < M; ++q) t[q] = 0.0;
+          spectral_radius_grad<EQ>(P, Wx, nx, ny, sc, t);
+          if constexpr (kWall) reflect_momentum(nx, ny, t);
+#pragma unroll
+          for (int q = 0; q < M; ++q) lWf[q] += t[q];
+        }
+        // Green-Gauss: half the difference of the ghost average to the cell's
+        if (presc) {
+#pragma unroll
+          for (int q = 0; q < M; ++q) lWf[q] -= 0.5 * lG[q];
+        }
+        if constexpr (kWall) {
+          if (wall) {
+            // -(m.n) n in the momentum components; the mirror's offset base
+            const double lmn = -(bx * lG[1] + by * lG[2]);
+            lWf[1] += lmn * bx;
+            lWf[2] += lmn * by;
+            reflect_momentum(nx, ny, lWT);
+#pragma unroll
+            for (int q = 0; q < M; ++q) lWf[q] += lWT[q];
+          }
+        }
+      }
     }
     if (valid) sface[f * sN + ic] = s;
   }
@@ -169,7 +271,7 @@ __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_face_ke
 // One work-item per (cell, component q): the reverse of the reconstruction of
 // component q (Steps 1-6, with the nonlinear-weight derivatives) from the
 // coefficient adjoints the face kernel summed, into the cell's stencil slots.
-template <int EQ, class Real>
+template <int EQ, class Real, bool SB>
 __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
     int N, int NB, Params P, const double* __restrict__ wbar, const Real* __restrict__ grad,
     const int32_t* __restrict__ nbr, const double* __restrict__ bnd_n, const Real* __restrict__ tbl,
@@ -194,14 +296,28 @@ __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
     for (int j = 0; j < 6; ++j) laq[j] = lacell[(size_t(ic) * 6 + j) * M + q];
     tile.store(stage, threadIdx.x);
     __syncthreads();
-    if (i >= N) return;
-    recon_rev<EQ, Real>(i, NB, P, S, bnd_n, reinterpret_cast<const Real*>(stage) + (i % kTile), area, laq, slot);
+    if (i >= N) return;  // whole cells: the four lanes of a quad leave together
+    double cross[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, reinterpret_cast<const Real*>(stage) + (i % kTile), area, laq, slot,
+                            q, N, wbar, grad, cross);
+    if constexpr (SB) {
+      // wall ghosts: the momentum lanes (q = 1, 2 of the quad) exchange the
+      // terms each produced for the other's component
+      static_assert(kBlock % 64 == 0 && M == 4, "a cell's four lanes form an aligned quad");
+      constexpr int kSwap12 = 3 | (2 << 2) | (1 << 4) | (0 << 6);  // lanes 0<->3, 1<->2
+#pragma unroll
+      for (int fl = 0; fl < 3; ++fl) {
+        const double own = q == 1 ? cross[0][fl] : (q == 2 ? cross[1][fl] : 0.0);
+        const double give = q == 1 ? cross[1][fl] : (q == 2 ? cross[0][fl] : 0.0);
+        slot[0][fl] += own + quad_perm<kSwap12>(give);
+      }
+    }
   } else {
     if (i >= N) return;
     const Stencil<Real> S = gather_stencil<EQ, Real>(i, q, N, wbar, grad, nbr);
 #pragma unroll
     for (int j = 0; j < 6; ++j) laq[j] = lacell[(size_t(i) * 6 + j) * M + q];
-    recon_rev<EQ, Real>(i, NB, P, S, bnd_n, tbl + tbl_col(i), area, laq, slot);
+    recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tbl + tbl_col(i), area, laq, slot, q, N, wbar, grad, nullptr);
   }
   slot[0][0] += lwcell[size_t(i) * M + q];
 #pragma unroll
@@ -315,9 +431,18 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
   const int64_t waves = (int64_t(N) + kFaceCells - 1) / kFaceCells;
   const dim3 grid(unsigned((waves * 64 + kBlock - 1) / kBlock));
   Real* lacell = static_cast<Real*>(d.lacell);
-#define HWE_ADJ_CELL(TRV, GPV)                                                                                      \
-  hipLaunchKernelGGL((adj_face_kernel<EQ, Real, TRV, GPV>), grid, dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg, R, \
-                     d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, lacell, d.lwcell, d.sface)
+  const bool sb = h.special_bnd;
+#define HWE_ADJ_CELL(TRV, GPV)                                                                                        \
+  do {                                                                                                                \
+    if (sb)                                                                                                           \
+      hipLaunchKernelGGL((adj_face_kernel<EQ, Real, TRV, GPV, true>), grid, dim3(kBlock), 0, st, N, E, NB, P, dt,     \
+                         wbar, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, lacell, d.lwcell,  \
+                         d.sface);                                                                                    \
+    else                                                                                                              \
+      hipLaunchKernelGGL((adj_face_kernel<EQ, Real, TRV, GPV, false>), grid, dim3(kBlock), 0, st, N, E, NB, P, dt,    \
+                         wbar, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, lacell, d.lwcell,  \
+                         d.sface);                                                                                    \
+  } while (0)
   if (M->opts.edge_rule == 3) {
     if (P.time_rule == 1)
       HWE_ADJ_CELL(1, 3);
@@ -329,8 +454,12 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
     HWE_ADJ_CELL(0, 2);
   }
 #undef HWE_ADJ_CELL
-  hipLaunchKernelGGL((adj_recon_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0, st, N,
-                     NB, P, wbar, grad, d.nbr, d.bnd_n, tbl, d.area, lacell, d.lwcell, d.slots);
+  if (sb)
+    hipLaunchKernelGGL((adj_recon_kernel<EQ, Real, true>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0,
+                       st, N, NB, P, wbar, grad, d.nbr, d.bnd_n, tbl, d.area, lacell, d.lwcell, d.slots);
+  else
+    hipLaunchKernelGGL((adj_recon_kernel<EQ, Real, false>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0,
+                       st, N, NB, P, wbar, grad, d.nbr, d.bnd_n, tbl, d.area, lacell, d.lwcell, d.slots);
   hipLaunchKernelGGL((adj_gather_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg,
                      d.nbr, d.nbr_back, d.cell_edge, d.enl, d.inv_area, nl, d.slots, d.sface, lw_out, lg_out);
   hipError_t err = hipGetLastError();
@@ -343,11 +472,12 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
 hwe_status launch_adjoint(hwe_mesh_s* M, const double* wbar_n, const void* grad_n, const void* R_n, const double* lw,
                           const void* lg, double* lw_out, void* lg_out, double dt, void* stream) {
   if (!R_n) {
-    hwe_status s = launch_recon(M, wbar_n, grad_n, M->d.R, stream);
+    hwe_status s = launch_recon(M, wbar_n, grad_n, M->d.R, M->time + 0.5 * dt, stream);
     if (s != HWE_OK) return s;
     R_n = M->d.R;
   }
-  const Params P = params_of(M->opts);
+  Params P = params_of(M->opts);
+  P.tb = M->time + 0.5 * dt;  // as the step: moving boundary states at the middle of the step
   hipStream_t st = static_cast<hipStream_t>(stream);
   const DevMesh& d = M->d;
   if (M->opts.prec == HWE_FP64) {

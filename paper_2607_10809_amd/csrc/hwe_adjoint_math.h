@@ -419,14 +419,22 @@ __host__ __device__ __forceinline__ void spectral_radius_grad(const Params& P, c
 // adjoints of AH, AD, AT of this lane, accumulate the adjoints of the cell's
 // coefficients a[6][M] and of its cell average.  Returns (in ADout) the
 // forward AD of the lane, used by the flux viscosity's adjoint.
-template <int EQ, class Real, int TR>
+// WALL (Euler): the face is a reflective wall, whose exterior flux term is
+// the normal flux at the mirror image, base WT = T Wbar and offsets T d(tau)
+// (T reflects the momentum about the face); lAHw seeds that term's time
+// integral, and lWT receives the adjoint of WT (the caller maps it back
+// through T).
+template <int EQ, class Real, int TR, bool WALL = false>
 __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double dt, const Real (&a)[6][NComp<EQ>::m],
                                                       const double (&Wbd)[NComp<EQ>::m], Real X, Real Y, Real nx,
                                                       Real ny, const Real (&lAH)[NComp<EQ>::m],
                                                       const Real (&lAD)[NComp<EQ>::m],
                                                       const Real (&lAT)[NComp<EQ>::m], Real (&la)[6][NComp<EQ>::m],
-                                                      double (&lW)[NComp<EQ>::m], Real (&ADout)[NComp<EQ>::m]) {
+                                                      double (&lW)[NComp<EQ>::m], Real (&ADout)[NComp<EQ>::m],
+                                                      const double* WT = nullptr, const Real* lAHw = nullptr,
+                                                      double* lWT = nullptr) {
   constexpr int M = NComp<EQ>::m;
+  static_assert(!WALL || EQ == EQ_EUL, "walls reflect a momentum");
   Real D[6][M], dl[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) {
@@ -445,6 +453,17 @@ __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double d
 #pragma unroll
   for (int q = 0; q < M; ++q) lb.w[q] = Real(0);
   lb.u = lb.v = lb.p = Real(0);
+  FluxBase<EQ, Real> baseT;
+  FluxBaseAdj<EQ, Real> lbT;
+  if constexpr (WALL) {
+    double W[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) W[q] = WT[q];
+    baseT = flux_base<EQ, Real>(P, W);
+#pragma unroll
+    for (int q = 0; q < M; ++q) lbT.w[q] = Real(0);
+    lbT.u = lbT.v = lbT.p = Real(0);
+  }
   Real ldl[M], lWt[M], lWtt[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) {
@@ -464,6 +483,21 @@ __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double d
       lds[q] = w * lAD[q];
     }
     normal_flux_delta_rev<EQ, Real>(P, base, dls, nx, ny, L, lds, lb);
+    if constexpr (WALL) {
+      // the mirror side's flux offset at T d(tau), reversed and mapped back through T
+      Real dT[M], LT[M], ldT[M];
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        dT[q] = dls[q];
+        LT[q] = w * lAHw[q];
+        ldT[q] = Real(0);
+      }
+      reflect_momentum(nx, ny, dT);
+      normal_flux_delta_rev<EQ, Real>(P, baseT, dT, nx, ny, LT, ldT, lbT);
+      reflect_momentum(nx, ny, ldT);
+#pragma unroll
+      for (int q = 0; q < M; ++q) lds[q] += ldT[q];
+    }
 #pragma unroll
     for (int q = 0; q < M; ++q) {
       ldl[q] += lds[q];
@@ -496,6 +530,17 @@ __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double d
     for (int q = 0; q < M; ++q) lD[j][q] = Real(0);
   lax_wendroff_rev<EQ, Real>(P, D, lWt, lWtt, lD);
   flux_base_rev<EQ, Real>(P, Wbd, lb, lW);
+  if constexpr (WALL) {
+    double W[M], l[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      W[q] = WT[q];
+      l[q] = 0.0;
+    }
+    flux_base_rev<EQ, Real>(P, W, lbT, l);
+#pragma unroll
+    for (int q = 0; q < M; ++q) lWT[q] += l[q];
+  }
 #pragma unroll
   for (int q = 0; q < M; ++q) {
     const Real l0 = ldl[q] + lD[0][q];
@@ -515,11 +560,20 @@ __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double d
 // slot[s][field] (s = 0: the cell itself, s = f+1: its neighbour across face
 // f; field 0 = Wbar, 1 = V, 2 = Y).  Ghost (mirror) neighbours are folded back
 // into slot 0.
-template <int EQ, class Real>
+// SB: the mesh has walls or prescribed boundary states.  A prescribed ghost
+// is a flat cell holding the prescribed state (only -W0 in its difference
+// depends on the cell); a wall ghost of an Euler momentum component mixes the
+// cell's two momentum components, and cross[c][field] (c = 0, 1: momentum
+// components 1, 2) receives those terms of slot 0 for the kernel to exchange
+// between the component lanes.  wbar, grad, N: the cell's other components.
+template <int EQ, class Real, bool SB = false>
 __host__ __device__ __forceinline__ void recon_rev(int i, int NB, const Params& P, const Stencil<Real>& S,
                                                   const double* __restrict__ bnd_n, const Real* __restrict__ tb,
                                                   const double* __restrict__ area, const Real (&la)[6],
-                                                  double (&slot)[4][3]) {
+                                                  double (&slot)[4][3], int q = 0, int N = 0,
+                                                  const double* __restrict__ wbar = nullptr,
+                                                  const Real* __restrict__ grad = nullptr,
+                                                  double (*cross)[3] = nullptr) {
   // ---- forward recomputation from the gathered stencil (gather_stencil)
   const double W0 = S.W0;
   double Wsum = W0, dW[3];
@@ -527,6 +581,22 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int NB, const Params& 
   int nb[3];
   Real gnx[3], gny[3];
   double Wn[3];
+  // ghost kinds (SB): 0 mirror, 1 wall (momentum component), 2 prescribed
+  int gk[3] = {0, 0, 0};
+  double wna[3] = {0, 0, 0}, wnx[3] = {0, 0, 0}, wny[3] = {0, 0, 0};
+  Real gV1 = Real(0), gY1 = Real(0), gV2 = Real(0), gY2 = Real(0);
+  double gm1 = 0.0, gm2 = 0.0;
+  if constexpr (SB && EQ == EQ_EUL) {
+    if (q == 1 || q == 2) {
+      constexpr int M = NComp<EQ>::m;
+      gm1 = wbar[1 * size_t(N) + i];
+      gm2 = wbar[2 * size_t(N) + i];
+      gV1 = grad[1 * size_t(N) + i];
+      gY1 = grad[(M + 1) * size_t(N) + i];
+      gV2 = grad[2 * size_t(N) + i];
+      gY2 = grad[(M + 2) * size_t(N) + i];
+    }
+  }
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     V[f] = S.V[f];
@@ -547,11 +617,41 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int NB, const Params& 
       const int b = -nb[f] - 1;
       gnx[f] = Real(bnd_n[b]);
       gny[f] = Real(bnd_n[NB + b]);
-      dW[f] = 0.0;
-      Wsum += W0;
-      const Real vn = V[0] * gnx[f] + Y[0] * gny[f];
-      V[f + 1] = V[0] - Real(2) * gnx[f] * vn;
-      Y[f + 1] = Y[0] - Real(2) * gny[f] * vn;
+      const double kind = SB ? bnd_n[2 * NB + b] : 0.0;
+      if (SB && kind >= 2.0) {
+        gk[f] = 2;
+        const double Wd = prescribed_component(P, kind, bnd_n[3 * NB + b], q);
+        dW[f] = Wd - W0;
+        Wsum += Wd;
+        V[f + 1] = Real(0);
+        Y[f + 1] = Real(0);
+      } else {
+        dW[f] = 0.0;
+        Wsum += W0;
+        const Real vn = V[0] * gnx[f] + Y[0] * gny[f];
+        V[f + 1] = V[0] - Real(2) * gnx[f] * vn;
+        Y[f + 1] = Y[0] - Real(2) * gny[f] * vn;
+        if constexpr (SB && EQ == EQ_EUL) {
+          if ((q == 1 || q == 2) && kind == 1.0) {
+            // as the forward: m -> m - 2 (m.n) n in the average, the momentum
+            // rows of the gradient mixed the same way
+            gk[f] = 1;
+            const double dnx = bnd_n[b], dny = bnd_n[NB + b], na = q == 1 ? dnx : dny;
+            wnx[f] = dnx;
+            wny[f] = dny;
+            wna[f] = na;
+            dW[f] = -2.0 * na * (gm1 * dnx + gm2 * dny);
+            Wsum += dW[f];
+            const Real nx = gnx[f], ny = gny[f];
+            const Real v1 = gV1 * nx + gY1 * ny, v2 = gV2 * nx + gY2 * ny;
+            const Real R1x = gV1 - Real(2) * nx * v1, R1y = gY1 - Real(2) * ny * v1;
+            const Real R2x = gV2 - Real(2) * nx * v2, R2y = gY2 - Real(2) * ny * v2;
+            const Real rn = Real(2) * Real(na);
+            V[f + 1] = V[f + 1] - rn * (nx * R1x + ny * R2x);
+            Y[f + 1] = Y[f + 1] - rn * (nx * R1y + ny * R2y);
+          }
+        }
+      }
     }
   }
   Real c[5];
@@ -699,12 +799,32 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int NB, const Params& 
       slot[0][0] -= ldW[f];
       slot[f + 1][1] += double(lV[f + 1]);
       slot[f + 1][2] += double(lY[f + 1]);
+    } else if (SB && gk[f] == 2) {
+      // prescribed ghost: dW = Wd - W0, no derivative averages
+      slot[0][0] -= ldW[f];
     } else {
       // ghost: W = W0 (dW = 0 identically), gradient reflected by I - 2 n n^T
       slot[0][0] += lWsum;
       const Real lvn = gnx[f] * lV[f + 1] + gny[f] * lY[f + 1];
       slot[0][1] += double(lV[f + 1] - Real(2) * gnx[f] * lvn);
       slot[0][2] += double(lY[f + 1] - Real(2) * gny[f] * lvn);
+      if constexpr (SB && EQ == EQ_EUL) {
+        if (gk[f] == 1) {
+          // wall: dW = -2 n_q (m.n), also summed into W_ave; the mixed rows
+          // -2 n_q (n_x R_1 + n_y R_2) with R_c the mirrored gradient of m_c
+          const double lmn = -2.0 * wna[f] * (ldW[f] + lWsum);
+          cross[0][0] += lmn * wnx[f];
+          cross[1][0] += lmn * wny[f];
+          const Real nx = gnx[f], ny = gny[f], rn = Real(2) * Real(wna[f]);
+          const Real a = lV[f + 1], b = lY[f + 1];
+          const Real l1x = -rn * nx * a, l2x = -rn * ny * a, l1y = -rn * nx * b, l2y = -rn * ny * b;
+          const Real lv1 = -Real(2) * (nx * l1x + ny * l1y), lv2 = -Real(2) * (nx * l2x + ny * l2y);
+          cross[0][1] += double(l1x + nx * lv1);
+          cross[0][2] += double(l1y + ny * lv1);
+          cross[1][1] += double(l2x + nx * lv2);
+          cross[1][2] += double(l2y + ny * lv2);
+        }
+      }
     }
   }
 }

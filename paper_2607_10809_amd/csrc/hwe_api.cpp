@@ -267,10 +267,6 @@ hwe_status check_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n, c
     set_error("output buffers overlap each other");
     return HWE_EINVAL;
   }
-  if (m->h.special_bnd) {
-    set_error("hwe_step_adjoint: meshes with reflective walls or prescribed boundary states are not differentiated");
-    return HWE_EINVAL;
-  }
   if (m->opts.positivity) {
     set_error("hwe_step_adjoint: the positivity limiter is not differentiated");
     return HWE_EINVAL;
@@ -347,7 +343,7 @@ hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, voi
     return HWE_EINVAL;
   }
   if ((s = set_dev(m)) != HWE_OK) return s;
-  return launch_recon(m, wbar, grad, R_out, stream);
+  return launch_recon(m, wbar, grad, R_out, m->time, stream);
 }
 
 hwe_status hwe_debug_edge(hwe_mesh m, const void* R, const double* wbar, double dt, double* F_out, void* G_out,

@@ -124,7 +124,9 @@ void free_device(hwe_mesh_s* M);
 // handle's scratch R.
 hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out,
                        void* grad_out, double dt, void* R_keep, void* stream);
-hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, void* R_out, void* stream);
+// tb: the time at which moving boundary states are evaluated (a step uses
+// the middle of the step)
+hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, void* R_out, double tb, void* stream);
 hwe_status launch_edge(hwe_mesh_s* M, const void* R, const double* wbar, double dt, double* F_out, void* G_out,
                        void* stream);
 // R_n (may be null): the reconstruction of state n kept by a step; null

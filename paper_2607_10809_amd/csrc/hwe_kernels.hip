@@ -653,9 +653,9 @@ hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in
   }
 }
 
-hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, void* R_out, void* stream) {
+hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, void* R_out, double tb, void* stream) {
   Params P = params_of(M->opts);
-  P.tb = M->time;
+  P.tb = tb;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const DevMesh& d = M->d;
   if (M->opts.prec == HWE_FP64) {

@@ -266,9 +266,12 @@ class Mesh:
         torch.cuda.current_stream(self.device).wait_stream(s)
         return g
 
-    def adjoint(self, wbar, grad, lam_wbar, lam_grad, dt, out=None, stream=None, recon=None):
-        """J^T lam at the state (wbar, grad).  recon: the buffer that
-        step(wbar, grad, ..., keep=recon) filled; skips the reconstruction."""
+    def adjoint(self, wbar, grad, lam_wbar, lam_grad, dt, out=None, stream=None, recon=None, t=None):
+        """J^T lam at the state (wbar, grad) (of the step from time t, if
+        given).  recon: the buffer that step(wbar, grad, ..., keep=recon)
+        filled; skips the reconstruction."""
+        if t is not None:
+            self.set_time(t)
         self._check_state(wbar, grad)
         self._check_state(lam_wbar, lam_grad)
         lw, lg = out if out is not None else self.empty_state()

@@ -1,7 +1,11 @@
 """GPU tests of the hand-written adjoint (hwe_step_adjoint) and the checkpointed rollout.
 
 * dot-product test: <J^T lam, v> from the HIP adjoint against <lam, J v> from
-  the oracle's dual-number JVP (FP64, several equations and boundaries);
+  the oracle's dual-number JVP (FP64, several equations; periodic and
+  transmissive boundaries, reflective walls, prescribed inflow states and the
+  moving switch between two states, with the 2- and 3-point edge rules);
+* a checkpointed rollout from t0 > 0 across the moving switch against the
+  oracle's multi-step JVP;
 * the full gradient on a tiny mesh against the oracle's Jacobian assembled
   column by column from its JVPs;
 * the C5 misfit gradient (vortex, 204,800 triangles, 200 steps, checkpoint
@@ -19,7 +23,10 @@ sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 from oracle import OracleMesh  # noqa: E402
 from workloads import (advection_workload, burgers_workload, fd_directions, make_vortex,  # noqa: E402
-                       cell_average_states, perturbed_vortex_target_center, riemann_workload, vortex_workload)
+                       cell_average_states, double_mach_workload, moving_shock_workload,
+                       perturbed_vortex_target_center, riemann_workload, shock_tube_workload, shu_osher_workload,
+                       split_square_mesh, vortex_workload, wedge_workload)
+from workloads.problems import Workload  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +76,113 @@ def test_dot_product_against_oracle_jvp(case):
         scale = float(np.abs(vj * v).sum())
         print(case, "<J^T l, v> =", a, "<l, J v> =", b, flush=True)
         assert abs(a - b) <= 1e-11 * scale
+
+
+def _closed_box_workload():
+    """Euler in the unit square with reflective walls all round (a smooth bump)."""
+    box = (0.0, 1.0, 0.0, 1.0)
+    mesh = split_square_mesh(12, box, jitter=0.2, seed=22, periodic=False)
+
+    def f(x, y, t):
+        r = 1.0 + 0.3 * np.exp(-30 * ((x - 0.4) ** 2 + (y - 0.55) ** 2))
+        return np.stack([r, 0.2 * r, -0.1 * r, 2.5 + 0.025 * r + 0 * x], -1)
+
+    return Workload(name="closed box", eq=2, m=4, mesh=mesh, state0=cell_average_states(mesh, f), T=0.1, cfl=0.3,
+                    walls=0b1111)
+
+
+# boundary cases: (workload, start time, oracle pre-steps to develop waves, options)
+BOUNDARY_CASES = {
+    "sod_walls": (lambda: shock_tube_workload("sod", nx=40), 0.0, 10, {}),
+    "closed_box_walls": (_closed_box_workload, 0.0, 5, {}),
+    "shu_osher_inflow": (lambda: shu_osher_workload(nx=60, height=0.3), 0.0, 5, {}),
+    "double_mach_moving": (lambda: double_mach_workload(n=12), 0.012, 0, {}),
+    "wedge_walls_inflow": (lambda: wedge_workload(nx=32, ny=12), 0.0, 5, {}),
+    "moving_shock": (lambda: moving_shock_workload(nx=40), 0.01, 0, {}),
+    "double_mach_edge3_gauss": (lambda: double_mach_workload(n=12), 0.012, 0, {"edge_rule": 3, "time_rule": 1}),
+    "closed_box_edge3": (_closed_box_workload, 0.0, 5, {"edge_rule": 3}),
+}
+
+
+@pytest.mark.parametrize("case", list(BOUNDARY_CASES))
+def test_dot_product_with_walls_and_prescribed_states(case):
+    """The adjoint on meshes with reflective walls, prescribed inflow states
+    and the moving switch between two states, against the oracle's JVP of the
+    step from the same time."""
+    make, t0, pre, opts = BOUNDARY_CASES[case]
+    wl = make()
+    rng = np.random.default_rng(sum(map(ord, case)))
+    om = OracleMesh.from_workload(wl, **opts)
+    s0 = _perturbed(wl, rng)
+    if pre:
+        s0 = om.run(s0, om.max_dt(s0, 0.3), pre, t=t0)
+    dt = om.max_dt(s0, 0.3)
+    mesh = _mesh(wl, **opts)
+    for _ in range(3):
+        v = rng.normal(size=s0.shape)
+        lam = rng.normal(size=s0.shape)
+        _, jv = om.jvp(s0, v, dt, 1, t=t0)
+        import torch
+        w, g = mesh.to_device(s0)
+        lw, lg = mesh.to_device(lam)
+        ow, og = mesh.adjoint(w, g, lw, lg, dt, t=t0)
+        torch.cuda.synchronize()
+        vj = mesh.to_host(ow, og)
+        a, b = float(np.sum(vj * v)), float(np.sum(lam * jv))
+        scale = float(np.abs(vj * v).sum())
+        print(case, "<J^T l, v> =", a, "<l, J v> =", b, "rel", abs(a - b) / scale, flush=True)
+        assert abs(a - b) <= 1e-11 * scale
+
+
+def test_mixed_adjoint_with_walls_close_to_fp64():
+    import torch
+    wl = double_mach_workload(n=12)
+    rng = np.random.default_rng(23)
+    s0 = _perturbed(wl, rng)
+    dt = OracleMesh.from_workload(wl).max_dt(s0, 0.3)
+    lam = rng.normal(size=s0.shape)
+    out = []
+    for prec in ("fp64", "mixed"):
+        mesh = _mesh(wl, prec)
+        w, g = mesh.to_device(s0)
+        lw, lg = mesh.to_device(lam)
+        ow, og = mesh.adjoint(w, g, lw, lg, dt, t=0.012)
+        torch.cuda.synchronize()
+        out.append(mesh.to_host(ow, og))
+    err = float(np.abs(out[1][0] - out[0][0]).max() / np.abs(out[0][0]).max())
+    print("double Mach: mixed vs fp64 adjoint (Wbar block) rel max", err, flush=True)
+    assert err <= 1e-4
+
+
+def test_rollout_through_a_moving_boundary_against_the_oracle_jvp():
+    """The checkpointed rollout from t0 > 0 sets each step's time (the moving
+    switch) in the forward pass, the recomputation and the adjoints: the
+    gradient of <lam, s_n> equals the oracle's n-step JVP."""
+    import torch
+    from paper_2607_10809_amd.autograd import rollout
+    wl = double_mach_workload(n=12)
+    rng = np.random.default_rng(29)
+    om = OracleMesh.from_workload(wl)
+    s0 = _perturbed(wl, rng)
+    dt, n, t0 = om.max_dt(s0, 0.3), 6, 0.012
+    mesh = _mesh(wl)
+    lam = rng.normal(size=s0.shape)
+    w0, g0 = mesh.to_device(s0)
+    lw, lg = mesh.to_device(lam)
+    w = w0.clone().requires_grad_(True)
+    g = g0.clone().requires_grad_(True)
+    wT, gT = rollout(mesh, w, g, dt, n, ckpt=4, t0=t0)
+    ((wT * lw).sum() + (gT * lg).sum()).backward()
+    torch.cuda.synchronize()
+    grad = mesh.to_host(w.grad, g.grad)
+    for _ in range(2):
+        v = rng.normal(size=s0.shape)
+        _, jv = om.jvp(s0, v, dt, n, t=t0)
+        a, b = float(np.sum(grad * v)), float(np.sum(lam * jv))
+        scale = float(np.abs(grad * v).sum())
+        print("double Mach rollout from t0: <grad, v> =", a, "<l, J^n v> =", b, "rel", abs(a - b) / scale,
+              flush=True)
+        assert abs(a - b) <= 1e-10 * scale
 
 
 @pytest.mark.parametrize("time_rule,wd,er", [(1, 1.0, 2), (1, 0.3, 2), (0, 1.0, 3), (1, 0.3, 3)])
@@ -232,6 +346,27 @@ def test_kept_reconstruction_is_bitwise(case, precision):
     wo = raw[:8 * mesh.m * mesh.N].view(torch.float64).view(mesh.m, mesh.N)
     with pytest.raises(HweError):
         mesh.step(w, g, dt, out=(wo, torch.empty_like(g)), keep=Rbad)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_kept_reconstruction_with_a_moving_switch_is_bitwise(precision):
+    """The kept reconstruction of a step from t (moving boundary states at
+    t + dt/2) serves the adjoint of that step bitwise."""
+    import torch
+    rng = np.random.default_rng(37)
+    wl = double_mach_workload(n=12)
+    mesh = _mesh(wl, precision)
+    w, g = mesh.to_device(_perturbed(wl, rng))
+    lw, lg = mesh.to_device(rng.normal(size=wl.state0.shape))
+    dt, t = mesh.max_dt(w, wl.cfl), 0.012
+    a = mesh.step(w, g, dt, t=t)
+    R = mesh.empty_recon()
+    b = mesh.step(w, g, dt, keep=R, t=t)
+    x = mesh.adjoint(w, g, lw, lg, dt, t=t)
+    y = mesh.adjoint(w, g, lw, lg, dt, recon=R, t=t)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert torch.equal(x[0], y[0]) and torch.equal(x[1], y[1])
 
 
 def test_mixed_adjoint_close_to_fp64():

@@ -112,12 +112,8 @@ def test_uniform_state_prescribed_all_round(precision):
     assert np.abs(s[1:]).max() <= (1e-12 if precision == "fp64" else 1e-5)
 
 
-def test_face_kinds_on_the_device_handle_and_adjoint_refusal():
-    from paper_2607_10809_amd._lib import HweError
+def test_face_kinds_on_the_device_handle():
     wl = double_mach_workload(n=12)
     m = _mesh(wl)
     om = OracleMesh.from_workload(wl)
     assert np.array_equal(m.host_array(5).astype(np.int64), om.face_kinds()[m.perm].T)
-    w, g = m.to_device(wl.state0)
-    with pytest.raises(HweError):
-        m.adjoint(w, g, w.clone(), g.clone(), 1e-4)

@@ -149,11 +149,3 @@ def test_closed_box_conserves_mass_and_matches_the_oracle():
     assert np.isfinite(got).all()
     assert drift <= 1e-13 and e5 <= 1e-12 and e1 <= 1e-12
 
-
-def test_adjoint_rejects_wall_meshes():
-    from paper_2607_10809_amd._lib import HweError
-    wl = shock_tube_workload("sod", nx=20)
-    mesh = _mesh(wl)
-    w, g = mesh.to_device(wl.state0)
-    with pytest.raises(HweError):
-        mesh.adjoint(w, g, w.clone(), g.clone(), 1e-3)
