@@ -342,6 +342,12 @@ hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, voi
     set_error("null pointer");
     return HWE_EINVAL;
   }
+  const size_t N = size_t(m->h.N), mm = size_t(m->h.m);
+  if (overlaps(R_out, 6 * mm * N * real_size(m), wbar, mm * N * sizeof(double)) ||
+      overlaps(R_out, 6 * mm * N * real_size(m), grad, 2 * mm * N * real_size(m))) {
+    set_error("the output buffer overlaps the state");
+    return HWE_EINVAL;
+  }
   if ((s = set_dev(m)) != HWE_OK) return s;
   return launch_recon(m, wbar, grad, R_out, m->time, stream);
 }
