@@ -196,8 +196,10 @@ hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, doub
  * differentiated: a prescribed or moving boundary state is a constant of the
  * step (evaluated, as in hwe_step, at the time set by hwe_set_time + dt/2, so
  * set the time of step n before its adjoint), a reflective wall's exterior is
- * the mirrored interior.  Returns HWE_EINVAL for meshes built with
- * opts.positivity = 1 (the limiter is not differentiated). */
+ * the mirrored interior.  The scaling limiter (opts.positivity = 1) is
+ * differentiated on the branches the forward takes (the point of least
+ * density, the point whose pressure root sets the scale); its threshold
+ * eps = min(1e-13, rho_bar, p_bar) is a constant of the derivative. */
 hwe_status hwe_step_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n,
                             const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n,
                             void* lam_grad_n, double dt, void* stream);

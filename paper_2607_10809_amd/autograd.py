@@ -22,8 +22,6 @@ class Rollout(torch.autograd.Function):
     def forward(ctx, wbar0, grad0, mesh, dt, n_steps, ckpt, t0):
         if ckpt <= 0:
             raise ValueError("ckpt must be positive")
-        if mesh.opts.positivity:
-            raise ValueError("the positivity limiter is not differentiated; build the mesh without it")
         checkpoints = [(wbar0.detach().clone(), grad0.detach().clone())]
         cur = (checkpoints[0][0], checkpoints[0][1])
         bufs = [mesh.empty_state(), mesh.empty_state()]

@@ -271,12 +271,66 @@ __global__ __launch_bounds__(kBlock, sizeof(Real) == 4 ? 2 : 1) void adj_face_ke
 // One work-item per (cell, component q): the reverse of the reconstruction of
 // component q (Steps 1-6, with the nonlinear-weight derivatives) from the
 // coefficient adjoints the face kernel summed, into the cell's stencil slots.
-template <int EQ, class Real, bool SB>
+// The scaling limiter between the reconstruction and its adjoint (Euler): the
+// four component lanes of a cell (an aligned quad) share the unlimited
+// coefficients, the cell average and the adjoints of the scales, and each
+// lane keeps its component of the limiter's reverse.  The limited
+// coefficients are theta_q a_q; so la_q <- theta_q la_q + (dtheta/da)^T lth.
+template <class Real, int NPT> struct ScalingLimiterRev {
+  int lane0, q, N, i;
+  double gam, W0;
+  const double* gpc;
+  __device__ __forceinline__ void operator()(const Real (&au)[6], const Real (&la)[6], Real (&lae)[6],
+                                             double& lW0) const {
+    Real all[4][6];
+    double Wb[4], lth[4];
+    double lthq = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) lthq += double(au[j]) * double(la[j]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) all[c][j] = __shfl(au[j], lane0 + c);
+      Wb[c] = __shfl(W0, lane0 + c);
+      lth[c] = __shfl(lthq, lane0 + c);
+    }
+    double px[NPT], py[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      px[k] = gpc[(2 * k) * size_t(N) + i];
+      py[k] = gpc[(2 * k + 1) * size_t(N) + i];
+    }
+    double th[4];
+    positivity_theta<Real, NPT>(gam, Wb, all, px, py, th);
+    double lall[4][6], lWb[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) lall[c][j] = 0.0;
+    positivity_theta_rev<Real, NPT>(gam, Wb, all, px, py, lth, lall, lWb);
+    const Real tq = Real(q == 0 ? th[0] : (q == 1 ? th[1] : (q == 2 ? th[2] : th[3])));
+    double lq[6] = {lall[0][0], lall[0][1], lall[0][2], lall[0][3], lall[0][4], lall[0][5]};
+    double lw = lWb[0];
+#pragma unroll
+    for (int c = 1; c < 4; ++c) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) lq[j] = q == c ? lall[c][j] : lq[j];
+      lw = q == c ? lWb[c] : lw;
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) lae[j] = tq * la[j] + Real(lq[j]);
+    lW0 = lw;
+  }
+};
+
+// NPT: the limiter's points per cell (0: no limiter, 6, or 9 with the
+// 3-point edge rule).
+template <int EQ, class Real, bool SB, int NPT>
 __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
     int N, int NB, Params P, const double* __restrict__ wbar, const Real* __restrict__ grad,
     const int32_t* __restrict__ nbr, const double* __restrict__ bnd_n, const Real* __restrict__ tbl,
-    const double* __restrict__ area, const Real* __restrict__ lacell, const double* __restrict__ lwcell,
-    double* __restrict__ slots) {
+    const double* __restrict__ area, const double* __restrict__ gpc, const Real* __restrict__ lacell,
+    const double* __restrict__ lwcell, double* __restrict__ slots) {
   constexpr int M = NComp<EQ>::m;
   const int blk = xcd_block_id();
   const int gid = blk * kBlock + threadIdx.x;
@@ -298,8 +352,13 @@ __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
     __syncthreads();
     if (i >= N) return;  // whole cells: the four lanes of a quad leave together
     double cross[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, reinterpret_cast<const Real*>(stage) + (i % kTile), area, laq, slot,
-                            q, N, wbar, grad, cross);
+    const Real* tb = reinterpret_cast<const Real*>(stage) + (i % kTile);
+    if constexpr (NPT > 0) {
+      const ScalingLimiterRev<Real, NPT> lim{int(threadIdx.x & 63) & ~3, q, N, i, P.gam, S.W0, gpc};
+      recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tb, area, laq, slot, q, N, wbar, grad, cross, lim);
+    } else {
+      recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tb, area, laq, slot, q, N, wbar, grad, cross);
+    }
     if constexpr (SB) {
       // wall ghosts: the momentum lanes (q = 1, 2 of the quad) exchange the
       // terms each produced for the other's component
@@ -454,12 +513,31 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
     HWE_ADJ_CELL(0, 2);
   }
 #undef HWE_ADJ_CELL
-  if (sb)
-    hipLaunchKernelGGL((adj_recon_kernel<EQ, Real, true>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0,
-                       st, N, NB, P, wbar, grad, d.nbr, d.bnd_n, tbl, d.area, lacell, d.lwcell, d.slots);
-  else
-    hipLaunchKernelGGL((adj_recon_kernel<EQ, Real, false>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0,
-                       st, N, NB, P, wbar, grad, d.nbr, d.bnd_n, tbl, d.area, lacell, d.lwcell, d.slots);
+  const dim3 rgrid(grid_for(int64_t(N) * NComp<EQ>::m));
+#define HWE_ADJ_RECON(SBV, NPTV)                                                                                    \
+  hipLaunchKernelGGL((adj_recon_kernel<EQ, Real, SBV, NPTV>), rgrid, dim3(kBlock), 0, st, N, NB, P, wbar, grad,     \
+                     d.nbr, d.bnd_n, tbl, d.area, d.gpc, lacell, d.lwcell, d.slots)
+  const int npt = (EQ == EQ_EUL && P.positivity) ? (M->opts.edge_rule == 3 ? 9 : 6) : 0;
+  if constexpr (EQ == EQ_EUL) {
+    if (npt == 6) {
+      if (sb)
+        HWE_ADJ_RECON(true, 6);
+      else
+        HWE_ADJ_RECON(false, 6);
+    } else if (npt == 9) {
+      if (sb)
+        HWE_ADJ_RECON(true, 9);
+      else
+        HWE_ADJ_RECON(false, 9);
+    }
+  }
+  if (npt == 0) {
+    if (sb)
+      HWE_ADJ_RECON(true, 0);
+    else
+      HWE_ADJ_RECON(false, 0);
+  }
+#undef HWE_ADJ_RECON
   hipLaunchKernelGGL((adj_gather_kernel<EQ, Real>), dim3(grid_for(int64_t(N) * NComp<EQ>::m)), dim3(kBlock), 0, st, N, E, P, dt, wbar, lw, lg,
                      d.nbr, d.nbr_back, d.cell_edge, d.enl, d.inv_area, nl, d.slots, d.sface, lw_out, lg_out);
   hipError_t err = hipGetLastError();

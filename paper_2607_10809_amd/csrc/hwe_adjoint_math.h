@@ -554,6 +554,160 @@ __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double d
   }
 }
 
+// ------------------------------------------------------------------ limiter
+// Reverse of positivity_theta (FP64), on the branches the forward takes: the
+// density scale through the point of least density, the pressure scale t
+// through the point whose root was taken (the quadratic's root formula
+// reversed).  The threshold eps = min(1e-13, rho_bar, p_bar) is a constant of
+// the derivative.  lth: adjoints of theta[0..3]; accumulates the adjoints of
+// the unlimited coefficients a[4][6] (la) and of the cell average Wb (lWb).
+template <class Real, int NP>
+__host__ __device__ __forceinline__ void positivity_theta_rev(double gam, const double (&Wb)[4],
+                                                             const Real (&a)[4][6], const double (&px)[NP],
+                                                             const double (&py)[NP], const double (&lth)[4],
+                                                             double (&la)[4][6], double (&lWb)[4]) {
+  // ---- forward, recording the branches
+  const double gm1 = gam - 1.0;
+  const double pbar = gm1 * (Wb[3] - 0.5 * (Wb[1] * Wb[1] + Wb[2] * Wb[2]) / Wb[0]);
+  const double eps = fmin(1e-13, fmin(Wb[0], pbar));
+  double d[NP][4];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const double X = px[k], Y = py[k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      d[k][q] = double(a[q][0]) + double(a[q][1]) * X + double(a[q][2]) * Y + double(a[q][3]) * X * X +
+                double(a[q][4]) * X * Y + double(a[q][5]) * Y * Y;
+  }
+  double rmin = 1e300;
+  int kmin = 0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const double r = Wb[0] + d[k][0];
+    if (r < rmin) {
+      rmin = r;
+      kmin = k;
+    }
+  }
+  const bool rho_on = rmin < eps;
+  const double th_rho = rho_on ? (Wb[0] - eps) / (Wb[0] - rmin) : 1.0;
+  const double Ep = Wb[3] - eps / gm1;
+  const double C = 2.0 * Wb[0] * Ep - (Wb[1] * Wb[1] + Wb[2] * Wb[2]);
+  double t = 1.0;
+  int kt = -1;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const double dr = th_rho * d[k][0], d1 = d[k][1], d2 = d[k][2], dE = d[k][3];
+    const double r = Wb[0] + dr, m1 = Wb[1] + d1, m2 = Wb[2] + d2, En = Wb[3] + dE;
+    const double p = gm1 * (En - 0.5 * (m1 * m1 + m2 * m2) / r);
+    if (!(p < eps)) continue;
+    const double A = 2.0 * dr * dE - (d1 * d1 + d2 * d2);
+    const double B = 2.0 * (Ep * dr + Wb[0] * dE) - 2.0 * (Wb[1] * d1 + Wb[2] * d2);
+    double root;
+    if (A == 0.0) {
+      root = -C / B;
+    } else {
+      const double disc = fmax(B * B - 4.0 * A * C, 0.0);
+      const double sq = sqrt(disc);
+      const double qq = B >= 0.0 ? -0.5 * (B + sq) : -0.5 * (B - sq);
+      const double r1 = qq / A, r2 = C / qq;
+      const bool ok1 = r1 >= 0.0 && r1 <= 1.0, ok2 = r2 >= 0.0 && r2 <= 1.0;
+      root = (ok1 && ok2) ? (r1 <= r2 ? r1 : r2) : (ok1 ? r1 : r2);
+    }
+    if (root < t) {
+      t = root;
+      kt = k;
+    }
+  }
+  // ---- reverse: theta[0] = th_rho t, theta[1..3] = t
+  const double lt = lth[0] * th_rho + lth[1] + lth[2] + lth[3];
+  double lthr = lth[0] * t;
+  double ld[NP][4];
+#pragma unroll
+  for (int k = 0; k < NP; ++k)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ld[k][q] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    if (k != kt) continue;
+    const double d0 = d[k][0], dr = th_rho * d0, d1 = d[k][1], d2 = d[k][2], dE = d[k][3];
+    const double A = 2.0 * dr * dE - (d1 * d1 + d2 * d2);
+    const double B = 2.0 * (Ep * dr + Wb[0] * dE) - 2.0 * (Wb[1] * d1 + Wb[2] * d2);
+    double lA = 0.0, lB = 0.0, lC = 0.0;
+    if (A == 0.0) {
+      lC = -lt / B;
+      lB = C / (B * B) * lt;
+    } else {
+      const double disc0 = B * B - 4.0 * A * C;
+      const double disc = fmax(disc0, 0.0);
+      const double sq = sqrt(disc);
+      const double qq = B >= 0.0 ? -0.5 * (B + sq) : -0.5 * (B - sq);
+      const double r1 = qq / A, r2 = C / qq;
+      const bool ok1 = r1 >= 0.0 && r1 <= 1.0, ok2 = r2 >= 0.0 && r2 <= 1.0;
+      const bool first = (ok1 && ok2) ? (r1 <= r2) : ok1;
+      double lqq;
+      if (first) {
+        lqq = lt / A;
+        lA = -qq / (A * A) * lt;
+      } else {
+        lC = lt / qq;
+        lqq = -C / (qq * qq) * lt;
+      }
+      lB += -0.5 * lqq;
+      const double lsq = (B >= 0.0 ? -0.5 : 0.5) * lqq;
+      const double ldisc = (disc0 > 0.0 && sq > 0.0) ? lsq / (2.0 * sq) : 0.0;
+      lB += 2.0 * B * ldisc;
+      lA += -4.0 * C * ldisc;
+      lC += -4.0 * A * ldisc;
+    }
+    const double ldr = 2.0 * dE * lA + 2.0 * Ep * lB;
+    ld[k][3] += 2.0 * dr * lA + 2.0 * Wb[0] * lB;
+    ld[k][1] += -2.0 * d1 * lA - 2.0 * Wb[1] * lB;
+    ld[k][2] += -2.0 * d2 * lA - 2.0 * Wb[2] * lB;
+    const double lEp = 2.0 * dr * lB + 2.0 * Wb[0] * lC;
+    lWb[0] += 2.0 * dE * lB + 2.0 * Ep * lC;
+    lWb[1] += -2.0 * d1 * lB - 2.0 * Wb[1] * lC;
+    lWb[2] += -2.0 * d2 * lB - 2.0 * Wb[2] * lC;
+    lthr += d0 * ldr;
+    ld[k][0] += th_rho * ldr;
+    lWb[3] += lEp;
+  }
+  if (rho_on) {
+    const double den = Wb[0] - rmin;
+    const double lrmin = lthr * (Wb[0] - eps) / (den * den);
+    lWb[0] += lthr / den - lrmin;
+    lWb[0] += lrmin;
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+      if (k == kmin) ld[k][0] += lrmin;
+  }
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const double X = px[k], Y = py[k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      la[q][0] += ld[k][q];
+      la[q][1] += ld[k][q] * X;
+      la[q][2] += ld[k][q] * Y;
+      la[q][3] += ld[k][q] * X * X;
+      la[q][4] += ld[k][q] * X * Y;
+      la[q][5] += ld[k][q] * Y * Y;
+    }
+  }
+}
+
+// The reconstruction reverse without a limiter: the coefficients' adjoint
+// passes through unchanged.
+struct NoLimiter {
+  template <class Real>
+  __host__ __device__ __forceinline__ void operator()(const Real (&)[6], const Real (&la)[6], Real (&lae)[6],
+                                                      double& lW0) const {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) lae[j] = la[j];
+    lW0 = 0.0;
+  }
+};
+
 // ------------------------------------------------------------------ recon
 // Reverse of recon_coeffs for component q of cell i: given the adjoint la[6]
 // of the coefficients, write the adjoints of the stencil inputs into
@@ -566,14 +720,14 @@ __host__ __device__ __forceinline__ void edge_lane_rev(const Params& P, double d
 // cell's two momentum components, and cross[c][field] (c = 0, 1: momentum
 // components 1, 2) receives those terms of slot 0 for the kernel to exchange
 // between the component lanes.  wbar, grad, N: the cell's other components.
-template <int EQ, class Real, bool SB = false>
+template <int EQ, class Real, bool SB = false, class Lim = NoLimiter>
 __host__ __device__ __forceinline__ void recon_rev(int i, int NB, const Params& P, const Stencil<Real>& S,
                                                   const double* __restrict__ bnd_n, const Real* __restrict__ tb,
-                                                  const double* __restrict__ area, const Real (&la)[6],
+                                                  const double* __restrict__ area, const Real (&la_in)[6],
                                                   double (&slot)[4][3], int q = 0, int N = 0,
                                                   const double* __restrict__ wbar = nullptr,
                                                   const Real* __restrict__ grad = nullptr,
-                                                  double (*cross)[3] = nullptr) {
+                                                  double (*cross)[3] = nullptr, const Lim& lim = Lim()) {
   // ---- forward recomputation from the gathered stencil (gather_stencil)
   const double W0 = S.W0;
   double Wsum = W0, dW[3];
@@ -696,8 +850,23 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int NB, const Params& 
   Real kl[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) kl[f] = Real(w[f + 1] - w[0] * P.lw[f + 1] / g1);
-  // ---- reverse
   const Real mxx = tb[kTblMom * kTile], mxy = tb[(kTblMom + 1) * kTile], myy = tb[(kTblMom + 2) * kTile];
+  // the limiter (if any) between the coefficients and their adjoint: the
+  // unlimited coefficients as the forward forms them (Step 6)
+  Real la[6];
+  double lW0lim;
+  {
+    Real R1 = k1 * c[0], R2 = k1 * c[1];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      R1 += kl[f] * bl[f];
+      R2 += kl[f] * cl[f];
+    }
+    const Real R3 = k1 * c[2], R4 = k1 * c[3], R5 = k1 * c[4];
+    const Real au[6] = {-(R3 * mxx + R4 * mxy + R5 * myy), R1, R2, R3, R4, R5};
+    lim(au, la_in, la, lW0lim);
+  }
+  // ---- reverse
   const Real lR1 = la[1], lR2 = la[2];
   const Real lR3 = la[3] - mxx * la[0], lR4 = la[4] - mxy * la[0], lR5 = la[5] - myy * la[0];
   Real lc[5];
@@ -789,7 +958,7 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int NB, const Params& 
   }
   // stencil inputs -> slots
   for (int s = 0; s < 4; ++s) slot[s][0] = slot[s][1] = slot[s][2] = 0.0;
-  slot[0][0] += lWsum;
+  slot[0][0] += lWsum + lW0lim;
   slot[0][1] += double(lV[0]);
   slot[0][2] += double(lY[0]);
 #pragma unroll

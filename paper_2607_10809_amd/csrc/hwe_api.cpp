@@ -267,10 +267,6 @@ hwe_status check_adjoint(hwe_mesh m, const double* wbar_n, const void* grad_n, c
     set_error("output buffers overlap each other");
     return HWE_EINVAL;
   }
-  if (m->opts.positivity) {
-    set_error("hwe_step_adjoint: the positivity limiter is not differentiated");
-    return HWE_EINVAL;
-  }
   return set_dev(m);
 }
 
