@@ -304,10 +304,11 @@ def test_checkpointing_does_not_change_the_gradient():
     w0, g0 = mesh.to_device(wl.state0)
     dt = mesh.max_dt(w0, wl.cfl)
     grads = []
-    for ck in (1, 7, 40):
+    # checkpoint intervals, with and without the recomputation overlapping the adjoints
+    for ck, overlap in ((1, True), (7, True), (7, False), (40, True)):
         w = w0.clone().requires_grad_(True)
         g = g0.clone().requires_grad_(True)
-        wT, gT = rollout(mesh, w, g, dt, 40, ckpt=ck)
+        wT, gT = rollout(mesh, w, g, dt, 40, ckpt=ck, overlap=overlap)
         (wT[0] ** 2).sum().backward()
         torch.cuda.synchronize()
         grads.append((w.grad.clone(), g.grad.clone()))
