@@ -347,6 +347,8 @@ def main():
     ap.add_argument("--forward-only", action="store_true",
                     help="skip the adjoint, copy and 980,000-triangle legs (for counter runs)")
     ap.add_argument("--no-c4", action="store_true", help="skip the 980,000-triangle Riemann leg")
+    ap.add_argument("--no-error", action="store_true",
+                    help="skip the run of both precisions to the vortex's final time (mixed-vs-FP64 error)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 20 device copies of 256 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -379,8 +381,9 @@ def main():
     log(f"mixed: {mix['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {mix['kernel_ms']}")
     adj = adjm = c4 = copy_gbps = merr = None
     if not args.forward_only:
-        log("mixed vs FP64 at T ...")
-        merr = mixed_error_leg(wl)
+        if not args.no_error:
+            log("mixed vs FP64 at T ...")
+            merr = mixed_error_leg(wl)
         if not args.no_c4:
             log("980,000-triangle Riemann leg ...")
             c4 = c4_leg(200, 10)
