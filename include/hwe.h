@@ -121,8 +121,7 @@ typedef struct {
                              the exterior value at a wall Gauss point is the
                              interior value with its momentum reflected.  Other
                              boundary faces stay transmissive.  0 = no walls
-                             (default).  hwe_step_adjoint rejects meshes with
-                             walls */
+                             (default) */
   int32_t n_regions;      /* HWE_BC_TRANSMISSIVE only: 0..HWE_MAX_REGIONS.  Each
                              boundary face takes the kind of the first region
                              that holds its midpoint (within 1e-9 of the box
