@@ -24,7 +24,7 @@ sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 from oracle import OracleMesh  # noqa: E402
 from workloads import (advection_workload, burgers_workload, fd_directions, make_vortex,  # noqa: E402
-                       cell_average_states, double_mach_workload, moving_shock_workload,
+                       cell_average_states, double_mach_workload, moving_shock_workload, near_vacuum_state,
                        perturbed_vortex_target_center, riemann_workload, shock_tube_workload, shu_osher_workload,
                        split_square_mesh, vortex_workload, wedge_workload)
 from workloads.problems import Workload  # noqa: E402
@@ -391,25 +391,6 @@ EDGE_POINTS = {2: (0.5 - np.sqrt(3.0) / 6.0, 0.5 + np.sqrt(3.0) / 6.0),
                3: (0.5 - np.sqrt(15.0) / 10.0, 0.5, 0.5 + np.sqrt(15.0) / 10.0)}
 
 
-def _limiter_data(wl, seed, branch):
-    """The workload's data with its low-density part thinned a thousandfold and
-    seeded derivative averages of the size of the averages over a cell, so
-    that the scaling limiter acts.  branch "pressure": small density
-    derivative averages (only the pressure scaling acts, on hundreds of
-    cells); "density": the gas at rest with small energy derivative averages
-    (only the density scaling acts)."""
-    s = wl.state0.copy()
-    low = s[0, 0] < 0.2 * s[0, 0].max()
-    s[:, :, low] *= 1e-3
-    if branch == "density":
-        s[:, 1:3] = 0.0
-    rng = np.random.default_rng(seed)
-    g = rng.normal(size=s[1:].shape) * np.abs(s[0])[None] / wl.mesh.h
-    scales = (0.05, 1.0, 1.0, 1.0) if branch == "pressure" else (1.0, 0.0, 0.0, 0.05)
-    s[1:] = g * np.asarray(scales)[None, :, None]
-    return s
-
-
 def _touching_cells(om, s, rule):
     """Cells scaled for their density, and for each the cell itself and the
     neighbour across the face of its least-density point: there the limited
@@ -454,7 +435,7 @@ def test_dot_product_with_the_scaling_limiter(case):
     make, seed, branch, opts = LIMITER_CASES[case]
     wl = make()
     om = OracleMesh.from_workload(wl, positivity=1, **opts)
-    s0 = _limiter_data(wl, seed, branch)
+    s0 = near_vacuum_state(wl, seed, branch)
     mask = np.ones(om.N)
     if branch == "density":
         nlim, touch = _touching_cells(om, s0, opts.get("edge_rule", 2))

@@ -588,3 +588,29 @@ def random_state(m, N, seed, scale=1.0, base=1.0):
     s[0] = base + 0.1 * scale * rng.uniform(-1.0, 1.0, size=(m, N))
     s[1:] = scale * rng.uniform(-1.0, 1.0, size=(2, m, N))
     return s
+
+
+def near_vacuum_state(wl: Workload, seed, branch="pressure", untie=False):
+    """Data on which the positivity (scaling) limiter acts: the workload's cell
+    averages with the part below a fifth of the largest density thinned a
+    thousandfold, and seeded derivative averages of the size of the averages
+    over a cell.  branch "pressure": small density derivative averages, so
+    that only the pressure scaling acts (on hundreds of cells of the
+    four-quadrant data); "density": the gas at rest with small energy
+    derivative averages, so that only the density scaling acts.  untie:
+    also perturb the averages (momentum additively) so that no two
+    neighbouring cells are equal and no gas is exactly at rest (piecewise
+    constant data sit on the ties of the flux viscosity's max and of |u.n|)."""
+    s = wl.state0.copy()
+    low = s[0, 0] < 0.2 * s[0, 0].max()
+    s[:, :, low] *= 1e-3
+    if branch == "density":
+        s[:, 1:3] = 0.0
+    rng = np.random.default_rng(seed)
+    g = rng.normal(size=s[1:].shape) * np.abs(s[0])[None] / wl.mesh.h
+    scales = (0.05, 1.0, 1.0, 1.0) if branch == "pressure" else (1.0, 0.0, 0.0, 0.05)
+    s[1:] = g * np.asarray(scales)[None, :, None]
+    if untie:
+        s[0] *= 1.0 + 1e-3 * rng.uniform(-1.0, 1.0, s[0].shape)
+        s[0, 1:3] += 1e-2 * np.abs(s[0, 0]) * rng.uniform(-1.0, 1.0, s[0, 1:3].shape)
+    return s
