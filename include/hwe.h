@@ -26,8 +26,16 @@
  *      grad : [2][m][N]              averages of W_x, then W_y  (eq. (aver))
  *             double for HWE_FP64, float for HWE_MIXED
  *    m = 1 (advection, Burgers) or 4 (Euler: rho, rho u, rho v, E).
- *  - A mesh handle owns device scratch; one handle must not be used by two
- *    streams at once (calls on one handle serialise on the stream given).
+ *  - A mesh handle owns device scratch, and two calls that use the same
+ *    scratch must not overlap in time (on one stream they serialise by
+ *    themselves).  The scratch sets: hwe_step and hwe_step_keep use the edge
+ *    fluxes (hwe_step also the reconstruction); hwe_step_adjoint and
+ *    hwe_step_adjoint_kept use the adjoint records (hwe_step_adjoint also the
+ *    reconstruction); hwe_max_dt and hwe_check_state one reduction buffer
+ *    each.  So hwe_step_keep on one stream may overlap hwe_step_adjoint_kept
+ *    on another (a checkpointed reverse sweep recomputes the next segment
+ *    beside the current one's adjoints), while two steps, or two adjoints,
+ *    may not.  The profiling events (hwe_profile_begin) assume one stream.
  *  - Memory given by the caller is never freed or reallocated by the library.
  */
 #ifndef HWE_H
