@@ -402,20 +402,65 @@ __global__ __launch_bounds__(kBlock) void adj_gather_kernel(
   const int i = gid / M, q = gid - (gid / M) * M;
   if (i >= N) return;
   const size_t sN = size_t(N), sE = size_t(E);
+  // per face: neighbour, back-slot, edge and side, n|e| of the cell's face,
+  // the edge normal and length, and the two sides' point sums of the face
+  // kernel; per component: the cell's average and its adjoint
   int nbf[3], bkf[3], cef[3];
+  double nlxf[3], nlyf[3], nxf[3], nyf[3], lenf[3], sownf[3], sothf[3];
+  double WK[M], lwK[M];
+  if constexpr (M == 4) {
+    // the quad's four lanes are the cell's components: a value the whole quad
+    // needs is loaded once (lane f for face f) and broadcast by DPP
+    const int fq = q < 3 ? q : 0;
+    const int nb_l = nbr[fq * sN + i], bk_l = nbr_back[fq * sN + i], ce_l = cell_edge[fq * sN + i];
+    const bool has_l = nb_l >= 0;
+    const int e_l = ce_l >> 1;
+    const double nlx_l = double(nl[fq * sN + i]), nly_l = double(nl[(3 + fq) * sN + i]);
+    const double nx_l = enl[e_l], ny_l = enl[sE + e_l], len_l = enl[2 * sE + e_l];
+    const double so_l = sface[fq * sN + i];
+    const double st_l = sface[(has_l ? bk_l : 0) * sN + (has_l ? nb_l : i)];
+    const double WKq = wbar[q * sN + i], lwKq = lw[q * sN + i];
 #pragma unroll
-  for (int f = 0; f < 3; ++f) {
-    nbf[f] = nbr[f * sN + i];
-    bkf[f] = nbr_back[f * sN + i];
-    cef[f] = cell_edge[f * sN + i];
+    for (int f = 0; f < 3; ++f) {
+      nbf[f] = quad_bcast(nb_l, f);
+      bkf[f] = quad_bcast(bk_l, f);
+      cef[f] = quad_bcast(ce_l, f);
+      nlxf[f] = quad_bcast(nlx_l, f);
+      nlyf[f] = quad_bcast(nly_l, f);
+      nxf[f] = quad_bcast(nx_l, f);
+      nyf[f] = quad_bcast(ny_l, f);
+      lenf[f] = quad_bcast(len_l, f);
+      sownf[f] = quad_bcast(so_l, f);
+      sothf[f] = quad_bcast(st_l, f);
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      WK[c] = quad_bcast(WKq, c);
+      lwK[c] = quad_bcast(lwKq, c);
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      nbf[f] = nbr[f * sN + i];
+      bkf[f] = nbr_back[f * sN + i];
+      cef[f] = cell_edge[f * sN + i];
+      const bool has = nbf[f] >= 0;
+      const int e = cef[f] >> 1;
+      nlxf[f] = double(nl[f * sN + i]);
+      nlyf[f] = double(nl[(3 + f) * sN + i]);
+      nxf[f] = enl[e];
+      nyf[f] = enl[sE + e];
+      lenf[f] = enl[2 * sE + e];
+      sownf[f] = sface[f * sN + i];
+      sothf[f] = sface[(has ? bkf[f] : 0) * sN + (has ? nbf[f] : i)];
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      WK[c] = wbar[c * sN + i];
+      lwK[c] = lw[c * sN + i];
+    }
   }
   const double iaK = inv_area[i];
-  double WK[M], lwK[M];
-#pragma unroll
-  for (int c = 0; c < M; ++c) {
-    WK[c] = wbar[c * sN + i];
-    lwK[c] = lw[c * sN + i];
-  }
   const double lgxK = double(lg[q * sN + i]), lgyK = double(lg[(M + q) * sN + i]);
   double aW = slots[slot_index<M>(i, 0, 0, q)];
   double aV = slots[slot_index<M>(i, 0, 1, q)];
@@ -428,21 +473,30 @@ __global__ __launch_bounds__(kBlock) void adj_gather_kernel(
     const bool has = nbf[f] >= 0;
     const int nb = has ? nbf[f] : i;
     const int bk = has ? bkf[f] : 0;
-    const int e = cef[f] >> 1, side = cef[f] & 1;
+    const int side = cef[f] & 1;
     const double sW = slots[slot_index<M>(nb, 1 + bk, 0, q)];
     const double sV = slots[slot_index<M>(nb, 1 + bk, 1, q)];
     const double sY = slots[slot_index<M>(nb, 1 + bk, 2, q)];
     double Wn[M], lwn[M];
+    if constexpr (M == 4) {
+      const double Wq = wbar[q * sN + nb], lwq = lw[q * sN + nb];
 #pragma unroll
-    for (int c = 0; c < M; ++c) {
-      Wn[c] = wbar[c * sN + nb];
-      lwn[c] = lw[c * sN + nb];
+      for (int c = 0; c < M; ++c) {
+        Wn[c] = quad_bcast(Wq, c);
+        lwn[c] = quad_bcast(lwq, c);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        Wn[c] = wbar[c * sN + nb];
+        lwn[c] = lw[c * sN + nb];
+      }
     }
     const double lgxn = double(lg[q * sN + nb]), lgyn = double(lg[(M + q) * sN + nb]);
     const double ian = inv_area[nb];
-    const double nlx = double(nl[f * sN + i]), nly = double(nl[(3 + f) * sN + i]);
-    const double nx = enl[e], ny = enl[sE + e], len = enl[2 * sE + e];
-    const double sown = sface[f * sN + i], soth = sface[bk * sN + nb];
+    const double nlx = nlxf[f], nly = nlyf[f];
+    const double nx = nxf[f], ny = nyf[f], len = lenf[f];
+    const double sown = sownf[f], soth = sothf[f];
     // every value feeds a select, so no load waits behind a branch
     // Green-Gauss: |K| Vbar_K includes n|e| (Wbar_nb - Wbar_K)/2 (and the neighbour the mirror term)
     const double gg = -0.5 * (nlx * (iaK * lgxK + ian * lgxn) + nly * (iaK * lgyK + ian * lgyn));

@@ -46,6 +46,15 @@ template <int CTRL> __device__ __forceinline__ double quad_perm(double v) {
   const int lo = quad_perm<CTRL>(__double2loint(v)), hi = quad_perm<CTRL>(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
+// The value of lane c (0..3) of each aligned quad, in every lane of the quad.
+template <class T> __device__ __forceinline__ T quad_bcast(T v, int c) {
+  switch (c) {
+    case 0: return quad_perm<0x00>(v);
+    case 1: return quad_perm<0x55>(v);
+    case 2: return quad_perm<0xAA>(v);
+    default: return quad_perm<0xFF>(v);
+  }
+}
 
 // Per-cell reconstruction tables, tiled: cells are grouped in tiles of kTile
 // consecutive cells; a tile stores kTblRows rows of kTile values (row-major),
