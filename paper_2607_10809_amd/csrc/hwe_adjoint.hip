@@ -21,6 +21,11 @@
 //      neighbours wrote for it, the Green-Gauss terms of the derivative
 //      averages and the derivative of the flux viscosity alpha (only on the
 //      cell whose spectral radius the max selected).
+// Meshes with reflective walls or prescribed boundary states run the face and
+// reconstruction reverses instantiated with SB = true (a boundary face's
+// flux, interface value, alpha and Green-Gauss terms, all local to its cell,
+// are reversed by the face kernel); the scaling limiter is reversed inside
+// the reconstruction reverse (template NPT = its points per cell).
 #include <hip/hip_runtime.h>
 
 #include "hwe_adjoint_math.h"
