@@ -243,7 +243,7 @@ hwe_status hwe_step_adjoint_kept(hwe_mesh m, const double* wbar_n, const void* g
  * taken when a step is launched. */
 hwe_status hwe_set_time(hwe_mesh m, double t);
 
-/* Largest stable step of the driver: dt = cfl * min_K r_K / max_K lambda_K
+/* Largest stable step of the time loop: dt = cfl * min_K r_K / max_K lambda_K
  * (r_K inradius, lambda_K the largest signal speed at the cell average).
  * Writes one double to device memory dt_dev. */
 hwe_status hwe_max_dt(hwe_mesh m, const double* wbar, double cfl, double* dt_dev, void* stream);

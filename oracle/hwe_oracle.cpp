@@ -1225,7 +1225,7 @@ int or_llf(const or_opts* oo, const double* Wi, const double* We, double nx, dou
   return 0;
 }
 
-// Time step of the driver: cfl * min_K r_K / max_K lambda_K, with r_K the
+// Time step of the time loop: cfl * min_K r_K / max_K lambda_K, with r_K the
 // inradius and lambda_K the largest signal speed over all directions at the
 // cell average.
 double or_max_dt(void* h, const double* s, double cfl) {
