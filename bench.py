@@ -297,6 +297,41 @@ def cpu_leg(wl, budget_s=12.0, budget_1t_s=5.0):
                 cpu_model=cpu_model())
 
 
+def small_configs_leg(steps=500, warmup=20):
+    """Throughput of the two small configurations: linear advection on 800
+    triangles (C1; launch-bound) and Burgers on 51,200 jittered triangles (C2),
+    each precision, as HIP-graph replays of the step."""
+    import torch
+    from paper_2607_10809_amd.hwe import Mesh
+    from workloads import advection_workload, burgers_workload
+    out = {}
+    for name, wl in (("advection_800", advection_workload()), ("burgers_51200", burgers_workload())):
+        res = {"triangles": wl.mesh.n_cells}
+        for prec in ("fp64", "mixed"):
+            mesh = Mesh.from_workload(wl, precision=prec)
+            w0, g0 = mesh.to_device(wl.state0)
+            dt = mesh.max_dt(w0, wl.cfl)
+            a, b = (w0.clone(), g0.clone()), mesh.empty_state()
+            for _ in range(warmup // 2):
+                mesh.step(a[0], a[1], dt, out=b)
+                mesh.step(b[0], b[1], dt, out=a)
+            graph = mesh.capture_steps(a, b, dt, 100)
+            graph.replay()
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(steps // 100):
+                graph.replay()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / (steps // 100 * 100)
+            res[prec] = {"value": mesh.N / (ms * 1e-3), "us_per_step": round(ms * 1e3, 2)}
+            del graph, mesh
+        out[name] = res
+    return out
+
+
 def c4_leg(steps, warmup):
     """Throughput on the 980,000-triangle Riemann problem (positivity limiter on):
     its step moves ~1 GB in FP64, far more than the 256 MB Infinity Cache."""
@@ -346,7 +381,8 @@ def main():
     ap.add_argument("--n", type=int, default=320, help="squares per side (default: 320 -> 204,800 triangles)")
     ap.add_argument("--forward-only", action="store_true",
                     help="skip the adjoint, copy and 980,000-triangle legs (for counter runs)")
-    ap.add_argument("--no-c4", action="store_true", help="skip the 980,000-triangle Riemann leg")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the 980,000-triangle Riemann leg and the two small configurations")
     ap.add_argument("--no-error", action="store_true",
                     help="skip the run of both precisions to the vortex's final time (mixed-vs-FP64 error)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -379,7 +415,7 @@ def main():
     log(f"FP64: {f64['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {f64['kernel_ms']}")
     mix = gpu_leg(wl, args.steps, args.warmup, "mixed")
     log(f"mixed: {mix['ms'] / args.steps * 1e3:.1f} us/step; kernels (ms) {mix['kernel_ms']}")
-    adj = adjm = c4 = copy_gbps = merr = None
+    adj = adjm = c4 = copy_gbps = merr = small = None
     if not args.forward_only:
         if not args.no_error:
             log("mixed vs FP64 at T ...")
@@ -387,6 +423,7 @@ def main():
         if not args.no_c4:
             log("980,000-triangle Riemann leg ...")
             c4 = c4_leg(200, 10)
+            small = small_configs_leg()
         copy_gbps = copy_bandwidth()
         adj = adjoint_leg(wl)
         log(f"adjoint (FP64, 200 steps, checkpoint 20): forward {adj['forward_ms']:.1f} ms, backward "
@@ -464,6 +501,7 @@ def main():
         "roofline": roofline,
         "state_flags": {"fp64": f64["flags"], "mixed": mix["flags"]},
         "riemann_980k": c4,
+        "small_configs": small,
         "hip_graph": {"steps_per_graph": f64["graph_chunk"],
                       "eager_ms_per_step": {"fp64": round(f64["ms_eager"] / args.steps, 5),
                                             "mixed": round(mix["ms_eager"] / args.steps, 5)}},
