@@ -259,7 +259,9 @@ hwe_status hwe_check_state(hwe_mesh m, const double* wbar, int32_t* flags_dev, v
  * in the monomial basis about the cell centroid:
  * R(x,y) - Wbar = a0 + a1 X + a2 Y + a3 X^2 + a4 XY + a5 Y^2.
  * Moving boundary states are taken at the time set by hwe_set_time (a step
- * takes them at that time + dt/2).  HWE_EINVAL if R_out overlaps the state. */
+ * takes them at that time + dt/2).  R_out must be 16-byte aligned (whole
+ * records are written with 16-byte stores); HWE_EINVAL if it is not or if it
+ * overlaps the state. */
 hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, void* R_out, void* stream);
 
 /* Edge stage only (Sec. 2.1, eqs. (fx), (flux), (tay), (tayext), and the

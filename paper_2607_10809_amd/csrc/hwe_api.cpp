@@ -338,6 +338,10 @@ hwe_status hwe_debug_recon(hwe_mesh m, const double* wbar, const void* grad, voi
     set_error("null pointer");
     return HWE_EINVAL;
   }
+  if (!aligned16(R_out)) {
+    set_error("misaligned reconstruction buffer (16-byte alignment required)");
+    return HWE_EINVAL;
+  }
   const size_t N = size_t(m->h.N), mm = size_t(m->h.m);
   if (overlaps(R_out, 6 * mm * N * real_size(m), wbar, mm * N * sizeof(double)) ||
       overlaps(R_out, 6 * mm * N * real_size(m), grad, 2 * mm * N * real_size(m))) {

@@ -42,6 +42,34 @@ constexpr int kBlock = 256;
 // For Euler a block covers exactly one table tile (64 cells x 4 components):
 // the tile's tables are one contiguous block, staged into LDS with 16-byte
 // loads that are all in flight together, while the stencil gathers proceed.
+// Euler: the four component lanes of a cell (an aligned quad) transpose
+// their six coefficients with DPP exchanges so that lane q writes row q of the
+// cell's [6][4] record (one 16-byte store in FP32, two in FP64) and half of
+// rows 4-5, instead of six scalar stores each.  R is 16-byte aligned.
+template <class Real>
+__device__ __forceinline__ void store_coeffs_quad(int i, int q, const Real (&a)[6], Real* __restrict__ R,
+                                                  bool valid) {
+  Real t[4] = {a[0], a[1], a[2], a[3]};
+  quad_transpose4(t, q);  // rows 0-3
+  // rows 4-5: lane q takes entries 16 + 2q and 17 + 2q of the record, i.e.
+  // row 4 + q/2, columns 2 (q mod 2) and 2 (q mod 2) + 1
+  constexpr int kEven = 0 | (2 << 2) | (0 << 4) | (2 << 6), kOdd = 1 | (3 << 2) | (1 << 4) | (3 << 6);
+  const Real x4 = quad_perm<kEven>(a[4]), x5 = quad_perm<kEven>(a[5]);
+  const Real y4 = quad_perm<kOdd>(a[4]), y5 = quad_perm<kOdd>(a[5]);
+  const Real b[2] = {(q >> 1) ? x5 : x4, (q >> 1) ? y5 : y4};
+  if (!valid) return;
+  Real* rec = R + size_t(i) * 24;
+  store_record<4>(rec + 4 * q, t);
+  if constexpr (sizeof(Real) == 8) {
+    store_record<2>(rec + 16 + 2 * q, b);
+  } else {
+    float2 v;
+    v.x = b[0];
+    v.y = b[1];
+    *reinterpret_cast<float2*>(rec + 16 + 2 * q) = v;
+  }
+}
+
 // NPT: the limiter's points per cell (6, or 9 with the 3-point edge rule).
 template <int EQ, class Real, int NPT>
 __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, const double* __restrict__ wbar,
@@ -93,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
 #pragma unroll
       for (int j = 0; j < 6; ++j) a[j] *= tq;
     }
-    if (valid) store_coeffs<EQ, Real>(i, q, N, a, R);
+    store_coeffs_quad<Real>(i, q, a, R, valid);
   } else {
     if (i >= N) return;
     Real a[6];

@@ -46,6 +46,27 @@ template <int CTRL> __device__ __forceinline__ double quad_perm(double v) {
   const int lo = quad_perm<CTRL>(__double2loint(v)), hi = quad_perm<CTRL>(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
+// A 4x4 transpose across each aligned quad: lane q holds column q of the
+// block in t[0..3] on entry and row q on exit (two DPP rounds: the
+// off-diagonal 2x2 blocks swap, then the entries within them).
+template <class T> __device__ __forceinline__ void quad_transpose4(T (&t)[4], int q) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const T got = quad_perm<kQuadXor2>((q & 2) ? t[j] : t[j + 2]);
+    if (q & 2)
+      t[j] = got;
+    else
+      t[j + 2] = got;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; j += 2) {
+    const T got = quad_perm<kQuadXor1>((q & 1) ? t[j] : t[j + 1]);
+    if (q & 1)
+      t[j] = got;
+    else
+      t[j + 1] = got;
+  }
+}
 // The value of lane c (0..3) of each aligned quad, in every lane of the quad.
 template <class T> __device__ __forceinline__ T quad_bcast(T v, int c) {
   switch (c) {
