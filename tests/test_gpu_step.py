@@ -435,6 +435,17 @@ def test_bad_arguments_raise():
         mesh.step(w, g, float("nan"))
     with pytest.raises(HweError):                 # output aliases the input
         mesh.step(w, g, 0.01, out=(w, g))
+    # the reconstruction record is written in 16-byte chunks: a misaligned or
+    # overlapping output buffer is refused before any launch
+    import ctypes
+    L = mesh._L
+    raw = torch.empty(6 * mesh.m * mesh.N * 8 + 64, dtype=torch.uint8, device=mesh.device)
+    bad = ctypes.c_void_p(raw.data_ptr() + 8)
+    st = L.hwe_debug_recon(mesh.handle, ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(g.data_ptr()), bad, None)
+    assert st != 0 and b"align" in L.hwe_last_error()
+    st = L.hwe_debug_recon(mesh.handle, ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                           ctypes.c_void_p(w.data_ptr()), None)
+    assert st != 0
     torch.cuda.synchronize()
 
 
