@@ -243,9 +243,12 @@ hwe_status hwe_step_adjoint_kept(hwe_mesh m, const double* wbar_n, const void* g
  * taken when a step is launched. */
 hwe_status hwe_set_time(hwe_mesh m, double t);
 
-/* Largest stable step of the time loop: dt = cfl * min_K r_K / max_K lambda_K
- * (r_K inradius, lambda_K the largest signal speed at the cell average).
- * Writes one double to device memory dt_dev. */
+/* Step size of the time loop.  Sec. 3 fixes only the CFL number (0.5 there);
+ * the length and speed it scales are a reading: dt = cfl * min_K r_K /
+ * max_K lambda_K with r_K the inradius of K and lambda_K the largest signal
+ * speed over all directions at the cell average (|a| for advection,
+ * sqrt(2)|u| for Burgers, |(u, v)| + c for Euler).  Writes one double to
+ * device memory dt_dev; a NaN average gives a NaN step. */
 hwe_status hwe_max_dt(hwe_mesh m, const double* wbar, double cfl, double* dt_dev, void* stream);
 
 /* State diagnostics into device int32 flags_dev[1] (overwritten):

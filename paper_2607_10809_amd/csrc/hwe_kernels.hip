@@ -349,6 +349,9 @@ __global__ __launch_bounds__(kUpdateBlock) void update_kernel(int N, int E, int 
 }
 
 // ---------------------------------------------------------------- reductions
+// Step size of the time loop (Sec. 3 states the CFL number): the largest
+// signal speed over the cells, reduced per block and then over the blocks;
+// dt = cfl * (smallest inradius, a mesh constant) / that speed.
 template <int EQ>
 __global__ __launch_bounds__(kBlock) void max_speed_kernel(int N, Params P, const double* __restrict__ wbar,
                                                             double* __restrict__ part) {
