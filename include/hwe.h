@@ -165,7 +165,9 @@ hwe_status hwe_opts_default(hwe_opts* o);
  * of every boundary face (opts.walls, opts.regions) and, per cell, the linear
  * maps of the constrained least-squares problems of Steps 1 and 2.  Copies the inputs;
  * the caller keeps ownership.  Returns HWE_EMESH or HWE_ESINGULAR for bad
- * meshes, HWE_EHIP / HWE_ENOMEM for device failures.  *out is valid only on
+ * meshes, HWE_EHIP / HWE_ENOMEM for device failures, and HWE_EINVAL for a
+ * device handle beyond the kernels' 32-bit indexing (N >= 2^28 cells, or
+ * E >= 2^29 edges, 2^28 with the 3-point edge rule).  *out is valid only on
  * HWE_OK. */
 hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tris, int64_t n_tris,
                          const hwe_opts* opts, hwe_mesh* out);

@@ -157,8 +157,12 @@ hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tr
     s = HWE_EMESH;
   }
   if (s == HWE_OK && o.device >= 0) {
-    if (M->h.N >= (int64_t(1) << 31) / 6 || M->h.E >= (int64_t(1) << 29)) {
-      set_error("mesh too large for 32-bit device indexing");
+    // the kernels index in 32 bits: the state's (2m + m) N entries per
+    // component block (N < 2^28 for m = 4), and 4 (8 with the 3-point edge
+    // rule) work-items per edge
+    const int64_t e_max = int64_t(1) << (o.edge_rule == 3 ? 28 : 29);
+    if (M->h.N >= (int64_t(1) << 28) || M->h.E >= e_max) {
+      set_error("mesh too large for 32-bit device indexing (N < 2^28, E < 2^29, or 2^28 with the 3-point edge rule)");
       s = HWE_EINVAL;
     } else {
       s = upload_mesh(M);

@@ -526,19 +526,24 @@ hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, cons
   // optional per-kernel events (profiling mode only)
   hipEvent_t* ev = nullptr;
   if (d.prof_n < d.prof_cap) ev = reinterpret_cast<hipEvent_t*>(&M->d.prof_ev[4 * size_t(d.prof_n)]);
-  if (ev) hipEventRecord(ev[0], st);
+  hipError_t ev_err = hipSuccess;
+  auto record = [&](int j) {
+    if (!ev) return;
+    const hipError_t e = hipEventRecord(ev[j], st);
+    if (e != hipSuccess && ev_err == hipSuccess) ev_err = e;
+  };
+  record(0);
   recon_launch<EQ, Real>(M, P, wbar_in, grad_in, tbl, R, st);
-  if (ev) hipEventRecord(ev[1], st);
+  record(1);
   edge_impl<EQ, Real>(M, P, dt, wbar_in, R, egp, F, G, st);
-  if (ev) hipEventRecord(ev[2], st);
+  record(2);
   hipLaunchKernelGGL((update_kernel<EQ, Real>), dim3((N + kUpdateBlock - 1) / kUpdateBlock), dim3(kUpdateBlock), 0, st, N, E, NB, P, dt, wbar_in,
                      d.bnd_n, d.nbr, d.cell_edge, nl, d.inv_area, F, G, wbar_out, grad_out);
-  if (ev) {
-    hipEventRecord(ev[3], st);
-    ++M->d.prof_n;
-  }
+  record(3);
+  if (ev) ++M->d.prof_n;
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return hip_fail(err, "kernel launch");
+  if (ev_err != hipSuccess) return hip_fail(ev_err, "hipEventRecord");
   return HWE_OK;
 }
 
