@@ -167,8 +167,9 @@ hwe_status hwe_opts_default(hwe_opts* o);
  * the caller keeps ownership.  Returns HWE_EMESH or HWE_ESINGULAR for bad
  * meshes, HWE_EHIP / HWE_ENOMEM for device failures, and HWE_EINVAL for a
  * device handle beyond the kernels' 32-bit indexing (N >= 2^28 cells, or
- * E >= 2^29 edges, 2^28 with the 3-point edge rule).  *out is valid only on
- * HWE_OK. */
+ * E >= 2^29 edges, 2^28 with the 3-point edge rule).  With a device it also
+ * resolves the device address of the static scratch of hwe_step_noalloc.
+ * *out is valid only on HWE_OK. */
 hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tris, int64_t n_tris,
                          const hwe_opts* opts, hwe_mesh* out);
 
@@ -238,6 +239,29 @@ hwe_status hwe_step_keep(hwe_mesh m, const double* wbar_in, const void* grad_in,
 hwe_status hwe_step_adjoint_kept(hwe_mesh m, const double* wbar_n, const void* grad_n, const void* recon_n,
                                  const double* lam_wbar_np1, const void* lam_grad_np1, double* lam_wbar_n,
                                  void* lam_grad_n, double dt, void* stream);
+
+/* For callers that cannot allocate device memory when they step: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * hwe_step_noalloc: hwe_step whose scratch (the reconstruction, [N][6][m] of
+ * double or float by precision, the edge fluxes, [E][m] double, and the
+ * interface values, [E][m] double or float, each part 256-byte aligned) lives
+ * in one static device array of HWE_NOALLOC_SCRATCH_BYTES per GPU that the
+ * library holds until the process ends, in place of the handle's scratch.  It
+ * calls no hipMalloc, hipFree or allocating library routine.  The array's
+ * device address is resolved by hwe_mesh_init for the handle's device.
+ * Same arguments, checks and results (bitwise) as hwe_step.
+ *  - HWE_EINVAL if the mesh's scratch exceeds HWE_NOALLOC_SCRATCH_BYTES
+ *    (64 MiB: e.g. 204,800 Euler triangles in FP64 need 59.0 MB, in the mixed
+ *    precision 39.3 MB); the message gives both sizes.
+ *  - Every call on one GPU, from any handle or thread, shares that GPU's
+ *    array, which keeps the last call's contents: calls that overlap in time
+ *    on one GPU race (serialise them, e.g. on one stream).  Nothing in the
+ *    array needs clearing: a step writes every entry it reads before reading
+ *    it. */
+#define HWE_NOALLOC_SCRATCH_BYTES (64u << 20)
+hwe_status hwe_step_noalloc(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out,
+                            void* grad_out, double dt, void* stream);
 
 /* Time of the state handed to the following hwe_step / hwe_step_keep /
  * hwe_step_adjoint / hwe_step_adjoint_kept calls on this handle (default 0).  Only HWE_BND_MOVING faces depend on it: a step

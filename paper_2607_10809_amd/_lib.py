@@ -59,6 +59,7 @@ def load_library():
     L.hwe_step.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp]
     L.hwe_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_double, vp]
     L.hwe_step_keep.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp, vp]
+    L.hwe_step_noalloc.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp]
     L.hwe_set_time.argtypes = [vp, C.c_double]
     L.hwe_step_adjoint_kept.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp]
     L.hwe_max_dt.argtypes = [vp, vp, C.c_double, vp, vp]
@@ -71,7 +72,7 @@ def load_library():
     L.hwe_last_error.restype = C.c_char_p
     for name in ("hwe_opts_default", "hwe_mesh_init", "hwe_mesh_destroy", "hwe_mesh_info", "hwe_mesh_cell_perm",
                  "hwe_step", "hwe_step_adjoint", "hwe_step_keep", "hwe_step_adjoint_kept", "hwe_set_time",
-                 "hwe_max_dt", "hwe_check_state", "hwe_debug_recon", "hwe_debug_edge", "hwe_debug_host_array",
+                 "hwe_step_noalloc", "hwe_max_dt", "hwe_check_state", "hwe_debug_recon", "hwe_debug_edge", "hwe_debug_host_array",
                  "hwe_profile_begin",
                  "hwe_profile_end"):
         getattr(L, name).restype = C.c_int
@@ -90,5 +91,5 @@ def exported_symbols():
     return ["hwe_opts_default", "hwe_mesh_init", "hwe_mesh_destroy", "hwe_mesh_info", "hwe_mesh_cell_perm",
             "hwe_step", "hwe_step_adjoint", "hwe_step_keep", "hwe_step_adjoint_kept", "hwe_set_time",
             "hwe_max_dt", "hwe_check_state", "hwe_debug_recon", "hwe_debug_edge", "hwe_debug_host_array",
-            "hwe_profile_begin", "hwe_profile_end",
+            "hwe_profile_begin", "hwe_profile_end", "hwe_step_noalloc",
             "hwe_last_error"]

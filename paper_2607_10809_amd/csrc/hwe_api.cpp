@@ -166,6 +166,7 @@ hwe_status hwe_mesh_init(const double* nodes, int64_t n_nodes, const int32_t* tr
       s = HWE_EINVAL;
     } else {
       s = upload_mesh(M);
+      if (s == HWE_OK) s = scratch_setup(o.device);
     }
   }
   if (s != HWE_OK) {
@@ -281,6 +282,13 @@ hwe_status hwe_step(hwe_mesh m, const double* wbar_in, const void* grad_in, doub
   hwe_status s = check_step(m, wbar_in, grad_in, wbar_out, grad_out, dt, nullptr);
   if (s != HWE_OK) return s;
   return launch_step(m, wbar_in, grad_in, wbar_out, grad_out, dt, nullptr, stream);
+}
+
+hwe_status hwe_step_noalloc(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out,
+                            void* grad_out, double dt, void* stream) {
+  hwe_status s = check_step(m, wbar_in, grad_in, wbar_out, grad_out, dt, nullptr);
+  if (s != HWE_OK) return s;
+  return launch_step_noalloc(m, wbar_in, grad_in, wbar_out, grad_out, dt, stream);
 }
 
 hwe_status hwe_step_keep(hwe_mesh m, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,

@@ -124,6 +124,14 @@ void free_device(hwe_mesh_s* M);
 // handle's scratch R.
 hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out,
                        void* grad_out, double dt, void* R_keep, void* stream);
+// hwe_step with its scratch in the library's static device array (see
+// hwe_step_noalloc); HWE_EINVAL when the mesh needs more than the array holds.
+hwe_status launch_step_noalloc(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out,
+                               void* grad_out, double dt, void* stream);
+// Bytes of step scratch (R, F, G, each 256-byte aligned) a handle needs.
+size_t step_scratch_bytes(const hwe_mesh_s* M);
+// Resolve the static scratch's device address on `device` (current) once.
+hwe_status scratch_setup(int device);
 // tb: the time at which moving boundary states are evaluated (a step uses
 // the middle of the step)
 hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, void* R_out, double tb, void* stream);

@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <sstream>
 
 #include "hwe_internal.h"
@@ -516,12 +517,10 @@ void edge_impl(hwe_mesh_s* M, const Params& P, double dt, const double* wbar, co
 template <int EQ, class Real>
 hwe_status step_impl(hwe_mesh_s* M, const Params& P, const double* wbar_in, const Real* grad_in, double* wbar_out,
                      Real* grad_out, double dt, hipStream_t st, const Real* tbl, const Real* nl,
-                     const Real* egp, Real* R) {
+                     const Real* egp, Real* R, double* F, Real* G) {
   const HostMesh& h = M->h;
   const DevMesh& d = M->d;
   const int N = int(h.N), E = int(h.E), NB = int(h.NB);
-  double* F = static_cast<double*>(d.F);
-  Real* G = static_cast<Real*>(d.G);
   constexpr int Mc = NComp<EQ>::m;
   // optional per-kernel events (profiling mode only)
   hipEvent_t* ev = nullptr;
@@ -662,35 +661,114 @@ void free_device(hwe_mesh_s* M) {
   d = DevMesh();
 }
 
-hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,
-                       double dt, void* R_keep, void* stream) {
+namespace {
+// The step with its scratch (reconstruction R, edge fluxes F, interface values
+// G) at the given device addresses.
+hwe_status launch_step_with(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out,
+                            void* grad_out, double dt, void* R, double* F, void* G, void* stream) {
   Params P = params_of(M->opts);
   P.tb = M->time + 0.5 * dt;  // moving boundary states: the middle of the step
   hipStream_t st = static_cast<hipStream_t>(stream);
   const DevMesh& d = M->d;
-  void* R = R_keep ? R_keep : d.R;
   if (M->opts.prec == HWE_FP64) {
     auto gi = static_cast<const double*>(grad_in);
     auto go = static_cast<double*>(grad_out);
+    auto r = static_cast<double*>(R);
+    auto g = static_cast<double*>(G);
     switch (M->opts.eq) {
       case HWE_ADVECTION:
-        return step_impl<EQ_ADV, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp, static_cast<double*>(R));
+        return step_impl<EQ_ADV, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp, r, F, g);
       case HWE_BURGERS:
-        return step_impl<EQ_BUR, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp, static_cast<double*>(R));
+        return step_impl<EQ_BUR, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp, r, F, g);
       default:
-        return step_impl<EQ_EUL, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp, static_cast<double*>(R));
+        return step_impl<EQ_EUL, double>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tbl, d.nl, d.egp, r, F, g);
     }
   }
   auto gi = static_cast<const float*>(grad_in);
   auto go = static_cast<float*>(grad_out);
+  auto r = static_cast<float*>(R);
+  auto g = static_cast<float*>(G);
   switch (M->opts.eq) {
     case HWE_ADVECTION:
-      return step_impl<EQ_ADV, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf, static_cast<float*>(R));
+      return step_impl<EQ_ADV, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf, r, F, g);
     case HWE_BURGERS:
-      return step_impl<EQ_BUR, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf, static_cast<float*>(R));
+      return step_impl<EQ_BUR, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf, r, F, g);
     default:
-      return step_impl<EQ_EUL, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf, static_cast<float*>(R));
+      return step_impl<EQ_EUL, float>(M, P, wbar_in, gi, wbar_out, go, dt, st, d.tblf, d.nlf, d.egpf, r, F, g);
   }
+}
+
+// Scratch of hwe_step_noalloc: one array per GPU for the whole library, held
+// until the process ends.  Host code never uses the array's name as an
+// address (on the host it is a stand-in, not device memory): the device
+// address is resolved once per device by scratch_setup and kept in
+// g_scratch_dev.
+constexpr size_t kStaticScratchBytes = size_t(HWE_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+}  // namespace
+
+hwe_status launch_step(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out, void* grad_out,
+                       double dt, void* R_keep, void* stream) {
+  const DevMesh& d = M->d;
+  return launch_step_with(M, wbar_in, grad_in, wbar_out, grad_out, dt, R_keep ? R_keep : d.R,
+                          static_cast<double*>(d.F), d.G, stream);
+}
+
+hwe_status scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device ordinal out of range for the static scratch");
+    return HWE_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return HWE_OK;
+  // the caller made `device` current
+  void* ptr = nullptr;
+  hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (err != hipSuccess) return hip_fail(err, "hipGetSymbolAddress(scratch)");
+  if (!ptr) {
+    set_error("hipGetSymbolAddress(scratch) returned a null address");
+    return HWE_EHIP;
+  }
+  g_scratch_dev[device] = ptr;
+  return HWE_OK;
+}
+
+size_t step_scratch_bytes(const hwe_mesh_s* M) {
+  const size_t N = size_t(M->h.N), E = size_t(M->h.E), m = size_t(M->h.m);
+  const size_t rs = M->opts.prec == HWE_FP64 ? sizeof(double) : sizeof(float);
+  return align256(6 * m * N * rs) + align256(m * E * sizeof(double)) + align256(m * E * rs);
+}
+
+hwe_status launch_step_noalloc(hwe_mesh_s* M, const double* wbar_in, const void* grad_in, double* wbar_out,
+                               void* grad_out, double dt, void* stream) {
+  const size_t need = step_scratch_bytes(M);
+  if (need > kStaticScratchBytes) {
+    std::ostringstream msg;
+    msg << "the mesh needs " << need << " bytes of step scratch; the static scratch holds " << kStaticScratchBytes;
+    set_error(msg.str());
+    return HWE_EINVAL;
+  }
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = M->d.device >= 0 && M->d.device < kMaxDevices ? g_scratch_dev[M->d.device] : nullptr;
+  }
+  if (!base) {
+    set_error("the static scratch of this device was not set up");
+    return HWE_EHIP;
+  }
+  const size_t N = size_t(M->h.N), E = size_t(M->h.E), m = size_t(M->h.m);
+  const size_t rs = M->opts.prec == HWE_FP64 ? sizeof(double) : sizeof(float);
+  unsigned char* b = static_cast<unsigned char*>(base);
+  void* R = b;
+  double* F = reinterpret_cast<double*>(b + align256(6 * m * N * rs));
+  void* G = b + align256(6 * m * N * rs) + align256(m * E * sizeof(double));
+  return launch_step_with(M, wbar_in, grad_in, wbar_out, grad_out, dt, R, F, G, stream);
 }
 
 hwe_status launch_recon(hwe_mesh_s* M, const double* wbar, const void* grad, void* R_out, double tb, void* stream) {

@@ -81,6 +81,11 @@ def hwe_step(handle, wbar_in, grad_in, wbar_out, grad_out, dt, stream=None):
                                   float(dt), _stream(stream)))
 
 
+def hwe_step_noalloc(handle, wbar_in, grad_in, wbar_out, grad_out, dt, stream=None):
+    check(load_library().hwe_step_noalloc(handle, _ptr(wbar_in), _ptr(grad_in), _ptr(wbar_out), _ptr(grad_out),
+                                          float(dt), _stream(stream)))
+
+
 def hwe_step_adjoint(handle, wbar_n, grad_n, lam_wbar_np1, lam_grad_np1, lam_wbar_n, lam_grad_n, dt, stream=None):
     check(load_library().hwe_step_adjoint(handle, _ptr(wbar_n), _ptr(grad_n), _ptr(lam_wbar_np1),
                                           _ptr(lam_grad_np1), _ptr(lam_wbar_n), _ptr(lam_grad_n), float(dt),

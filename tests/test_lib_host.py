@@ -76,6 +76,9 @@ def test_error_statuses():
     st = L.hwe_step(m.handle, C.c_void_p(16), C.c_void_p(32), C.c_void_p(48), C.c_void_p(64), C.c_double(0.1),
                     C.c_void_p())
     assert st == -6                             # host-only handle: no device work
+    st = L.hwe_step_noalloc(m.handle, C.c_void_p(16), C.c_void_p(32), C.c_void_p(48), C.c_void_p(64),
+                            C.c_double(0.1), C.c_void_p())
+    assert st == -6
     st = L.hwe_step_keep(m.handle, C.c_void_p(16), C.c_void_p(32), C.c_void_p(48), C.c_void_p(64),
                          C.c_double(0.1), C.c_void_p(4096), C.c_void_p())
     assert st == -6
