@@ -39,7 +39,9 @@
 //   index) on ties.
 //
 // Everything is templated on the scalar type: double for the forward map,
-// Dual (value + one tangent) for exact Jacobian-vector products.
+// Dual (value + one tangent) for exact Jacobian-vector products, Rev (a node
+// on a local tape) for the reverse mode, i.e. vector-Jacobian products, and
+// Cnt for counting the floating-point operations of a step by stage.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -83,6 +85,124 @@ inline Dual sqrtv(Dual a) {
   return Dual(s, a.d / (2.0 * s));
 }
 template <class T> inline T maxfirst(T a, T b) { return val(a) >= val(b) ? a : b; }
+
+// Reverse mode.  A Rev number is a value and the index of its node on the
+// calling thread's tape (-1: a constant).  Every operation records its
+// operands' nodes and the partial derivatives with respect to them; a reverse
+// sweep over the tape then carries adjoints from outputs to leaves.  The
+// tapes are local: one cell's update (eq. (flx) and the Green-Gauss averages)
+// or one cell's reconstruction (Sec. 2.2) is recorded, reversed and cleared,
+// and the adjoints of its inputs are added to the cells they belong to.
+struct Tape {
+  std::vector<int32_t> pa, pb;
+  std::vector<double> da, db;
+  void clear() {
+    pa.clear();
+    pb.clear();
+    da.clear();
+    db.clear();
+  }
+  size_t size() const { return pa.size(); }
+  int32_t push(int32_t a, double ga, int32_t b, double gb) {
+    pa.push_back(a);
+    da.push_back(ga);
+    pb.push_back(b);
+    db.push_back(gb);
+    return int32_t(pa.size() - 1);
+  }
+  // adj: seeded adjoints of the nodes (size() entries); on return the
+  // adjoint of every node, leaves included.
+  void reverse(std::vector<double>& adj) const {
+    for (size_t k = pa.size(); k-- > 0;) {
+      const double g = adj[k];
+      if (g == 0.0) continue;
+      if (pa[k] >= 0) adj[pa[k]] += da[k] * g;
+      if (pb[k] >= 0) adj[pb[k]] += db[k] * g;
+    }
+  }
+};
+thread_local Tape* g_tape = nullptr;
+
+struct Rev {
+  double v;
+  int32_t i;
+  Rev() : v(0), i(-1) {}
+  Rev(double a) : v(a), i(-1) {}
+  Rev(double a, int32_t k) : v(a), i(k) {}
+};
+inline Rev rev_node(double v, int32_t a, double ga, int32_t b, double gb) {
+  if (a < 0 && b < 0) return Rev(v);
+  return Rev(v, g_tape->push(a, ga, b, gb));
+}
+inline Rev rev_leaf(double v) { return Rev(v, g_tape->push(-1, 0.0, -1, 0.0)); }
+inline Rev operator+(Rev a, Rev b) { return rev_node(a.v + b.v, a.i, 1.0, b.i, 1.0); }
+inline Rev operator-(Rev a, Rev b) { return rev_node(a.v - b.v, a.i, 1.0, b.i, -1.0); }
+inline Rev operator-(Rev a) { return rev_node(-a.v, a.i, -1.0, -1, 0.0); }
+inline Rev operator*(Rev a, Rev b) { return rev_node(a.v * b.v, a.i, b.v, b.i, a.v); }
+inline Rev operator/(Rev a, Rev b) {
+  const double q = a.v / b.v;
+  return rev_node(q, a.i, 1.0 / b.v, b.i, -q / b.v);
+}
+inline Rev& operator+=(Rev& a, Rev b) { a = a + b; return a; }
+inline Rev& operator-=(Rev& a, Rev b) { a = a - b; return a; }
+inline Rev& operator*=(Rev& a, Rev b) { a = a * b; return a; }
+inline double val(Rev a) { return a.v; }
+inline Rev absval(Rev a) { return rev_node(std::fabs(a.v), a.i, sgn0(a.v), -1, 0.0); }
+inline Rev sqrtv(Rev a) {
+  const double r = std::sqrt(a.v);
+  return rev_node(r, a.i, 0.5 / r, -1, 0.0);
+}
+
+// Operation counting.  A Cnt number counts every +, -, *, / and square root
+// applied to it (sign changes and |x| are free) into the calling thread's
+// counter of the current stage.  Constants equal to zero are structural
+// zeros: operations with them (x * 0, x + 0, 0 / x) are not counted and give
+// a structural zero or the other operand, so that e.g. the unused parts of a
+// hyper-dual number cost nothing.
+enum { kStRecon = 0, kStLimiter, kStAlpha, kStEval, kStLW, kStFlux, kStUpdate, kNStages };
+thread_local int g_stage = kStRecon;
+thread_local uint64_t g_flops[kNStages] = {};
+inline void stage(int s) { g_stage = s; }
+
+struct Cnt {
+  double v;
+  bool z;  // structural zero
+  Cnt() : v(0), z(true) {}
+  Cnt(double a) : v(a), z(a == 0.0) {}
+  Cnt(double a, bool zz) : v(a), z(zz) {}
+};
+inline Cnt counted(double v) {
+  ++g_flops[g_stage];
+  return Cnt(v, false);
+}
+inline Cnt operator+(Cnt a, Cnt b) {
+  if (a.z) return b;
+  if (b.z) return a;
+  return counted(a.v + b.v);
+}
+inline Cnt operator-(Cnt a) { return Cnt(-a.v, a.z); }
+inline Cnt operator-(Cnt a, Cnt b) {
+  if (b.z) return a;
+  if (a.z) return -b;
+  return counted(a.v - b.v);
+}
+inline Cnt operator*(Cnt a, Cnt b) {
+  if (a.z || b.z) return Cnt(0.0, true);
+  return counted(a.v * b.v);
+}
+inline Cnt operator/(Cnt a, Cnt b) {
+  if (a.z) return Cnt(0.0, true);
+  return counted(a.v / b.v);
+}
+inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
+inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
+inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
+inline double val(Cnt a) { return a.v; }
+inline Cnt absval(Cnt a) { return Cnt(std::fabs(a.v), a.z); }
+inline Cnt sqrtv(Cnt a) {
+  if (a.z) return a;
+  return counted(std::sqrt(a.v));
+}
 
 // Hyper-dual number a + e1 b1 + e2 b2 + e1 e2 b12 over scalar T
 // (e1^2 = e2^2 = 0).  f(w + e1 x + e2 y + e1e2 z) has e1 part f'x and e1e2
@@ -423,6 +543,7 @@ template <class T>
 bool reconstruct(const Mesh& M, const T* s, int64_t k, Recon<T>& R) {
   const Opts& o = M.o;
   const int m = M.m;
+  stage(kStRecon);
   StencilCell<T> st[4];
   stencil_of(M, s, k, st);
   const double x0 = M.cx[k], y0 = M.cy[k];
@@ -549,7 +670,10 @@ bool reconstruct(const Mesh& M, const T* s, int64_t k, Recon<T>& R) {
     }
     for (int l = 0; l < 4; ++l) R.omega[q][l] = wb[l] / ssum;
   }
-  if (o.positivity && o.eq == 2) positivity_scaling(M, k, R);
+  if (o.positivity && o.eq == 2) {
+    stage(kStLimiter);
+    positivity_scaling(M, k, R);
+  }
   return true;
 }
 
@@ -709,6 +833,7 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
       for (int q = 0; q < m; ++q) Wbn[q] = s[q * N + F.nb];
     // alpha: spectral radii at the two cell averages, the first argument
     // belonging to the cell with the lower index
+    stage(kStAlpha);
     T alpha = T(0.0);
     if (F.nb >= 0) {
       T aK = spectral_radius(o, Wbar, F.nx, F.ny);
@@ -732,6 +857,7 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
       double xg = t.x[f] + er.s[G] * (t.x[f1] - t.x[f]);
       double yg = t.y[f] + er.s[G] * (t.y[f1] - t.y[f]);
       T Di[6][4], De[6][4], tmp[6];
+      stage(kStEval);
       for (int q = 0; q < m; ++q) {
         eval_recon(o, R[k], q, xg, yg, tmp);
         for (int j = 0; j < 6; ++j) Di[j][q] = tmp[j];
@@ -743,8 +869,10 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
         }
       }
       T it[4], itx[4], ity[4], itt[4], et[4], etx[4], ety[4], ett[4];
+      stage(kStLW);
       lax_wendroff(o, m, Di, it, itx, ity, itt);
       if (F.nb >= 0) lax_wendroff(o, m, De, et, etx, ety, ett);
+      stage(kStFlux);
       // Taylor polynomials in time, eq. (tay), of the interior and exterior values
       // (boundary: W_ext = W_int on a transmissive face, the reflected W_int on a wall)
       auto taylor = [&](double tau, T Wi[4], T We[4]) {
@@ -780,6 +908,7 @@ void update_cell(const Mesh& M, const T* s, const std::vector<Recon<T>>& R, int6
     }
   }
   const double A = M.area[k];
+  stage(kStUpdate);
   for (int q = 0; q < m; ++q) {
     Wn[q] = Wbar[q] - T(dt / A) * Fsum[q];
     Vn[q] = Vs[q] / T(A);
@@ -835,6 +964,194 @@ int step_all(const Mesh& M, const T* s, T* out, double dt, int nthr) {
   std::vector<int64_t> cells(M.N);
   for (int64_t k = 0; k < M.N; ++k) cells[k] = k;
   return step_cells(M, s, cells.data(), M.N, out, dt, nthr);
+}
+
+// ---------------------------------------------------------------- reverse mode
+// The fields of a reconstruction that the update reads: the candidates'
+// coefficients, the nonlinear weights, the limiter's scaling and the cell
+// averages (Sec. 2.2, Steps 1-6).
+template <class T, class Fn>
+void recon_fields(Recon<T>& R, int m, Fn fn) {
+  for (int l = 0; l < 4; ++l)
+    for (int q = 0; q < m; ++q)
+      for (int j = 0; j < 6; ++j) fn(R.p[l][q][j]);
+  for (int q = 0; q < m; ++q)
+    for (int l = 0; l < 4; ++l) fn(R.omega[q][l]);
+  for (int q = 0; q < m; ++q) {
+    fn(R.theta[q]);
+    fn(R.wbar[q]);
+  }
+}
+
+// The cell and its face neighbours, each once.
+inline int stencil_cells(const Mesh& M, int64_t k, int64_t out[4]) {
+  int n = 0;
+  out[n++] = k;
+  for (int f = 0; f < 3; ++f) {
+    const int64_t c = M.face[k][f].nb;
+    bool seen = c < 0;
+    for (int j = 0; j < n && !seen; ++j) seen = out[j] == c;
+    if (!seen) out[n++] = c;
+  }
+  return n;
+}
+
+// Vector-Jacobian product of one step at the state s (double [3][m][N]):
+// lam_in = J^T lam_out.  Reverse of the updates first (each cell's update
+// reads the averages of the cell and its face neighbours and their
+// reconstructions), then of the reconstructions (each reads the state of the
+// cell and its face neighbours).  The same non-smooth conventions as the
+// dual numbers: d|x| = sign(x) dx with sign(0) = 0, max takes its first
+// argument on ties, the limiter's branches are the forward's.
+int vjp_step(const Mesh& M, const double* s, const double* lam_out, double* lam_in, double dt, int nthr) {
+  const int m = M.m;
+  const int64_t N = M.N;
+  const size_t n3 = size_t(3 * m) * N;
+  std::vector<Recon<double>> R(N);
+  int bad = 0;
+  nthr = nthreads_or_default(nthr);
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthr) reduction(+ : bad)
+  for (int64_t k = 0; k < N; ++k)
+    if (!reconstruct(M, s, k, R[k])) bad += 1;
+  if (bad) return -3;
+  std::vector<Recon<double>> lamR(N);
+  for (auto& r : lamR) recon_fields(r, m, [](double& x) { x = 0.0; });
+  std::vector<double> lam_s(n3, 0.0);
+  // reverse of the updates
+#pragma omp parallel num_threads(nthr)
+  {
+    Tape tape;
+    g_tape = &tape;
+    std::vector<double> adj;
+    std::vector<Rev> srev(n3);
+    for (size_t i = 0; i < n3; ++i) srev[i] = Rev(s[i]);
+    std::vector<Recon<Rev>> Rrev(N);
+    std::vector<Recon<double>> lamR_t(N);
+    for (auto& r : lamR_t) recon_fields(r, m, [](double& x) { x = 0.0; });
+    std::vector<double> lam_t(n3, 0.0);
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t k = 0; k < N; ++k) {
+      tape.clear();
+      int64_t cells[4];
+      const int nc = stencil_cells(M, k, cells);
+      for (int j = 0; j < nc; ++j) {
+        const int64_t c = cells[j];
+        for (int q = 0; q < m; ++q) srev[size_t(q) * N + c] = rev_leaf(s[size_t(q) * N + c]);
+        Recon<Rev>& rr = Rrev[c];
+        Recon<double>& rd = R[c];
+        rr.cx = rd.cx;
+        rr.cy = rd.cy;
+        // copy the values, then make every field a leaf
+        for (int l = 0; l < 4; ++l)
+          for (int q = 0; q < m; ++q)
+            for (int i = 0; i < 6; ++i) rr.p[l][q][i] = Rev(rd.p[l][q][i]);
+        for (int q = 0; q < m; ++q) {
+          for (int l = 0; l < 4; ++l) rr.omega[q][l] = Rev(rd.omega[q][l]);
+          rr.theta[q] = Rev(rd.theta[q]);
+          rr.wbar[q] = Rev(rd.wbar[q]);
+        }
+        recon_fields(rr, m, [](Rev& x) { x = rev_leaf(x.v); });
+      }
+      Rev Wn[4], Vn[4], Yn[4];
+      update_cell(M, srev.data(), Rrev, k, dt, Wn, Vn, Yn);
+      adj.assign(tape.size(), 0.0);
+      for (int q = 0; q < m; ++q) {
+        if (Wn[q].i >= 0) adj[Wn[q].i] += lam_out[size_t(q) * N + k];
+        if (Vn[q].i >= 0) adj[Vn[q].i] += lam_out[size_t(m + q) * N + k];
+        if (Yn[q].i >= 0) adj[Yn[q].i] += lam_out[size_t(2 * m + q) * N + k];
+      }
+      tape.reverse(adj);
+      for (int j = 0; j < nc; ++j) {
+        const int64_t c = cells[j];
+        for (int q = 0; q < m; ++q) {
+          Rev& x = srev[size_t(q) * N + c];
+          lam_t[size_t(q) * N + c] += adj[x.i];
+          x = Rev(x.v);
+        }
+        // the adjoints of cell c's reconstruction fields, in field order
+        std::vector<double> g;
+        recon_fields(Rrev[c], m, [&](Rev& x) { g.push_back(adj[x.i]); });
+        size_t u = 0;
+        recon_fields(lamR_t[c], m, [&](double& x) { x += g[u++]; });
+      }
+    }
+#pragma omp critical
+    {
+      for (size_t i = 0; i < n3; ++i) lam_s[i] += lam_t[i];
+      for (int64_t c = 0; c < N; ++c) {
+        std::vector<double> g;
+        recon_fields(lamR_t[c], m, [&](double& x) { g.push_back(x); });
+        size_t u = 0;
+        recon_fields(lamR[c], m, [&](double& x) { x += g[u++]; });
+      }
+    }
+    g_tape = nullptr;
+  }
+  // reverse of the reconstructions
+#pragma omp parallel num_threads(nthr)
+  {
+    Tape tape;
+    g_tape = &tape;
+    std::vector<double> adj;
+    std::vector<Rev> srev(n3);
+    for (size_t i = 0; i < n3; ++i) srev[i] = Rev(s[i]);
+    std::vector<double> lam_t(n3, 0.0);
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t k = 0; k < N; ++k) {
+      tape.clear();
+      int64_t cells[4];
+      const int nc = stencil_cells(M, k, cells);
+      for (int j = 0; j < nc; ++j)
+        for (int b = 0; b < 3 * m; ++b) {
+          const size_t ix = size_t(b) * N + cells[j];
+          srev[ix] = rev_leaf(s[ix]);
+        }
+      Recon<Rev> Rk;
+      reconstruct(M, srev.data(), k, Rk);
+      adj.assign(tape.size(), 0.0);
+      std::vector<double> g;
+      recon_fields(lamR[k], m, [&](double& x) { g.push_back(x); });
+      size_t u = 0;
+      recon_fields(Rk, m, [&](Rev& x) {
+        if (x.i >= 0) adj[x.i] += g[u];
+        ++u;
+      });
+      tape.reverse(adj);
+      for (int j = 0; j < nc; ++j)
+        for (int b = 0; b < 3 * m; ++b) {
+          const size_t ix = size_t(b) * N + cells[j];
+          lam_t[ix] += adj[srev[ix].i];
+          srev[ix] = Rev(s[ix]);
+        }
+    }
+#pragma omp critical
+    for (size_t i = 0; i < n3; ++i) lam_s[i] += lam_t[i];
+    g_tape = nullptr;
+  }
+  std::memcpy(lam_in, lam_s.data(), n3 * sizeof(double));
+  return 0;
+}
+
+// Operation counts of one step at the state s, per stage (kSt*), summed over
+// the cells: the reconstructions of all cells, then the updates of all cells
+// (each cell's update evaluates the flux through its three faces, so every
+// interior edge is evaluated twice, once from each side).
+int count_step(const Mesh& M, const double* s, double dt, uint64_t out[kNStages]) {
+  const int m = M.m;
+  const int64_t N = M.N;
+  const size_t n3 = size_t(3 * m) * N;
+  std::vector<Cnt> sc(n3);
+  for (size_t i = 0; i < n3; ++i) sc[i] = Cnt(s[i], false);
+  for (int k = 0; k < kNStages; ++k) g_flops[k] = 0;
+  std::vector<Recon<Cnt>> R(N);
+  for (int64_t k = 0; k < N; ++k)
+    if (!reconstruct(M, sc.data(), k, R[k])) return -3;
+  for (int64_t k = 0; k < N; ++k) {
+    Cnt Wn[4], Vn[4], Yn[4];
+    update_cell(M, sc.data(), R, k, dt, Wn, Vn, Yn);
+  }
+  for (int k = 0; k < kNStages; ++k) out[k] = g_flops[k];
+  return 0;
 }
 
 // ---------------------------------------------------------------- mesh build
@@ -1137,6 +1454,49 @@ int or_jvp(void* h, double* s, double* ds, double dt, int64_t nsteps, int nthr) 
     ds[i] = a[i].d;
   }
   return 0;
+}
+
+// Vector-Jacobian product of nsteps steps from the state s at the mesh's
+// time: on entry lam is the adjoint of the final state, on return that of s
+// (both [3][m][N]).  The forward states are kept; the steps are reversed in
+// the opposite order.
+int or_vjp(void* h, const double* s, double* lam, double dt, int64_t nsteps, int nthr) {
+  Mesh* M = static_cast<Mesh*>(h);
+  const size_t n = 3 * M->m * M->N;
+  std::vector<std::vector<double>> states(nsteps);
+  std::vector<double> cur(s, s + n), nxt(n);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    states[k] = cur;
+    M->t_bnd = M->time + (double(k) + 0.5) * dt;
+    int st = step_all(*M, cur.data(), nxt.data(), dt, nthr);
+    if (st) return st;
+    std::swap(cur, nxt);
+  }
+  std::vector<double> lin(n);
+  for (int64_t k = nsteps; k-- > 0;) {
+    M->t_bnd = M->time + (double(k) + 0.5) * dt;
+    int st = vjp_step(*M, states[k].data(), lam, lin.data(), dt, nthr);
+    if (st) return st;
+    std::memcpy(lam, lin.data(), n * sizeof(double));
+  }
+  return 0;
+}
+
+// Floating-point operations of one step at the state s, by stage:
+// out[0] reconstructions (Steps 1-5 with the oracle's per-step least-squares
+// solves), out[1] the scaling limiter, out[2] the flux viscosities, out[3] the
+// evaluation of the final reconstruction at the edge Gauss points (eq.
+// (recon), candidate by candidate), out[4] the Lax-Wendroff procedure, out[5]
+// the Taylor values, fluxes and quadratures of eqs. (fx), (flux), (timeflux),
+// out[6] the update of eqs. (flx) and (derave2d2).  Stages 2-5 are counted
+// from both sides of every edge (each cell evaluates its own faces).
+int or_count_flops(void* h, const double* s, double dt, double* out) {
+  Mesh* M = static_cast<Mesh*>(h);
+  M->t_bnd = M->time + 0.5 * dt;
+  uint64_t c[kNStages];
+  int st = count_step(*M, s, dt, c);
+  for (int k = 0; k < kNStages; ++k) out[k] = double(c[k]);
+  return st;
 }
 
 // Reconstruction details of one cell: p[4][m][6] monomial coefficients about

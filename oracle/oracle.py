@@ -61,6 +61,8 @@ def _load():
         L.or_run.argtypes = [C.c_void_p, dp, C.c_double, C.c_int64, C.c_int]
         L.or_set_time.argtypes = [C.c_void_p, C.c_double]
         L.or_jvp.argtypes = [C.c_void_p, dp, dp, C.c_double, C.c_int64, C.c_int]
+        L.or_vjp.argtypes = [C.c_void_p, dp, dp, C.c_double, C.c_int64, C.c_int]
+        L.or_count_flops.argtypes = [C.c_void_p, dp, C.c_double, dp]
         L.or_recon_cell.argtypes = [C.c_void_p, dp, C.c_int64, dp, dp, dp, dp]
         L.or_eval_recon.argtypes = [C.c_void_p, dp, C.c_int64, dp, C.c_int64, dp]
         L.or_recon_theta.argtypes = [C.c_void_p, dp, C.c_int64, dp]
@@ -222,6 +224,29 @@ class OracleMesh:
         if st:
             raise RuntimeError(f"oracle jvp failed ({st})")
         return s, ds
+
+    def vjp(self, s, lam, dt, nsteps, nthreads=0, t=0.0):
+        """Reverse mode: J^T lam for nsteps steps of size dt from the state s
+        at time t (lam: the adjoint of the final state)."""
+        s = self._check_state(s).copy()
+        lam = self._check_state(lam).copy()
+        _lib.or_set_time(self._h, float(t))
+        st = _lib.or_vjp(self._h, _p(s), _p(lam), float(dt), int(nsteps), int(nthreads))
+        if st:
+            raise RuntimeError(f"oracle vjp failed ({st})")
+        return lam
+
+    COUNT_STAGES = ("recon", "limiter", "alpha", "eval", "lax_wendroff", "flux", "update")
+
+    def count_flops(self, s, dt, t=0.0):
+        """Floating-point operations of one step by stage (see or_count_flops):
+        each interior edge's flux work is counted from both of its cells."""
+        s = self._check_state(s)
+        out = np.zeros(len(self.COUNT_STAGES))
+        _lib.or_set_time(self._h, float(t))
+        if _lib.or_count_flops(self._h, _p(s), float(dt), _p(out)):
+            raise RuntimeError("oracle count failed")
+        return dict(zip(self.COUNT_STAGES, out))
 
     def recon_cell(self, s, k):
         s = self._check_state(s)
