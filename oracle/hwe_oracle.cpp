@@ -41,7 +41,7 @@
 // Everything is templated on the scalar type: double for the forward map,
 // Dual (value + one tangent) for exact Jacobian-vector products, Rev (a node
 // on a local tape) for the reverse mode, i.e. vector-Jacobian products, and
-// Cnt for counting the floating-point operations of a step by stage.
+// for counting the floating-point operations of a step by stage.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -93,21 +93,35 @@ template <class T> inline T maxfirst(T a, T b) { return val(a) >= val(b) ? a : b
 // tapes are local: one cell's update (eq. (flx) and the Green-Gauss averages)
 // or one cell's reconstruction (Sec. 2.2) is recorded, reversed and cleared,
 // and the adjoints of its inputs are added to the cells they belong to.
+// Constants equal to zero are structural zeros: x * 0, 0 / x and x + 0 record
+// nothing (exact, and so are their derivatives).
+//
+// The same tapes count the step's floating-point operations: each node
+// records whether it is an arithmetic operation (+, -, *, / or a square root;
+// a sign change or |x| is not) and the stage of the step it belongs to, and
+// the operations from which an output of the step can be reached are counted.
+enum { kStRecon = 0, kStLimiter, kStAlpha, kStEval, kStLW, kStFlux, kStUpdate, kNStages };
+thread_local int g_stage = kStRecon;
+inline void stage(int s) { g_stage = s; }
+
 struct Tape {
   std::vector<int32_t> pa, pb;
   std::vector<double> da, db;
+  std::vector<uint8_t> st;  // stage * 2 + (1 if an arithmetic operation)
   void clear() {
     pa.clear();
     pb.clear();
     da.clear();
     db.clear();
+    st.clear();
   }
   size_t size() const { return pa.size(); }
-  int32_t push(int32_t a, double ga, int32_t b, double gb) {
+  int32_t push(int32_t a, double ga, int32_t b, double gb, bool flop) {
     pa.push_back(a);
     da.push_back(ga);
     pb.push_back(b);
     db.push_back(gb);
+    st.push_back(uint8_t(g_stage * 2 + (flop ? 1 : 0)));
     return int32_t(pa.size() - 1);
   }
   // adj: seeded adjoints of the nodes (size() entries); on return the
@@ -120,6 +134,16 @@ struct Tape {
       if (pb[k] >= 0) adj[pb[k]] += db[k] * g;
     }
   }
+  // live: the nodes marked on entry (the outputs); on return every node an
+  // output depends on.  Adds the arithmetic operations among them to count.
+  void count_live(std::vector<char>& live, uint64_t count[kNStages]) const {
+    for (size_t k = pa.size(); k-- > 0;) {
+      if (!live[k]) continue;
+      if (pa[k] >= 0) live[pa[k]] = 1;
+      if (pb[k] >= 0) live[pb[k]] = 1;
+      if (st[k] & 1) ++count[st[k] >> 1];
+    }
+  }
 };
 thread_local Tape* g_tape = nullptr;
 
@@ -130,16 +154,29 @@ struct Rev {
   Rev(double a) : v(a), i(-1) {}
   Rev(double a, int32_t k) : v(a), i(k) {}
 };
-inline Rev rev_node(double v, int32_t a, double ga, int32_t b, double gb) {
+inline bool szero(Rev a) { return a.i < 0 && a.v == 0.0; }
+inline Rev rev_node(double v, int32_t a, double ga, int32_t b, double gb, bool flop = true) {
   if (a < 0 && b < 0) return Rev(v);
-  return Rev(v, g_tape->push(a, ga, b, gb));
+  return Rev(v, g_tape->push(a, ga, b, gb, flop));
 }
-inline Rev rev_leaf(double v) { return Rev(v, g_tape->push(-1, 0.0, -1, 0.0)); }
-inline Rev operator+(Rev a, Rev b) { return rev_node(a.v + b.v, a.i, 1.0, b.i, 1.0); }
-inline Rev operator-(Rev a, Rev b) { return rev_node(a.v - b.v, a.i, 1.0, b.i, -1.0); }
-inline Rev operator-(Rev a) { return rev_node(-a.v, a.i, -1.0, -1, 0.0); }
-inline Rev operator*(Rev a, Rev b) { return rev_node(a.v * b.v, a.i, b.v, b.i, a.v); }
+inline Rev rev_leaf(double v) { return Rev(v, g_tape->push(-1, 0.0, -1, 0.0, false)); }
+inline Rev operator-(Rev a) { return rev_node(-a.v, a.i, -1.0, -1, 0.0, false); }
+inline Rev operator+(Rev a, Rev b) {
+  if (szero(a)) return b;
+  if (szero(b)) return a;
+  return rev_node(a.v + b.v, a.i, 1.0, b.i, 1.0);
+}
+inline Rev operator-(Rev a, Rev b) {
+  if (szero(b)) return a;
+  if (szero(a)) return -b;
+  return rev_node(a.v - b.v, a.i, 1.0, b.i, -1.0);
+}
+inline Rev operator*(Rev a, Rev b) {
+  if (szero(a) || szero(b)) return Rev(0.0);
+  return rev_node(a.v * b.v, a.i, b.v, b.i, a.v);
+}
 inline Rev operator/(Rev a, Rev b) {
+  if (szero(a)) return Rev(0.0);
   const double q = a.v / b.v;
   return rev_node(q, a.i, 1.0 / b.v, b.i, -q / b.v);
 }
@@ -147,61 +184,10 @@ inline Rev& operator+=(Rev& a, Rev b) { a = a + b; return a; }
 inline Rev& operator-=(Rev& a, Rev b) { a = a - b; return a; }
 inline Rev& operator*=(Rev& a, Rev b) { a = a * b; return a; }
 inline double val(Rev a) { return a.v; }
-inline Rev absval(Rev a) { return rev_node(std::fabs(a.v), a.i, sgn0(a.v), -1, 0.0); }
+inline Rev absval(Rev a) { return rev_node(std::fabs(a.v), a.i, sgn0(a.v), -1, 0.0, false); }
 inline Rev sqrtv(Rev a) {
   const double r = std::sqrt(a.v);
   return rev_node(r, a.i, 0.5 / r, -1, 0.0);
-}
-
-// Operation counting.  A Cnt number counts every +, -, *, / and square root
-// applied to it (sign changes and |x| are free) into the calling thread's
-// counter of the current stage.  Constants equal to zero are structural
-// zeros: operations with them (x * 0, x + 0, 0 / x) are not counted and give
-// a structural zero or the other operand, so that e.g. the unused parts of a
-// hyper-dual number cost nothing.
-enum { kStRecon = 0, kStLimiter, kStAlpha, kStEval, kStLW, kStFlux, kStUpdate, kNStages };
-thread_local int g_stage = kStRecon;
-thread_local uint64_t g_flops[kNStages] = {};
-inline void stage(int s) { g_stage = s; }
-
-struct Cnt {
-  double v;
-  bool z;  // structural zero
-  Cnt() : v(0), z(true) {}
-  Cnt(double a) : v(a), z(a == 0.0) {}
-  Cnt(double a, bool zz) : v(a), z(zz) {}
-};
-inline Cnt counted(double v) {
-  ++g_flops[g_stage];
-  return Cnt(v, false);
-}
-inline Cnt operator+(Cnt a, Cnt b) {
-  if (a.z) return b;
-  if (b.z) return a;
-  return counted(a.v + b.v);
-}
-inline Cnt operator-(Cnt a) { return Cnt(-a.v, a.z); }
-inline Cnt operator-(Cnt a, Cnt b) {
-  if (b.z) return a;
-  if (a.z) return -b;
-  return counted(a.v - b.v);
-}
-inline Cnt operator*(Cnt a, Cnt b) {
-  if (a.z || b.z) return Cnt(0.0, true);
-  return counted(a.v * b.v);
-}
-inline Cnt operator/(Cnt a, Cnt b) {
-  if (a.z) return Cnt(0.0, true);
-  return counted(a.v / b.v);
-}
-inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
-inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
-inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
-inline double val(Cnt a) { return a.v; }
-inline Cnt absval(Cnt a) { return Cnt(std::fabs(a.v), a.z); }
-inline Cnt sqrtv(Cnt a) {
-  if (a.z) return a;
-  return counted(std::sqrt(a.v));
 }
 
 // Hyper-dual number a + e1 b1 + e2 b2 + e1 e2 b12 over scalar T
@@ -1133,24 +1119,77 @@ int vjp_step(const Mesh& M, const double* s, const double* lam_out, double* lam_
 }
 
 // Operation counts of one step at the state s, per stage (kSt*), summed over
-// the cells: the reconstructions of all cells, then the updates of all cells
-// (each cell's update evaluates the flux through its three faces, so every
-// interior edge is evaluated twice, once from each side).
+// the cells: the live arithmetic operations of every cell's reconstruction
+// (those its reconstruction fields depend on) and of every cell's update (those
+// its new state depends on; each cell evaluates the flux through its three
+// faces, so every interior edge is evaluated twice, once from each side).
 int count_step(const Mesh& M, const double* s, double dt, uint64_t out[kNStages]) {
   const int m = M.m;
   const int64_t N = M.N;
   const size_t n3 = size_t(3 * m) * N;
-  std::vector<Cnt> sc(n3);
-  for (size_t i = 0; i < n3; ++i) sc[i] = Cnt(s[i], false);
-  for (int k = 0; k < kNStages; ++k) g_flops[k] = 0;
-  std::vector<Recon<Cnt>> R(N);
+  for (int k = 0; k < kNStages; ++k) out[k] = 0;
+  std::vector<Recon<double>> R(N);
   for (int64_t k = 0; k < N; ++k)
-    if (!reconstruct(M, sc.data(), k, R[k])) return -3;
+    if (!reconstruct(M, s, k, R[k])) return -3;
+  Tape tape;
+  g_tape = &tape;
+  std::vector<Rev> srev(n3);
+  std::vector<char> live;
+  for (size_t i = 0; i < n3; ++i) srev[i] = Rev(s[i]);
+  std::vector<Recon<Rev>> Rrev(N);
   for (int64_t k = 0; k < N; ++k) {
-    Cnt Wn[4], Vn[4], Yn[4];
-    update_cell(M, sc.data(), R, k, dt, Wn, Vn, Yn);
+    // the reconstruction of cell k
+    tape.clear();
+    int64_t cells[4];
+    const int nc = stencil_cells(M, k, cells);
+    for (int j = 0; j < nc; ++j)
+      for (int b = 0; b < 3 * m; ++b) {
+        const size_t ix = size_t(b) * N + cells[j];
+        srev[ix] = rev_leaf(s[ix]);
+      }
+    Recon<Rev> Rk;
+    reconstruct(M, srev.data(), k, Rk);
+    live.assign(tape.size(), 0);
+    recon_fields(Rk, m, [&](Rev& x) {
+      if (x.i >= 0) live[x.i] = 1;
+    });
+    tape.count_live(live, out);
+    for (int j = 0; j < nc; ++j)
+      for (int b = 0; b < 3 * m; ++b) {
+        const size_t ix = size_t(b) * N + cells[j];
+        srev[ix] = Rev(s[ix]);
+      }
+    // the update of cell k from the reconstructions of its stencil
+    tape.clear();
+    for (int j = 0; j < nc; ++j) {
+      const int64_t c = cells[j];
+      for (int q = 0; q < m; ++q) srev[size_t(q) * N + c] = rev_leaf(s[size_t(q) * N + c]);
+      Recon<Rev>& rr = Rrev[c];
+      const Recon<double>& rd = R[c];
+      rr.cx = rd.cx;
+      rr.cy = rd.cy;
+      for (int l = 0; l < 4; ++l)
+        for (int q = 0; q < m; ++q)
+          for (int i = 0; i < 6; ++i) rr.p[l][q][i] = rd.p[l][q][i] == 0.0 && l > 0 && i > 2
+                                                          ? Rev(0.0)
+                                                          : rev_leaf(rd.p[l][q][i]);
+      for (int q = 0; q < m; ++q) {
+        for (int l = 0; l < 4; ++l) rr.omega[q][l] = rev_leaf(rd.omega[q][l]);
+        rr.theta[q] = rev_leaf(rd.theta[q]);
+        rr.wbar[q] = rev_leaf(rd.wbar[q]);
+      }
+    }
+    Rev Wn[4], Vn[4], Yn[4];
+    update_cell(M, srev.data(), Rrev, k, dt, Wn, Vn, Yn);
+    live.assign(tape.size(), 0);
+    for (int q = 0; q < m; ++q)
+      for (const Rev& x : {Wn[q], Vn[q], Yn[q]})
+        if (x.i >= 0) live[x.i] = 1;
+    tape.count_live(live, out);
+    for (int j = 0; j < nc; ++j)
+      for (int q = 0; q < m; ++q) srev[size_t(q) * N + cells[j]] = Rev(s[size_t(q) * N + cells[j]]);
   }
-  for (int k = 0; k < kNStages; ++k) out[k] = g_flops[k];
+  g_tape = nullptr;
   return 0;
 }
 
@@ -1482,14 +1521,15 @@ int or_vjp(void* h, const double* s, double* lam, double dt, int64_t nsteps, int
   return 0;
 }
 
-// Floating-point operations of one step at the state s, by stage:
-// out[0] reconstructions (Steps 1-5 with the oracle's per-step least-squares
-// solves), out[1] the scaling limiter, out[2] the flux viscosities, out[3] the
-// evaluation of the final reconstruction at the edge Gauss points (eq.
-// (recon), candidate by candidate), out[4] the Lax-Wendroff procedure, out[5]
-// the Taylor values, fluxes and quadratures of eqs. (fx), (flux), (timeflux),
-// out[6] the update of eqs. (flx) and (derave2d2).  Stages 2-5 are counted
-// from both sides of every edge (each cell evaluates its own faces).
+// Floating-point operations of one step at the state s, by stage (the live
+// operations: those a result of the step depends on): out[0] reconstructions
+// (Steps 1-5 with the oracle's per-step least-squares solves), out[1] the
+// scaling limiter, out[2] the flux viscosities, out[3] the evaluation of the
+// final reconstruction at the edge Gauss points (eq. (recon), candidate by
+// candidate), out[4] the Lax-Wendroff procedure, out[5] the Taylor values,
+// fluxes and quadratures of eqs. (fx), (flux), (timeflux), out[6] the update
+// of eqs. (flx) and (derave2d2).  Stages 2-5 are counted from both sides of
+// every edge (each cell evaluates its own faces).
 int or_count_flops(void* h, const double* s, double dt, double* out) {
   Mesh* M = static_cast<Mesh*>(h);
   M->t_bnd = M->time + 0.5 * dt;

@@ -240,7 +240,10 @@ class OracleMesh:
 
     def count_flops(self, s, dt, t=0.0):
         """Floating-point operations of one step by stage (see or_count_flops):
-        each interior edge's flux work is counted from both of its cells."""
+        the live +, -, *, / and square roots (those a result of the step
+        depends on through arithmetic; values that only decide a branch, such
+        as the losing spectral radius of the flux viscosity, are not counted).
+        Each interior edge's flux work is counted from both of its cells."""
         s = self._check_state(s)
         out = np.zeros(len(self.COUNT_STAGES))
         _lib.or_set_time(self._h, float(t))

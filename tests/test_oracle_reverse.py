@@ -130,3 +130,31 @@ def test_reverse_mode_equals_the_assembled_jacobian_transpose(name):
         err = np.abs(got - ref).max() / np.abs(ref).max()
         print(name, seed, err, flush=True)
         assert err <= 1e-13
+
+
+def test_operation_counts_are_per_cell_and_per_edge_constants():
+    """The live operation counts of one step (the tape's arithmetic nodes that a
+    result depends on) on periodic vortex meshes of 128 and 512 cells: every
+    cell and every edge does the same work up to data-dependent branches (the
+    kappa = 0 case of the weights, the losing radius of the flux viscosity),
+    so the counts per cell (reconstruction, update) and per edge (viscosity,
+    evaluation, Lax-Wendroff, fluxes) agree within 1% between the sizes.  A
+    step of linear advection, whose fluxes are linear, needs far fewer
+    Lax-Wendroff operations per point than the Euler equations."""
+    per = []
+    for n in (8, 16):
+        wl = vortex_workload(n=n)
+        om = OracleMesh.from_workload(wl)
+        c = om.count_flops(wl.state0, om.max_dt(wl.state0, 0.3))
+        per.append(np.array([c["recon"] / om.N, c["update"] / om.N,
+                             *(c[k] / (2 * om.E) for k in ("alpha", "eval", "lax_wendroff", "flux"))]))
+        assert c["limiter"] == 0
+    assert np.allclose(per[0], per[1], rtol=1e-2, atol=0), per
+    wl = advection_workload(n=8)
+    om = OracleMesh.from_workload(wl)
+    c = om.count_flops(wl.state0, om.max_dt(wl.state0, 0.3))
+    lw_adv = c["lax_wendroff"] / (2 * om.E) / 4       # 2 sides x 2 Gauss points per edge evaluation
+    lw_eul = per[1][4] / 4
+    print("vortex per cell / per edge:", per[1], "LW per point and side: advection", lw_adv, "Euler", lw_eul,
+          flush=True)
+    assert 0 < lw_adv < 30 and lw_eul > 500
