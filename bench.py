@@ -28,12 +28,33 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+# Algorithmic bytes of one Euler cell-step in FP64 (mixed): the state read and
+# written once, the reconstruction tables, geometry and connectivity once, 1.5
+# edge records per cell (73 table entries per cell; the factored tables of
+# this library hold 53).
+ALG_BYTES_PER_CELL_STEP = {"fp64": 976, "mixed": 542}
+# Algorithmic FP64 operations of the Euler edge stage per edge: the oracle's
+# live operation count (the arithmetic a result of the step depends on) of the
+# flux viscosity (15), the Lax-Wendroff procedure (3,232) and the Taylor
+# values, normal fluxes and quadratures (757) for the edge's two sides and two
+# Gauss points, evaluated once; the evaluation of the reconstruction at the
+# points is left out (the oracle evaluates the four candidates, the edge kernel
+# the combined polynomial).  The CPU leg recounts it with the oracle
+# (cpu_baseline.oracle_flops) and tests/test_oracle_reverse.py checks this
+# constant against the oracle.
+EDGE_ALG_FLOP_PER_EDGE = 4004
+# Algorithmic FP64 operations of one whole Euler cell-step by the same count
+# (reconstruction 1,483 per cell, the four edge stages 5,412 per edge, 1.5
+# edges per cell, update 16 per cell).
+ALG_FLOP_PER_CELL_STEP = 9617
 # FP64 flops the Euler edge kernel executes per edge (two sides x two Gauss
 # points: evaluation of R, Lax-Wendroff jets, three offset fluxes, side terms,
 # LLF combination), from the SQ_INSTS_VALU_FLOPS_FP64 counter x 64 lanes / E on
 # the 204,800-triangle mesh; the arithmetic has no data-dependent paths on
 # interior edges.
 EDGE_FP64_FLOP_PER_EDGE = 3493
+# timed repeats of the K steps; the value is their median
+REPEATS = 5
 CSRC = os.path.join(ROOT, "paper_2607_10809_amd", "csrc")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_euler_vortex_204800.md")
 
@@ -154,23 +175,33 @@ def gpu_leg(wl, steps, warmup, precision):
     # the timed region: the same steps recorded once into a HIP graph of
     # `chunk` steps and replayed (no host work between the kernels)
     chunk = 100 if steps % 100 == 0 else (steps if steps % 2 == 0 else 0)
+    reps = []
     if chunk:
         a = bufs[pos % 2]
         b = bufs[(pos + 1) % 2]
         graph = mesh.capture_steps(a, b, dt, chunk)
         graph.replay()                      # warm replay
         torch.cuda.synchronize()
-        t_wall0 = time.perf_counter()
-        ev0.record(stream)
-        for _ in range(steps // chunk):
-            graph.replay()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        t_wall = time.perf_counter() - t_wall0
-        ms = ev0.elapsed_time(ev1)
+        for _ in range(REPEATS):
+            t_wall0 = time.perf_counter()
+            ev0.record(stream)
+            for _ in range(steps // chunk):
+                graph.replay()
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            reps.append((ev0.elapsed_time(ev1), time.perf_counter() - t_wall0))
         del graph
     else:
-        ms, t_wall = ms_eager, ms_eager * 1e-3
+        for _ in range(REPEATS):
+            t_wall0 = time.perf_counter()
+            ev0.record(stream)
+            pos = run(steps, pos)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            reps.append((ev0.elapsed_time(ev1), time.perf_counter() - t_wall0))
+    reps.sort()
+    ms, t_wall = reps[len(reps) // 2]
+    rep_ms = [r[0] for r in reps]
     flags = mesh.check_state(bufs[pos % 2][0])
     # per-kernel durations with events around each kernel (separate profiled loop)
     nprof = min(steps, 2000)
@@ -179,7 +210,7 @@ def gpu_leg(wl, steps, warmup, precision):
     kms, nk = mesh.profile_end()
     torch.cuda.synchronize()
     return dict(mesh=mesh, dt=dt, ms=ms, ms_eager=ms_eager, graph_chunk=chunk, wall=t_wall, flags=flags,
-                kernel_ms=[k / nk for k in kms])
+                kernel_ms=[k / nk for k in kms], rep_ms=rep_ms)
 
 
 def adjoint_leg(wl, nsteps=200, ckpt=20, precision="fp64"):
@@ -263,18 +294,50 @@ def mixed_error_leg(wl):
 
 
 def cpu_model():
+    """The host CPU as lscpu describes it (model, sockets, cores, threads,
+    clock), else /proc/cpuinfo's model name."""
+    import subprocess
+    info = {}
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
-    except OSError:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)",
+                     "CPU max MHz", "L3 cache"):
+                info[k] = v.strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return None
+    if "Model name" not in info:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    info["Model name"] = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return info or None
 
 
 def cpu_leg(wl, budget_s=12.0, budget_1t_s=5.0):
-    """The oracle on the host cores (all of OMP_NUM_THREADS, then one thread)."""
+    """The oracle on the host cores (all of OMP_NUM_THREADS, then one thread),
+    compiled for this host (g++ -O3 -march=native -fopenmp) into a temporary
+    directory; and the oracle's live operation count of one step."""
+    import tempfile
+    from oracle import oracle as orc
+    build = orc.use_native_build(tempfile.mkdtemp(prefix="hwe_oracle_"))
     from oracle import OracleMesh
+    from workloads import vortex_workload
+    small = vortex_workload(n=16)
+    oc = OracleMesh.from_workload(small)
+    c = oc.count_flops(small.state0, oc.max_dt(small.state0, small.cfl))
+    per_edge = {k: c[k] / (2 * oc.E) for k in ("alpha", "eval", "lax_wendroff", "flux")}
+    flops = {"per_cell": {"recon": c["recon"] / oc.N, "update": c["update"] / oc.N},
+             "per_edge": {k: round(v, 2) for k, v in per_edge.items()},
+             "edge_stage_per_edge": round(per_edge["alpha"] + per_edge["lax_wendroff"] + per_edge["flux"], 1),
+             "per_cell_step": round((c["recon"] + c["update"]) / oc.N + sum(per_edge.values()) * oc.E / oc.N, 1),
+             "mesh": f"vortex, 16x16 split squares ({oc.N} triangles), one step"}
+    del oc
     om = OracleMesh.from_workload(wl)
     dt = om.max_dt(wl.state0, wl.cfl)
 
@@ -294,7 +357,7 @@ def cpu_leg(wl, budget_s=12.0, budget_1t_s=5.0):
                 sample=f"{n} full FP64 steps of the 204,800-triangle vortex mesh after one warm-up step "
                        f"({el:.1f} s wall)",
                 one_thread={"value": om.N * n1 / el1, "steps": n1, "seconds": round(el1, 2)},
-                cpu_model=cpu_model())
+                build=build, cpu_model=cpu_model(), oracle_flops=flops)
 
 
 def small_configs_leg(steps=500, warmup=20):
@@ -387,6 +450,8 @@ def main():
                     help="skip the run of both precisions to the vortex's final time (mixed-vs-FP64 error)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 20 device copies of 256 MiB (reference for HBM byte counters)")
+    ap.add_argument("--c4-only", action="store_true",
+                    help="only the 980,000-triangle Riemann leg (for counter runs); prints its JSON")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the benchmark runs on one GPU only; run with --gpus 1", file=sys.stderr)
@@ -405,6 +470,9 @@ def main():
         return
     from paper_2607_10809_amd import _lib
     _lib.load_library()
+    if args.c4_only:
+        print(json.dumps({"riemann_980k": c4_leg(args.steps, args.warmup)}), flush=True)
+        return
     from workloads import vortex_workload
 
     log("building workload ...")
@@ -449,10 +517,18 @@ def main():
     t_dom = f64["kernel_ms"][names.index(dom)] * 1e-3
     gbps = kb64[dom] / t_dom / 1e9
     if dom == "edge":
-        tflops = EDGE_FP64_FLOP_PER_EDGE * E / t_dom / 1e12
+        tflops = EDGE_ALG_FLOP_PER_EDGE * E / t_dom / 1e12
+        xtflops = EDGE_FP64_FLOP_PER_EDGE * E / t_dom / 1e12
         roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4),
-                    "per_launch_flops": int(EDGE_FP64_FLOP_PER_EDGE * E), "algorithmic_GBps": round(gbps, 1)}
+                    "per_launch_flops": int(EDGE_ALG_FLOP_PER_EDGE * E),
+                    "flops_per_unit": {"per_edge": EDGE_ALG_FLOP_PER_EDGE,
+                                       "source": "oracle live operation count: viscosity + Lax-Wendroff + "
+                                                 "Taylor values and fluxes, two sides x two Gauss points"},
+                    "executed": {"per_launch_flops": int(EDGE_FP64_FLOP_PER_EDGE * E), "TFLOPs": round(xtflops, 2),
+                                 "frac": round(xtflops / FP64_VECTOR_PEAK_TFLOPS, 4),
+                                 "source": "SQ_INSTS_VALU_FLOPS_FP64 x 64 / E"},
+                    "algorithmic_GBps": round(gbps, 1)}
     else:
         roofline = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbps / HBM_PEAK_GBS, 4)}
@@ -473,6 +549,15 @@ def main():
     if copy_gbps:
         roofline["hbm_kernel"]["frac_of_copy"] = round(rec_gbps / copy_gbps, 4)
     step_bytes = sum(kb64.values())
+    ms64, msm = f64["ms"] / args.steps, mix["ms"] / args.steps
+    step_roofline = {
+        "hbm": {prec: {"alg_bytes_per_cell_step": ALG_BYTES_PER_CELL_STEP[prec],
+                       "achieved_GBps": round(v * ALG_BYTES_PER_CELL_STEP[prec] / 1e9, 1),
+                       "frac": round(v * ALG_BYTES_PER_CELL_STEP[prec] / 1e9 / HBM_PEAK_GBS, 4)}
+                for prec, v in (("fp64", value), ("mixed", value_mixed))},
+        "alu_fp64": {"alg_flops_per_cell_step": ALG_FLOP_PER_CELL_STEP,
+                     "achieved_TFLOPs": round(value * ALG_FLOP_PER_CELL_STEP / 1e12, 2),
+                     "frac": round(value * ALG_FLOP_PER_CELL_STEP / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4)}}
     out = {
         "metric": "cell-steps/s FP64 vs FP32 + adjoint/forward time ratio, Euler 204,800 tris",
         "value": value,
@@ -480,7 +565,10 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": f64["ms"] / args.steps,
+        "ms_per_step": ms64,
+        "repeats": {"count": REPEATS, "statistic": "median",
+                    "ms_per_step": {"fp64": [round(r / args.steps, 5) for r in f64["rep_ms"]],
+                                    "mixed": [round(r / args.steps, 5) for r in mix["rep_ms"]]}},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -489,7 +577,7 @@ def main():
         "config": {"workload": f"euler isentropic vortex, periodic [0,10]^2, {args.n}x{args.n} split squares "
                                f"+-0.1h jitter seed 3 ({N} triangles)", "cells": N, "edges": E,
                    "dt": f64["dt"], "parallelism": "1 GPU"},
-        "mixed": {"value": value_mixed, "ms_per_step": mix["ms"] / args.steps, "dtype": "f32 bulk + f64 averages/weights",
+        "mixed": {"value": value_mixed, "ms_per_step": msm, "dtype": "f32 bulk + f64 averages/weights",
                   "speedup_vs_fp64": value_mixed / value, "error_vs_fp64": merr},
         "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": {"fp64": adj, "mixed": adjm,
@@ -499,6 +587,7 @@ def main():
                       "mixed": round(sum(kbm.values()) / (mix["ms"] / args.steps * 1e-3) / 1e9, 1)},
         "kernels": per_kernel,
         "roofline": roofline,
+        "step_roofline": step_roofline,
         "state_flags": {"fp64": f64["flags"], "mixed": mix["flags"]},
         "riemann_980k": c4,
         "small_configs": small,

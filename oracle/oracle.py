@@ -29,7 +29,8 @@ class _Opts(C.Structure):
 
 
 def build_oracle(force: bool = True) -> str:
-    """Compile the oracle with g++ (OpenMP, -O2, no machine-specific flags)."""
+    """Compile the oracle with g++ (OpenMP, -O2, no machine-specific flags: the
+    build travels to other hosts)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC]
         subprocess.check_call(cmd)
@@ -38,6 +39,20 @@ def build_oracle(force: bool = True) -> str:
 
 
 _lib = None
+
+
+def use_native_build(dest_dir):
+    """Compile the oracle for the host it runs on (g++ -O3 -march=native
+    -fopenmp) into dest_dir and load that build; must precede any other use of
+    the oracle in the process.  Returns the compile command."""
+    global _LIB
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    lib = os.path.join(dest_dir, "libhwe_oracle_native.so")
+    cmd = ["g++", "-O3", "-march=native", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", lib, _SRC]
+    subprocess.check_call(cmd)
+    _LIB = lib
+    return " ".join(cmd[:6])
 
 
 def _load():

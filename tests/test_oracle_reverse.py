@@ -158,3 +158,17 @@ def test_operation_counts_are_per_cell_and_per_edge_constants():
     print("vortex per cell / per edge:", per[1], "LW per point and side: advection", lw_adv, "Euler", lw_eul,
           flush=True)
     assert 0 < lw_adv < 30 and lw_eul > 500
+
+
+def test_benchmark_flop_constants_are_the_oracle_counts():
+    """bench.py's algorithmic operation counts (edge stage per edge, whole
+    step per cell) are the oracle's live counts on the 512-cell vortex."""
+    import bench
+    wl = vortex_workload(n=16)
+    om = OracleMesh.from_workload(wl)
+    c = om.count_flops(wl.state0, om.max_dt(wl.state0, 0.3))
+    pe = {k: c[k] / (2 * om.E) for k in ("alpha", "eval", "lax_wendroff", "flux")}
+    edge = pe["alpha"] + pe["lax_wendroff"] + pe["flux"]
+    cell_step = (c["recon"] + c["update"]) / om.N + sum(pe.values()) * om.E / om.N
+    assert abs(edge - bench.EDGE_ALG_FLOP_PER_EDGE) <= 1.0, edge
+    assert abs(cell_step - bench.ALG_FLOP_PER_CELL_STEP) <= 1.0, cell_step
