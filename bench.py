@@ -243,6 +243,13 @@ def adjoint_leg(wl, nsteps=200, ckpt=20, precision="fp64"):
     once()
     runs = sorted((once() for _ in range(3)), key=lambda fb: fb[1] / fb[0])
     f, b = runs[1]                          # the run with the median ratio
+    # the gradient itself (density slice, caller order), for the mixed-vs-FP64 error
+    w = w0.clone().requires_grad_(True)
+    g = g0.clone().requires_grad_(True)
+    wT, gT = rollout(mesh, w, g, dt, nsteps, ckpt)
+    (0.5 * ((wT[0] - tgt) ** 2).sum()).backward()
+    torch.cuda.synchronize()
+    grad_rho = mesh.to_host(w.grad, g.grad.double())[0, 0]
     # per-step kernel time: adjoint step vs forward step on the same state
     la, lg = mesh.empty_state()
     la.normal_()
@@ -259,7 +266,7 @@ def adjoint_leg(wl, nsteps=200, ckpt=20, precision="fp64"):
     torch.cuda.synchronize()
     fs, as_ = ev[0].elapsed_time(ev[1]) / 100, ev[1].elapsed_time(ev[2]) / 100
     return {"forward_ms": f, "backward_ms": b, "ratio": b / f, "runs": 3, "steps": nsteps, "ckpt": ckpt,
-            "step_us": fs * 1e3, "adjoint_step_us": as_ * 1e3, "per_step_ratio": as_ / fs}
+            "step_us": fs * 1e3, "adjoint_step_us": as_ * 1e3, "per_step_ratio": as_ / fs, "_grad": grad_rho}
 
 
 def mixed_error_leg(wl):
@@ -498,6 +505,9 @@ def main():
             f"{adj['backward_ms']:.1f} ms, ratio {adj['ratio']:.2f}; per step {adj['adjoint_step_us']:.1f} us vs "
             f"{adj['step_us']:.1f} us")
         adjm = adjoint_leg(wl, precision="mixed")
+        ga, gb = adjm.pop("_grad"), adj.pop("_grad")
+        adjm["gradient_error_vs_fp64"] = {"rel_l2": float(np.linalg.norm(ga - gb) / np.linalg.norm(gb)),
+                                          "rel_max": float(np.abs(ga - gb).max() / np.abs(gb).max())}
     E, m = f64["mesh"].E, f64["mesh"].m
     value = N * args.steps / (f64["ms"] * 1e-3)
     value_mixed = N * args.steps / (mix["ms"] * 1e-3)

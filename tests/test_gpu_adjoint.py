@@ -296,6 +296,54 @@ def test_c5_gradient_against_central_differences(c5):
     assert worst <= 1e-6
 
 
+def test_c5_mixed_gradient_against_fp64_and_central_differences(c5):
+    """The C5 misfit gradient of the mixed path (FP32 bulk, FP64 cell averages,
+    weights and accumulation), through the same 200-step checkpointed rollout,
+    against the FP64 gradient: relative L2 and max errors on the density slice
+    within 1e-5 (the FP32 step's relative rounding, ~1e-7 per step, over 200
+    steps); and against central differences of the mixed misfit on the 32
+    directions within 1e-4 (the FP32 rounding of the forward enters the
+    differences as noise / eps)."""
+    import torch
+    from paper_2607_10809_amd.autograd import rollout
+    wl, mesh64, dt, tgt = c5
+    grads = {}
+    meshes = {"fp64": mesh64, "mixed": _mesh(wl, "mixed")}
+    for prec, mesh in meshes.items():
+        w0, g0 = mesh.to_device(wl.state0)
+        w = w0.clone().requires_grad_(True)
+        g = g0.clone().requires_grad_(True)
+        wT, gT = rollout(mesh, w, g, dt, 200, ckpt=20)
+        loss = 0.5 * ((wT[0] - tgt) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        grads[prec] = mesh.to_host(w.grad, g.grad.double())[0, 0]
+    a, b = grads["mixed"], grads["fp64"]
+    l2 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    mx = float(np.abs(a - b).max() / np.abs(b).max())
+    mesh = meshes["mixed"]
+    w0, g0 = mesh.to_device(wl.state0)
+    dirs = fd_directions(mesh.N, 32)
+    worst = 0.0
+    for k in range(32):
+        v = dirs[k]
+        ad = float(np.dot(a, v))
+        vd = torch.from_numpy(v[mesh.perm]).to(w0.device)
+        best = np.inf
+        for eps in (1e-2, 1e-3):
+            wp = w0.clone()
+            wp[0] += eps * vd
+            wm = w0.clone()
+            wm[0] -= eps * vd
+            fd = (_misfit(mesh, wp, g0, dt, tgt) - _misfit(mesh, wm, g0, dt, tgt)) / (2 * eps)
+            best = min(best, abs(fd - ad) / max(abs(ad), 1e-300))
+        worst = max(worst, best)
+    print(f"C5 mixed gradient vs FP64: rel L2 {l2:.2e}, rel max {mx:.2e}; vs central differences of the mixed "
+          f"misfit, worst of 32 directions {worst:.2e}", flush=True)
+    assert l2 <= 1e-5 and mx <= 1e-5
+    assert worst <= 1e-4
+
+
 def test_checkpointing_does_not_change_the_gradient():
     import torch
     from paper_2607_10809_amd.autograd import rollout
