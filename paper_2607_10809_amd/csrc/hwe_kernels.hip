@@ -71,7 +71,10 @@ __device__ __forceinline__ void store_coeffs_quad(int i, int q, const Real (&a)[
   }
 }
 
-// NPT: the limiter's points per cell (6, or 9 with the 3-point edge rule).
+// NPT: the limiter's points per cell (6, or 9 with the 3-point edge rule);
+// 0 compiles the limiter out (fewer registers, which lets the kernel's waves
+// share a SIMD with a long adjoint wave when a reverse sweep recomputes a
+// segment beside the adjoints).
 template <int EQ, class Real, int NPT>
 __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, const double* __restrict__ wbar,
                                                         const Real* __restrict__ grad,
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
     const Real* tb = reinterpret_cast<const Real*>(stage) + (i % kTile);
     Real a[6];
     recon_from_stencil<EQ, Real>(ic, q, N, NB, P, S, bnd_n, tb, area, wbar, grad, a);
-    if (P.positivity) {
+    if constexpr (NPT > 0) {
       const int lane0 = (threadIdx.x & 63) & ~3;
       Real all[4][6];
       double Wb[4];
@@ -484,7 +487,10 @@ void recon_launch(hwe_mesh_s* M, const Params& P, const double* wbar, const Real
   const DevMesh& d = M->d;
   const int N = int(M->h.N), NB = int(M->h.NB);
   const dim3 grid(grid_for(int64_t(N) * NComp<EQ>::m));
-  if (M->opts.edge_rule == 3 && P.positivity)
+  if (!P.positivity)
+    hipLaunchKernelGGL((recon_kernel<EQ, Real, 0>), grid, dim3(kBlock), 0, st, N, NB, P, wbar, grad, d.nbr, d.bnd_n,
+                       tbl, d.area, d.gpc, R);
+  else if (M->opts.edge_rule == 3)
     hipLaunchKernelGGL((recon_kernel<EQ, Real, 9>), grid, dim3(kBlock), 0, st, N, NB, P, wbar, grad, d.nbr, d.bnd_n,
                        tbl, d.area, d.gpc, R);
   else
