@@ -328,7 +328,7 @@ def cpu_model():
 
 def cpu_leg(wl, budget_s=12.0, budget_1t_s=5.0):
     """The oracle on the host cores (all of OMP_NUM_THREADS, then one thread),
-    compiled for this host (g++ -O3 -march=native -fopenmp) into a temporary
+    compiled for this host (g++ -O3 -march=native -ffp-contract=off -fopenmp) into a temporary
     directory; and the oracle's live operation count of one step."""
     import tempfile
     from oracle import oracle as orc

@@ -44,12 +44,15 @@ _lib = None
 def use_native_build(dest_dir):
     """Compile the oracle for the host it runs on (g++ -O3 -march=native
     -fopenmp) into dest_dir and load that build; must precede any other use of
-    the oracle in the process.  Returns the compile command."""
+    the oracle in the process.  Products are not contracted into fused
+    multiply-adds (-ffp-contract=off), so the build computes what the portable
+    one does, rounding for rounding.  Returns the compile command."""
     global _LIB
     if _lib is not None:
         raise RuntimeError("the oracle library is already loaded")
     lib = os.path.join(dest_dir, "libhwe_oracle_native.so")
-    cmd = ["g++", "-O3", "-march=native", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", lib, _SRC]
+    cmd = ["g++", "-O3", "-march=native", "-ffp-contract=off", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o",
+           lib, _SRC]
     subprocess.check_call(cmd)
     _LIB = lib
     return " ".join(cmd[:6])
