@@ -81,31 +81,54 @@ __global__ __launch_bounds__(kFaceBlock<Real>, sizeof(Real) == 4 ? 2 : 1) void a
   }
   {
     const int f = lane;
-    // the face's edge and neighbour (nbr < 0: boundary face, no neighbour); the
-    // neighbour's loads read the cell itself there and are not used
+    // Every load of the lane is issued before any arithmetic, in two rounds:
+    // what the cell index fixes, then what the face's edge and neighbour fix
+    // (nbr < 0: boundary face, no neighbour; the neighbour's loads then read
+    // the cell itself and are not used).  With one wave per SIMD nothing else
+    // hides a load's latency, so the waits are kept to these two.
     const int ce = cell_edge[f * sN + ic];
     const int nbv = nbr[f * sN + ic];
+    double WK[M], lwK[M], lgxK[M], lgyK[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      WK[q] = wbar[q * sN + ic];
+      lwK[q] = lw[q * sN + ic];
+      lgxK[q] = double(lg[q * sN + ic]);
+      lgyK[q] = double(lg[(M + q) * sN + ic]);
+    }
+    const double iaK = inv_area[ic];
+    const double nlx = double(nl[f * sN + ic]), nly = double(nl[(3 + f) * sN + ic]);
+    Real a[6][M];
+    load_record<6 * M>(R + size_t(ic) * (6 * M), &a[0][0]);
     const int e = ce >> 1, side = ce & 1;
     const bool has = nbv >= 0;
     const int nb = has ? nbv : -1, nc = has ? nbv : ic;
     const double nx = enl[e], ny = enl[sE + e], len = enl[2 * sE + e];
-    const double sigma = side ? -1.0 : 1.0;
-    const double iaK = inv_area[ic];
-    const double nlx = double(nl[f * sN + ic]), nly = double(nl[(3 + f) * sN + ic]);
-    double WK[M], Wn[M], lF[M], lG[M];
     const double ianc = inv_area[nc];
+    double Wc[M], lwn[M], lgxn[M], lgyn[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      Wc[q] = wbar[q * sN + nc];
+      lwn[q] = lw[q * sN + nc];
+      lgxn[q] = double(lg[q * sN + nc]);
+      lgyn[q] = double(lg[(M + q) * sN + nc]);
+    }
+    Real Xg[GP], Yg[GP];
+#pragma unroll
+    for (int g = 0; g < GP; ++g) {
+      Xg[g] = egp[(2 * GP * side + 2 * g) * sE + e];
+      Yg[g] = egp[(2 * GP * side + 2 * g + 1) * sE + e];
+    }
+    asm volatile("" ::: "memory");  // the loads above stay above the arithmetic below
+    const double sigma = side ? -1.0 : 1.0;
+    double Wn[M], lF[M], lG[M];
     const double ian = has ? ianc : 0.0;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
-      WK[q] = wbar[q * sN + ic];
-      const double Wc = wbar[q * sN + nc], lwn = lw[q * sN + nc];
-      const double lgxn = double(lg[q * sN + nc]), lgyn = double(lg[(M + q) * sN + nc]);
-      Wn[q] = has ? Wc : WK[q];
-      const double lwK = lw[q * sN + ic];
-      const double lgxK = double(lg[q * sN + ic]), lgyK = double(lg[(M + q) * sN + ic]);
-      lF[q] = has ? -dt * sigma * (iaK * lwK - ian * lwn) : -dt * iaK * lwK;
-      lG[q] = has ? nlx * (iaK * lgxK - ian * lgxn) + nly * (iaK * lgyK - ian * lgyn)
-                  : iaK * (nlx * lgxK + nly * lgyK);
+      Wn[q] = has ? Wc[q] : WK[q];
+      lF[q] = has ? -dt * sigma * (iaK * lwK[q] - ian * lwn[q]) : -dt * iaK * lwK[q];
+      lG[q] = has ? nlx * (iaK * lgxK[q] - ian * lgxn[q]) + nly * (iaK * lgyK[q] - ian * lgyn[q])
+                  : iaK * (nlx * lgxK[q] + nly * lgyK[q]);
     }
     // SB: a boundary face may be a reflective wall (exterior: the mirror image
     // T Wbar_K, T reflecting the momentum about the face) or hold a prescribed
@@ -175,8 +198,6 @@ __global__ __launch_bounds__(kFaceBlock<Real>, sizeof(Real) == 4 ? 2 : 1) void a
 #pragma unroll
     for (int q = 0; q < M; ++q) lWT[q] = 0.0;
     double sT = 0.0;
-    Real a[6][M];
-    load_record<6 * M>(R + size_t(ic) * (6 * M), &a[0][0]);
     double s = 0.0;
     auto point = [&](int g) {
       // seeds of Gauss point g (weight wg; 1/2 each with 2 points)
@@ -200,8 +221,7 @@ __global__ __launch_bounds__(kFaceBlock<Real>, sizeof(Real) == 4 ? 2 : 1) void a
         }
         sAHw[q] = wall ? sAH[q] : Real(0);
       }
-      const Real X = egp[(2 * GP * side + 2 * g) * sE + e];
-      const Real Y = egp[(2 * GP * side + 2 * g + 1) * sE + e];
+      const Real X = Xg[g], Y = Yg[g];
       Real ADg[M];
       edge_lane_rev<EQ, Real, TR, kWall>(P, dt, a, WK, X, Y, Real(nx), Real(ny), sAH, sAD, sAT, la, lWf, ADg, Wx,
                                          sAHw, lWT);
@@ -345,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
   const int gid = blk * kBlock + threadIdx.x;
   const int i = gid / M, q = gid - (gid / M) * M;
   Real laq[6];
-  double slot[4][3];
+  double slot[4][3], lw0;  // lw0: the face kernel's direct adjoint of the cell average
   if constexpr (EQ == EQ_EUL) {
     // one block per table tile, staged through LDS as in the forward reconstruction
     static_assert(kBlock == kTile * 4, "one Euler block per table tile");
@@ -354,9 +374,10 @@ __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
     Copy tile;
     tile.load(tbl, blk, threadIdx.x);
     const int ic = i < N ? i : N - 1;
-    const Stencil<Real> S = gather_stencil<EQ, Real>(ic, q, N, wbar, grad, nbr);
+    const Stencil<Real> S = gather_stencil<EQ, Real>(ic, q, N, wbar, grad, nbr, area);
 #pragma unroll
     for (int j = 0; j < 6; ++j) laq[j] = lacell[(size_t(ic) * 6 + j) * M + q];
+    lw0 = lwcell[size_t(ic) * M + q];
     tile.store(stage, threadIdx.x);
     __syncthreads();
     if (i >= N) return;  // whole cells: the four lanes of a quad leave together
@@ -364,9 +385,9 @@ __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
     const Real* tb = reinterpret_cast<const Real*>(stage) + (i % kTile);
     if constexpr (NPT > 0) {
       const ScalingLimiterRev<Real, NPT> lim{int(threadIdx.x & 63) & ~3, q, N, i, P.gam, S.W0, gpc};
-      recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tb, area, laq, slot, q, N, wbar, grad, cross, lim);
+      recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tb, laq, slot, q, N, wbar, grad, cross, lim);
     } else {
-      recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tb, area, laq, slot, q, N, wbar, grad, cross);
+      recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tb, laq, slot, q, N, wbar, grad, cross);
     }
     if constexpr (SB) {
       // wall ghosts: the momentum lanes (q = 1, 2 of the quad) exchange the
@@ -382,12 +403,13 @@ __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
     }
   } else {
     if (i >= N) return;
-    const Stencil<Real> S = gather_stencil<EQ, Real>(i, q, N, wbar, grad, nbr);
+    const Stencil<Real> S = gather_stencil<EQ, Real>(i, q, N, wbar, grad, nbr, area);
 #pragma unroll
     for (int j = 0; j < 6; ++j) laq[j] = lacell[(size_t(i) * 6 + j) * M + q];
-    recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tbl + tbl_col(i), area, laq, slot, q, N, wbar, grad, nullptr);
+    lw0 = lwcell[size_t(i) * M + q];
+    recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tbl + tbl_col(i), laq, slot, q, N, wbar, grad, nullptr);
   }
-  slot[0][0] += lwcell[size_t(i) * M + q];
+  slot[0][0] += lw0;
 #pragma unroll
   for (int sl = 0; sl < 4; ++sl)
 #pragma unroll

@@ -723,7 +723,7 @@ struct NoLimiter {
 template <int EQ, class Real, bool SB = false, class Lim = NoLimiter>
 __host__ __device__ __forceinline__ void recon_rev(int i, int NB, const Params& P, const Stencil<Real>& S,
                                                   const double* __restrict__ bnd_n, const Real* __restrict__ tb,
-                                                  const double* __restrict__ area, const Real (&la_in)[6],
+                                                  const Real (&la_in)[6],
                                                   double (&slot)[4][3], int q = 0, int N = 0,
                                                   const double* __restrict__ wbar = nullptr,
                                                   const Real* __restrict__ grad = nullptr,
@@ -821,7 +821,7 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int NB, const Params& 
     cl[f] = Y[f + 1] + pdy[f] * t;
   }
   const double g1 = P.lw[0];
-  const double A0 = area[i];
+  const double A0 = S.A0;
   double w[4], beta[4], wb[4] = {0, 0, 0, 0}, Dl[4] = {0, 0, 0, 0};
   double wave = 0.0, w2 = 0.0, ts = 0.0, kappa = 0.0, ssum = 1.0;
   if (P.linear) {

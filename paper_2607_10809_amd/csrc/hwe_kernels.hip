@@ -96,28 +96,31 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
     // all four component lanes of a cell stay active for the limiter's shuffles
     const bool valid = i < N;
     const int ic = valid ? i : N - 1;
-    const Stencil<Real> S = gather_stencil<EQ, Real>(ic, q, N, wbar, grad, nbr);
-    tile.store(stage, threadIdx.x);
-    __syncthreads();
-    const Real* tb = reinterpret_cast<const Real*>(stage) + (i % kTile);
-    Real a[6];
-    recon_from_stencil<EQ, Real>(ic, q, N, NB, P, S, bnd_n, tb, area, wbar, grad, a);
+    const Stencil<Real> S = gather_stencil<EQ, Real>(ic, q, N, wbar, grad, nbr, area);
+    // the limiter's points, loaded with the stencil rather than after the arithmetic
+    constexpr int kPts = NPT > 0 ? NPT : 1;
+    double px[kPts], py[kPts];
     if constexpr (NPT > 0) {
-      const int lane0 = (threadIdx.x & 63) & ~3;
-      Real all[4][6];
-      double Wb[4];
-      const double w0 = wbar[q * size_t(N) + ic];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-#pragma unroll
-        for (int j = 0; j < 6; ++j) all[c][j] = __shfl(a[j], lane0 + c);
-        Wb[c] = __shfl(w0, lane0 + c);
-      }
-      double px[NPT], py[NPT];
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         px[k] = gpc[(2 * k) * size_t(N) + ic];
         py[k] = gpc[(2 * k + 1) * size_t(N) + ic];
+      }
+    }
+    tile.store(stage, threadIdx.x);
+    __syncthreads();
+    const Real* tb = reinterpret_cast<const Real*>(stage) + (i % kTile);
+    Real a[6];
+    recon_from_stencil<EQ, Real>(ic, q, N, NB, P, S, bnd_n, tb, wbar, grad, a);
+    if constexpr (NPT > 0) {
+      const int lane0 = (threadIdx.x & 63) & ~3;
+      Real all[4][6];
+      double Wb[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) all[c][j] = __shfl(a[j], lane0 + c);
+        Wb[c] = __shfl(S.W0, lane0 + c);
       }
       double th[4];
       positivity_theta<Real, NPT>(P.gam, Wb, all, px, py, th);

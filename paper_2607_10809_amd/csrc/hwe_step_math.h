@@ -102,18 +102,20 @@ template <class Real, int kThreads> struct TileCopy {
 // replaces those values.
 template <class Real> struct Stencil {
   int nbi[3];
-  double W0, Wn[3];
+  double W0, Wn[3], A0;  // A0: the cell's area
   Real V[4], Y[4];
 };
 template <int EQ, class Real>
 __host__ __device__ __forceinline__ Stencil<Real> gather_stencil(int i, int q, int N,
                                                                 const double* __restrict__ wbar,
                                                                 const Real* __restrict__ grad,
-                                                                const int32_t* __restrict__ nbr) {
+                                                                const int32_t* __restrict__ nbr,
+                                                                const double* __restrict__ area) {
   constexpr int M = NComp<EQ>::m;
   Stencil<Real> S;
 #pragma unroll
   for (int f = 0; f < 3; ++f) S.nbi[f] = nbr[f * N + i];
+  S.A0 = area[i];
   S.W0 = wbar[q * N + i];
   S.V[0] = grad[q * N + i];
   S.Y[0] = grad[(M + q) * N + i];
@@ -160,7 +162,6 @@ __host__ __device__ __forceinline__ void recon_from_stencil(int i, int q, int N,
                                                            const Stencil<Real>& S,
                                                            const double* __restrict__ bnd_n,
                                                            const Real* __restrict__ tb,
-                                                           const double* __restrict__ area,
                                                            const double* __restrict__ wbar,
                                                            const Real* __restrict__ grad, Real (&a)[6]) {
   const double W0 = S.W0;
@@ -236,7 +237,7 @@ __host__ __device__ __forceinline__ void recon_from_stencil(int i, int q, int N,
 #pragma unroll
     for (int l = 0; l < 4; ++l) w[l] = P.lw[l];
   } else {
-    const double A0 = area[i];
+    const double A0 = S.A0;
     const double c1 = c[0], c2 = c[1], c3 = c[2], c4 = c[3], c5 = c[4];
     double beta[4];
     beta[0] = A0 * (c1 * c1 + c2 * c2) + A0 * A0 * (4.0 * c3 * c3 + c4 * c4 + 4.0 * c5 * c5);
@@ -287,8 +288,8 @@ __host__ __device__ __forceinline__ void recon_coeffs(int i, int q, int N, int N
                                                      const int32_t* __restrict__ nbr, const double* __restrict__ bnd_n,
                                                      const Real* __restrict__ tb, const double* __restrict__ area,
                                                      Real (&a)[6]) {
-  const Stencil<Real> S = gather_stencil<EQ, Real>(i, q, N, wbar, grad, nbr);
-  recon_from_stencil<EQ, Real>(i, q, N, NB, P, S, bnd_n, tb, area, wbar, grad, a);
+  const Stencil<Real> S = gather_stencil<EQ, Real>(i, q, N, wbar, grad, nbr, area);
+  recon_from_stencil<EQ, Real>(i, q, N, NB, P, S, bnd_n, tb, wbar, grad, a);
 }
 
 template <int EQ, class Real>
