@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kFaceBlock<Real>, sizeof(Real) == 4 ? 2 : 1) void a
       Xg[g] = egp[(2 * GP * side + 2 * g) * sE + e];
       Yg[g] = egp[(2 * GP * side + 2 * g + 1) * sE + e];
     }
-    asm volatile("" ::: "memory");  // the loads above stay above the arithmetic below
+    issue_fence();
     const double sigma = side ? -1.0 : 1.0;
     double Wn[M], lF[M], lG[M];
     const double ian = has ? ianc : 0.0;
@@ -378,6 +378,14 @@ __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
 #pragma unroll
     for (int j = 0; j < 6; ++j) laq[j] = lacell[(size_t(ic) * 6 + j) * M + q];
     lw0 = lwcell[size_t(ic) * M + q];
+    // the gathers arrive with the table tile, before its LDS store and the
+    // barrier (left to itself the compiler issues them after the barrier: a
+    // third round of latency)
+    tile.arrived_all();
+    stencil_arrived(S);
+    arrived(lw0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) arrived(laq[j]);
     tile.store(stage, threadIdx.x);
     __syncthreads();
     if (i >= N) return;  // whole cells: the four lanes of a quad leave together
@@ -439,6 +447,37 @@ __global__ __launch_bounds__(kBlock) void adj_gather_kernel(
   int nbf[3], bkf[3], cef[3];
   double nlxf[3], nlyf[3], nxf[3], nyf[3], lenf[3], sownf[3], sothf[3];
   double WK[M], lwK[M];
+  // the neighbours' values for every face, issued as soon as the neighbour
+  // indices are known (Euler: each component lane loads its own component,
+  // broadcast by DPP later)
+  constexpr int MC = M == 4 ? 1 : M;
+  double sWf[3], sVf[3], sYf[3], lgxnf[3], lgynf[3], ianf[3], Wcf[3][MC], lwcf[3][MC];
+  auto load_neighbours = [&]() {
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const bool has = nbf[f] >= 0;
+      const int nb = has ? nbf[f] : i;
+      const int bk = has ? bkf[f] : 0;
+      sWf[f] = slots[slot_index<M>(nb, 1 + bk, 0, q)];
+      sVf[f] = slots[slot_index<M>(nb, 1 + bk, 1, q)];
+      sYf[f] = slots[slot_index<M>(nb, 1 + bk, 2, q)];
+#pragma unroll
+      for (int c = 0; c < MC; ++c) {
+        const int cq = M == 4 ? q : c;
+        Wcf[f][c] = wbar[cq * sN + nb];
+        lwcf[f][c] = lw[cq * sN + nb];
+      }
+      lgxnf[f] = double(lg[q * sN + nb]);
+      lgynf[f] = double(lg[(M + q) * sN + nb]);
+      ianf[f] = inv_area[nb];
+    }
+  };
+  // the cell's own values
+  const double iaK = inv_area[i];
+  const double lgxK = double(lg[q * sN + i]), lgyK = double(lg[(M + q) * sN + i]);
+  double aW = slots[slot_index<M>(i, 0, 0, q)];
+  double aV = slots[slot_index<M>(i, 0, 1, q)];
+  double aY = slots[slot_index<M>(i, 0, 2, q)];
   if constexpr (M == 4) {
     // the quad's four lanes are the cell's components: a value the whole quad
     // needs is loaded once (lane f for face f) and broadcast by DPP
@@ -456,6 +495,11 @@ __global__ __launch_bounds__(kBlock) void adj_gather_kernel(
       nbf[f] = quad_bcast(nb_l, f);
       bkf[f] = quad_bcast(bk_l, f);
       cef[f] = quad_bcast(ce_l, f);
+    }
+    load_neighbours();
+    issue_fence();
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
       nlxf[f] = quad_bcast(nlx_l, f);
       nlyf[f] = quad_bcast(nly_l, f);
       nxf[f] = quad_bcast(nx_l, f);
@@ -485,46 +529,38 @@ __global__ __launch_bounds__(kBlock) void adj_gather_kernel(
       sownf[f] = sface[f * sN + i];
       sothf[f] = sface[(has ? bkf[f] : 0) * sN + (has ? nbf[f] : i)];
     }
+    load_neighbours();
 #pragma unroll
     for (int c = 0; c < M; ++c) {
       WK[c] = wbar[c * sN + i];
       lwK[c] = lw[c * sN + i];
     }
+    issue_fence();
   }
-  const double iaK = inv_area[i];
-  const double lgxK = double(lg[q * sN + i]), lgyK = double(lg[(M + q) * sN + i]);
-  double aW = slots[slot_index<M>(i, 0, 0, q)];
-  double aV = slots[slot_index<M>(i, 0, 1, q)];
-  double aY = slots[slot_index<M>(i, 0, 2, q)];
   double aWall[M];  // flux-viscosity adjoint, all components
 #pragma unroll
   for (int c = 0; c < M; ++c) aWall[c] = 0.0;
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const bool has = nbf[f] >= 0;
-    const int nb = has ? nbf[f] : i;
-    const int bk = has ? bkf[f] : 0;
     const int side = cef[f] & 1;
-    const double sW = slots[slot_index<M>(nb, 1 + bk, 0, q)];
-    const double sV = slots[slot_index<M>(nb, 1 + bk, 1, q)];
-    const double sY = slots[slot_index<M>(nb, 1 + bk, 2, q)];
+    const double sW = sWf[f], sV = sVf[f], sY = sYf[f];
     double Wn[M], lwn[M];
     if constexpr (M == 4) {
-      const double Wq = wbar[q * sN + nb], lwq = lw[q * sN + nb];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        Wn[c] = quad_bcast(Wq, c);
-        lwn[c] = quad_bcast(lwq, c);
+        Wn[c] = quad_bcast(Wcf[f][0], c);
+        lwn[c] = quad_bcast(lwcf[f][0], c);
       }
     } else {
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        Wn[c] = wbar[c * sN + nb];
-        lwn[c] = lw[c * sN + nb];
+        Wn[c] = Wcf[f][c];
+        lwn[c] = lwcf[f][c];
       }
     }
-    const double lgxn = double(lg[q * sN + nb]), lgyn = double(lg[(M + q) * sN + nb]);
-    const double ian = inv_area[nb];
+    const double lgxn = lgxnf[f], lgyn = lgynf[f];
+    const double ian = ianf[f];
     const double nlx = nlxf[f], nly = nlyf[f];
     const double nx = nxf[f], ny = nyf[f], len = lenf[f];
     const double sown = sownf[f], soth = sothf[f];

@@ -107,6 +107,17 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
         py[k] = gpc[(2 * k + 1) * size_t(N) + ic];
       }
     }
+    // the table tile and every gather arrive together, in two rounds (the
+    // neighbour indices, then the rest), before the LDS store and the barrier
+    tile.arrived_all();
+    stencil_arrived(S);
+    if constexpr (NPT > 0) {
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        arrived(px[k]);
+        arrived(py[k]);
+      }
+    }
     tile.store(stage, threadIdx.x);
     __syncthreads();
     const Real* tb = reinterpret_cast<const Real*>(stage) + (i % kTile);

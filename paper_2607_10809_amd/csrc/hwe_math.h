@@ -129,6 +129,23 @@ __host__ __device__ __forceinline__ double prescribed_component(const Params& P,
   return q == 0 ? W[0] : (q == 1 ? W[1] : (q == 2 ? W[2] : W[3]));
 }
 
+// Nothing is scheduled across this point: every load issued above it is in
+// flight before the arithmetic below waits for any of them.  A kernel whose
+// waves cannot hide each other's latency (one or two per SIMD) gathers its
+// inputs this way in as few rounds as their index dependences allow, where the
+// compiler would otherwise issue many loads next to their first use.
+__host__ __device__ __forceinline__ void issue_fence() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
+// The value of x is needed here (it is an operand of an empty asm statement):
+// its load is issued above this point and waited for at it.  Used where the
+// compiler would otherwise move a gather below a barrier, next to its use.
+template <class T> __device__ __forceinline__ void arrived(const T& x) { asm volatile("" ::"v"(x)); }
+__device__ __forceinline__ void arrived(const uint4& x) { asm volatile("" ::"v"(x.x), "v"(x.y), "v"(x.z), "v"(x.w)); }
+
 // 1/x for the FP32 bulk of the mixed path: the hardware reciprocal (within an
 // ulp of the quotient); FP64 keeps the correctly rounded division.
 __host__ __device__ __forceinline__ float recip(float x) {

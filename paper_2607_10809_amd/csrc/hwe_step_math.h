@@ -88,6 +88,11 @@ template <class Real, int kThreads> struct TileCopy {
     for (int r = 0; r < kFull; ++r) buf[r] = src[t + r * kThreads];
     rest = src[t + kFull * kThreads - (t < kRest ? 0 : kThreads)];
   }
+  __device__ __forceinline__ void arrived_all() const {
+#pragma unroll
+    for (int r = 0; r < kFull; ++r) arrived(buf[r]);
+    arrived(rest);
+  }
   __device__ __forceinline__ void store(uint4* stage, int t) const {
 #pragma unroll
     for (int r = 0; r < kFull; ++r) stage[t + r * kThreads] = buf[r];
@@ -105,6 +110,19 @@ template <class Real> struct Stencil {
   double W0, Wn[3], A0;  // A0: the cell's area
   Real V[4], Y[4];
 };
+// Every gathered value of S has arrived (arrived() in hwe_math.h).
+template <class Real> __device__ __forceinline__ void stencil_arrived(const Stencil<Real>& S) {
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    arrived(S.Wn[f]);
+    arrived(S.V[f + 1]);
+    arrived(S.Y[f + 1]);
+  }
+  arrived(S.W0);
+  arrived(S.A0);
+  arrived(S.V[0]);
+  arrived(S.Y[0]);
+}
 template <int EQ, class Real>
 __host__ __device__ __forceinline__ Stencil<Real> gather_stencil(int i, int q, int N,
                                                                 const double* __restrict__ wbar,
