@@ -352,11 +352,14 @@ def test_checkpointing_does_not_change_the_gradient():
     w0, g0 = mesh.to_device(wl.state0)
     dt = mesh.max_dt(w0, wl.cfl)
     grads = []
-    # checkpoint intervals, with and without the recomputation overlapping the adjoints
-    for ck, overlap in ((1, True), (7, True), (7, False), (40, True)):
+    # checkpoint intervals, with and without the recomputation overlapping the
+    # adjoints, with the last segment kept from the forward pass or recomputed
+    # (a last segment of 5 steps with ckpt 7)
+    for ck, overlap, keep in ((1, True, True), (7, True, True), (7, False, True), (7, True, False),
+                              (40, True, True), (40, True, False), (1, False, False)):
         w = w0.clone().requires_grad_(True)
         g = g0.clone().requires_grad_(True)
-        wT, gT = rollout(mesh, w, g, dt, 40, ckpt=ck, overlap=overlap)
+        wT, gT = rollout(mesh, w, g, dt, 40, ckpt=ck, overlap=overlap, keep_last=keep)
         (wT[0] ** 2).sum().backward()
         torch.cuda.synchronize()
         grads.append((w.grad.clone(), g.grad.clone()))
