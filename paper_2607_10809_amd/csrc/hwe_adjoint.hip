@@ -28,6 +28,8 @@
 // the reconstruction reverse (template NPT = its points per cell).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "hwe_adjoint_math.h"
 #include "hwe_internal.h"
 
@@ -41,10 +43,21 @@ constexpr int kBlock = 256;
 
 
 // Stencil-slot adjoints, cell-major: cell i's record holds 4 slots (itself,
-// then its neighbours across faces 0-2) x 3 fields (Wbar, V, Y) x M components,
-// so a neighbour's slot for this cell is one contiguous 3M-value run.
-template <int M> __device__ __forceinline__ size_t slot_index(int i, int sl, int fl, int q) {
-  return size_t(i) * (12 * M) + size_t((sl * 3 + fl) * M + q);
+// then its neighbours across faces 0-2) x 3 fields (Wbar, V, Y) x M
+// components.  The Wbar field is FP64 (it adds into the cell-average adjoint,
+// FP64 in both precisions): a [N][4][M] double block; the V and Y fields are
+// Real, like the derivative-average adjoints they add into: a [N][4][2][M]
+// block after it (FP32 in the mixed path, which halves their traffic).  A
+// neighbour's slot for this cell is one M-run of each block.
+template <int M> __device__ __forceinline__ size_t slot_w(int i, int sl, int q) {
+  return (size_t(i) * 4 + sl) * M + q;
+}
+template <int M> __device__ __forceinline__ size_t slot_vy(int i, int sl, int fl, int q) {
+  return ((size_t(i) * 4 + sl) * 2 + (fl - 1)) * M + q;
+}
+template <int M, class Real, class P> __device__ __forceinline__ auto slot_vy_block(P* slots, int N) {
+  using R = std::conditional_t<std::is_const_v<P>, const Real, Real>;
+  return reinterpret_cast<R*>(slots + size_t(N) * 4 * M);
 }
 
 // GP: Gauss points per edge (2, or 3 for the 3-point rule; egp holds 2 GP rows
@@ -418,10 +431,13 @@ __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
     recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tbl + tbl_col(i), laq, slot, q, N, wbar, grad, nullptr);
   }
   slot[0][0] += lw0;
+  Real* vy = slot_vy_block<M, Real>(slots, N);
 #pragma unroll
-  for (int sl = 0; sl < 4; ++sl)
-#pragma unroll
-    for (int fl = 0; fl < 3; ++fl) slots[slot_index<M>(i, sl, fl, q)] = slot[sl][fl];
+  for (int sl = 0; sl < 4; ++sl) {
+    slots[slot_w<M>(i, sl, q)] = slot[sl][0];
+    vy[slot_vy<M>(i, sl, 1, q)] = Real(slot[sl][1]);
+    vy[slot_vy<M>(i, sl, 2, q)] = Real(slot[sl][2]);
+  }
 }
 
 // One work-item per (cell, component q).  Every load is issued before the
@@ -441,6 +457,7 @@ __global__ __launch_bounds__(kBlock) void adj_gather_kernel(
   const int i = gid / M, q = gid - (gid / M) * M;
   if (i >= N) return;
   const size_t sN = size_t(N), sE = size_t(E);
+  const Real* vy = slot_vy_block<M, Real>(slots, N);
   // per face: neighbour, back-slot, edge and side, n|e| of the cell's face,
   // the edge normal and length, and the two sides' point sums of the face
   // kernel; per component: the cell's average and its adjoint
@@ -458,9 +475,9 @@ __global__ __launch_bounds__(kBlock) void adj_gather_kernel(
       const bool has = nbf[f] >= 0;
       const int nb = has ? nbf[f] : i;
       const int bk = has ? bkf[f] : 0;
-      sWf[f] = slots[slot_index<M>(nb, 1 + bk, 0, q)];
-      sVf[f] = slots[slot_index<M>(nb, 1 + bk, 1, q)];
-      sYf[f] = slots[slot_index<M>(nb, 1 + bk, 2, q)];
+      sWf[f] = slots[slot_w<M>(nb, 1 + bk, q)];
+      sVf[f] = double(vy[slot_vy<M>(nb, 1 + bk, 1, q)]);
+      sYf[f] = double(vy[slot_vy<M>(nb, 1 + bk, 2, q)]);
 #pragma unroll
       for (int c = 0; c < MC; ++c) {
         const int cq = M == 4 ? q : c;
@@ -475,9 +492,9 @@ __global__ __launch_bounds__(kBlock) void adj_gather_kernel(
   // the cell's own values
   const double iaK = inv_area[i];
   const double lgxK = double(lg[q * sN + i]), lgyK = double(lg[(M + q) * sN + i]);
-  double aW = slots[slot_index<M>(i, 0, 0, q)];
-  double aV = slots[slot_index<M>(i, 0, 1, q)];
-  double aY = slots[slot_index<M>(i, 0, 2, q)];
+  double aW = slots[slot_w<M>(i, 0, q)];
+  double aV = double(vy[slot_vy<M>(i, 0, 1, q)]);
+  double aY = double(vy[slot_vy<M>(i, 0, 2, q)]);
   if constexpr (M == 4) {
     // the quad's four lanes are the cell's components: a value the whole quad
     // needs is loaded once (lane f for face f) and broadcast by DPP
