@@ -6,9 +6,11 @@ pinned in tests/test_oracle_reverse.py), on every cell, every component and
 all three state blocks (the averages of W, W_x and W_y): relative max-norm per
 block within 1e-10 in FP64.  Cases: linear advection on the 800-triangle mesh,
 the vortex (1,152 triangles), the double Mach reflection (walls, prescribed
-inflow, the moving switch; 1,152 triangles), and the four-quadrant Riemann
+inflow, the moving switch; 1,152 triangles), the four-quadrant Riemann
 problem with the scaling limiter acting through its pressure branch and
-through its density branch (1,152 triangles).
+through its density branch (1,152 triangles), and the method's variants (the
+2-point time rule, the 3-point edge rule, weighted Step-2 rows) on the vortex
+(512 triangles) and on the double Mach reflection.
 """
 import numpy as np
 import pytest
@@ -66,6 +68,16 @@ def _case(name):
         om = OracleMesh.from_workload(wl)
         s0 = wl.state0 * (1.0 + 1e-3 * rng.uniform(-1, 1, wl.state0.shape))
         return wl, om, {}, s0, om.max_dt(s0, 0.3), 0.012
+    if name in ("vortex_gauss_time_edge3_weighted", "double_mach_edge3"):
+        # the variants of the method: the 2-point Gauss-Legendre time rule, the
+        # 3-point edge rule and the weighted Step-2 rows, on a smooth and on a
+        # walled mesh
+        kw = ({"time_rule": 1, "edge_rule": 3, "deriv_weight": 0.3} if name.startswith("vortex")
+              else {"edge_rule": 3})
+        wl = vortex_workload(n=16) if name.startswith("vortex") else double_mach_workload(n=12)
+        om = OracleMesh.from_workload(wl, **kw)
+        s0 = wl.state0 * (1.0 + 1e-3 * rng.uniform(-1, 1, wl.state0.shape))
+        return wl, om, kw, s0, om.max_dt(s0, 0.3), 0.0 if name.startswith("vortex") else 0.012
     if name in ("riemann_limited_pressure_n24", "riemann_limited_density_n24"):
         wl = riemann_workload(n=24)
         om = OracleMesh.from_workload(wl, positivity=1)
@@ -74,7 +86,8 @@ def _case(name):
     raise KeyError(name)
 
 
-@pytest.mark.parametrize("name", ["c1_advection", "vortex_n24", "double_mach_n12", "riemann_limited_pressure_n24"])
+@pytest.mark.parametrize("name", ["c1_advection", "vortex_n24", "double_mach_n12", "riemann_limited_pressure_n24",
+                                  "vortex_gauss_time_edge3_weighted", "double_mach_edge3"])
 def test_one_step_adjoint_element_by_element(name):
     wl, om, kw, s0, dt, t0 = _case(name)
     mesh = _mesh(wl, **kw)
