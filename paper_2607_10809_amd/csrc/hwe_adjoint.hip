@@ -74,14 +74,18 @@ __global__ __launch_bounds__(kFaceBlock<Real>, sizeof(Real) == 4 ? 2 : 1) void a
     const Real* __restrict__ lg, const Real* __restrict__ R, const int32_t* __restrict__ nbr,
     const int32_t* __restrict__ cell_edge, const double* __restrict__ enl, const Real* __restrict__ egp,
     const double* __restrict__ inv_area, const Real* __restrict__ nl, const double* __restrict__ bnd_n,
-    Real* __restrict__ lacell, double* __restrict__ lwcell, double* __restrict__ sface) {
+    Real* __restrict__ lacell, double* __restrict__ lwcell, double* __restrict__ sface,
+    const int32_t* __restrict__ cells, int ncells) {
   constexpr int M = NComp<EQ>::m;
   constexpr bool kWall = SB && EQ == EQ_EUL;
   const int gid = xcd_block_id() * kFaceBlock<Real> + threadIdx.x;
   const int wv = gid >> 6, wl = gid & 63;
   const int c = wl / 3, lane = wl - 3 * c;                 // lane = the face
-  const int i = wv * kFaceCells + c;
-  const bool valid = wl < 3 * kFaceCells && i < N;
+  // SB: only the cells with a wall or prescribed face (cells[0..ncells)),
+  // after the kernel without special boundaries has covered every cell
+  const int k = wv * kFaceCells + c;
+  const bool valid = wl < 3 * kFaceCells && (SB ? k < ncells : k < N);
+  const int i = SB ? (valid ? cells[k] : 0) : k;
   const int ic = valid ? i : N - 1;
   const size_t sN = size_t(N), sE = size_t(E);
   Real la[6][M];
@@ -625,20 +629,25 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
   const HostMesh& h = M->h;
   const DevMesh& d = M->d;
   const int N = int(h.N), E = int(h.E), NB = int(h.NB);
-  const int64_t waves = (int64_t(N) + kFaceCells - 1) / kFaceCells;
-  const dim3 grid{unsigned((waves * 64 + kFaceBlock<Real> - 1) / kFaceBlock<Real>)};
+  auto face_grid = [](int64_t cells) {
+    const int64_t waves = (cells + kFaceCells - 1) / kFaceCells;
+    return dim3{unsigned((waves * 64 + kFaceBlock<Real> - 1) / kFaceBlock<Real>)};
+  };
+  const dim3 grid = face_grid(N), sb_grid = face_grid(d.n_sb);
   Real* lacell = static_cast<Real*>(d.lacell);
   const bool sb = h.special_bnd;
+  // every cell by the kernel without special boundaries (its registers fit),
+  // then the cells with a wall or prescribed face again, by the kernel that
+  // treats them (it spills; on the double Mach mesh those are 1% of the cells)
 #define HWE_ADJ_CELL(TRV, GPV)                                                                                        \
   do {                                                                                                                \
-    if (sb)                                                                                                           \
-      hipLaunchKernelGGL((adj_face_kernel<EQ, Real, TRV, GPV, true>), grid, dim3(kFaceBlock<Real>), 0, st, N, E, NB, P, dt,     \
-                         wbar, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, lacell, d.lwcell,  \
-                         d.sface);                                                                                    \
-    else                                                                                                              \
-      hipLaunchKernelGGL((adj_face_kernel<EQ, Real, TRV, GPV, false>), grid, dim3(kFaceBlock<Real>), 0, st, N, E, NB, P, dt,    \
-                         wbar, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, lacell, d.lwcell,  \
-                         d.sface);                                                                                    \
+    hipLaunchKernelGGL((adj_face_kernel<EQ, Real, TRV, GPV, false>), grid, dim3(kFaceBlock<Real>), 0, st, N, E, NB, P,  \
+                       dt, wbar, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, lacell, d.lwcell, \
+                       d.sface, nullptr, 0);                                                                        \
+    if (sb && d.n_sb > 0)                                                                                             \
+      hipLaunchKernelGGL((adj_face_kernel<EQ, Real, TRV, GPV, true>), sb_grid, dim3(kFaceBlock<Real>), 0, st, N, E, NB, \
+                         P, dt, wbar, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, lacell,     \
+                         d.lwcell, d.sface, d.sb_cells, d.n_sb);                                                      \
   } while (0)
   if (M->opts.edge_rule == 3) {
     if (P.time_rule == 1)

@@ -37,6 +37,7 @@ struct HostMesh {
   std::vector<double> bnd_n;       // [4][NB] outward unit normal of boundary face b, its kind
                                    // (hwe_bnd_kind, as a double) and the x of its midpoint
   bool special_bnd = false;        // some boundary face is a wall or prescribed
+  std::vector<int32_t> sb_cells;   // the cells with a wall or prescribed face, ascending
   std::vector<double> p1;          // [55][N] Step-1 map (row-major 5 x 11 per cell; host tests)
   std::vector<double> p1f;         // [41][N] factored Step-1 map (device tables)
   std::vector<double> p2;          // [9][N] Step-2 data
@@ -86,6 +87,8 @@ struct DevMesh {
   // adjoint scratch: stencil-slot adjoints [N][4][3][m] and per-face scalars [3][N]
   double* slots = nullptr;
   double* sface = nullptr;
+  int32_t* sb_cells = nullptr;  // HostMesh::sb_cells (null when there are none)
+  int n_sb = 0;
   // adjoint scratch: per-cell coefficient adjoints [N][6][m] (Real) and
   // flux-base adjoints [N][m] (double) handed from the face to the recon kernel
   void* lacell = nullptr;

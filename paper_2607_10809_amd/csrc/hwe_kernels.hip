@@ -659,6 +659,10 @@ hwe_status upload_mesh(hwe_mesh_s* M) {
   HWE_TRY(dev_alloc(&d.G, m * E * rs));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.slots), 12 * m * N * sizeof(double)));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.sface), 3 * N * sizeof(double)));
+  if (!h.sb_cells.empty()) {
+    HWE_TRY(dev_copy(&d.sb_cells, h.sb_cells.data(), h.sb_cells.size()));
+    d.n_sb = int(h.sb_cells.size());
+  }
   HWE_TRY(dev_alloc(&d.lacell, 6 * m * N * rs));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.lwcell), m * N * sizeof(double)));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.red), kRedBlocks * sizeof(double)));
@@ -674,7 +678,7 @@ void free_device(hwe_mesh_s* M) {
   hipDeviceSynchronize();
   void* ptrs[] = {d.nbr, d.cell_edge, d.ecell, d.nbr_back, d.bnd_n, d.area, d.tbl, d.nl, d.inv_area,
                   d.gpc, d.enl, d.egp, d.tblf, d.nlf, d.egpf, d.R, d.F, d.G, d.slots, d.sface, d.lacell, d.lwcell,
-                  d.red, d.redi};
+                  d.red, d.redi, d.sb_cells};
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (void* e : d.prof_ev) hipEventDestroy(static_cast<hipEvent_t>(e));

@@ -541,7 +541,10 @@ hwe_status build_host_mesh(const double* nodes, int64_t n_nodes, const int32_t* 
         h.bnd_n[2 * h.NB + bcount] = double(kind);
         h.bnd_n[3 * h.NB + bcount] = t.x[f] + 0.5 * ex;
         if (kind >= HWE_BND_STATE_A) h.ecell[E + (face_edge[3 * k + f] >> 1)] = int32_t(-3 - bcount);
-        if (kind != HWE_BND_TRANSMISSIVE) h.special_bnd = true;
+        if (kind != HWE_BND_TRANSMISSIVE) {
+          h.special_bnd = true;
+          if (h.sb_cells.empty() || h.sb_cells.back() != int32_t(i)) h.sb_cells.push_back(int32_t(i));
+        }
         ++bcount;
         Tri gt;
         for (int v = 0; v < 3; ++v) {
