@@ -36,6 +36,14 @@
  *    on another (a checkpointed reverse sweep recomputes the next segment
  *    beside the current one's adjoints), while two steps, or two adjoints,
  *    may not.  The profiling events (hwe_profile_begin) assume one stream.
+ *  - On a mesh with reflective walls or prescribed boundary states the two
+ *    adjoint calls fork part of their work onto a stream the handle owns
+ *    (default priority, created with the handle) and join it back into the
+ *    caller's stream by events before their next launch there: the work
+ *    starts after what precedes the call on the caller's stream and is
+ *    complete before what follows it, and a graph captured from that stream
+ *    holds the forked branch.  That stream belongs to the adjoint's scratch
+ *    set above.
  *  - Memory given by the caller is never freed or reallocated by the library.
  */
 #ifndef HWE_H

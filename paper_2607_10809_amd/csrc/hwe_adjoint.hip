@@ -21,11 +21,14 @@
 //      neighbours wrote for it, the Green-Gauss terms of the derivative
 //      averages and the derivative of the flux viscosity alpha (only on the
 //      cell whose spectral radius the max selected).
-// Meshes with reflective walls or prescribed boundary states run the face and
-// reconstruction reverses instantiated with SB = true (a boundary face's
-// flux, interface value, alpha and Green-Gauss terms, all local to its cell,
-// are reversed by the face kernel); the scaling limiter is reversed inside
-// the reconstruction reverse (template NPT = its points per cell).
+// Meshes with reflective walls or prescribed boundary states run the
+// reconstruction reverse instantiated with SB = true, and the face reverse
+// twice: SB = false over every cell, and beside it, on a second stream, SB =
+// true over the cells with such a face (a boundary face's flux, interface
+// value, alpha and Green-Gauss terms, all local to its cell, are reversed
+// there), whose outputs then replace those cells' records; the scaling
+// limiter is reversed inside the reconstruction reverse (template NPT = its
+// points per cell).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -82,12 +85,12 @@ __global__ __launch_bounds__(kFaceBlock<Real>, sizeof(Real) == 4 ? 2 : 1) void a
   const int wv = gid >> 6, wl = gid & 63;
   const int c = wl / 3, lane = wl - 3 * c;                 // lane = the face
   // SB: only the cells with a wall or prescribed face (cells[0..ncells)),
-  // after the kernel without special boundaries has covered every cell
+  // their outputs written compactly by list position (sface then [3][ncells])
   const int k = wv * kFaceCells + c;
   const bool valid = wl < 3 * kFaceCells && (SB ? k < ncells : k < N);
   const int i = SB ? (valid ? cells[k] : 0) : k;
   const int ic = valid ? i : N - 1;
-  const size_t sN = size_t(N), sE = size_t(E);
+  const size_t sN = size_t(N), sE = size_t(E), sO = SB ? size_t(ncells) : sN;
   Real la[6][M];
   double lWf[M];
 #pragma unroll
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(kFaceBlock<Real>, sizeof(Real) == 4 ? 2 : 1) void a
         }
       }
     }
-    if (valid) sface[f * sN + ic] = s;
+    if (valid) sface[f * sO + (SB ? k : ic)] = s;
   }
   // sum over the cell's three lanes into its first
   const int s1 = wl + 1 < 64 ? wl + 1 : wl, s2 = wl + 2 < 64 ? wl + 2 : wl;
@@ -308,10 +311,34 @@ __global__ __launch_bounds__(kFaceBlock<Real>, sizeof(Real) == 4 ? 2 : 1) void a
     }
   }
   if (valid && lane == 0) {
-    store_record<6 * M>(lacell + size_t(i) * (6 * M), &la[0][0]);
+    const int o = SB ? k : i;
+    store_record<6 * M>(lacell + size_t(o) * (6 * M), &la[0][0]);
 #pragma unroll
-    for (int q = 0; q < M; ++q) lwcell[size_t(i) * M + q] = lWf[q];
+    for (int q = 0; q < M; ++q) lwcell[size_t(o) * M + q] = lWf[q];
   }
+}
+
+// The listed cells' face-reverse outputs (compact, by list position) copied
+// over their records: one work-item per (listed cell, value), the 6M
+// coefficient adjoints, then the M flux-base adjoints, then the 3 face scalars.
+template <int M, class Real>
+__global__ __launch_bounds__(256) void adj_face_patch_kernel(int N, int n, const int32_t* __restrict__ cells,
+                                                             const Real* __restrict__ la_c,
+                                                             const double* __restrict__ lw_c,
+                                                             const double* __restrict__ sf_c,
+                                                             Real* __restrict__ lacell, double* __restrict__ lwcell,
+                                                             double* __restrict__ sface) {
+  constexpr int W = 7 * M + 3;
+  const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (g >= int64_t(n) * W) return;
+  const int k = int(g / W), j = int(g - int64_t(k) * W);
+  const size_t i = size_t(cells[k]);
+  if (j < 6 * M)
+    lacell[i * (6 * M) + j] = la_c[size_t(k) * (6 * M) + j];
+  else if (j < 7 * M)
+    lwcell[i * M + (j - 6 * M)] = lw_c[size_t(k) * M + (j - 6 * M)];
+  else
+    sface[size_t(j - 7 * M) * N + i] = sf_c[size_t(j - 7 * M) * n + k];
 }
 
 // One work-item per (cell, component q): the reverse of the reconstruction of
@@ -636,18 +663,29 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
   const dim3 grid = face_grid(N), sb_grid = face_grid(d.n_sb);
   Real* lacell = static_cast<Real*>(d.lacell);
   const bool sb = h.special_bnd;
-  // every cell by the kernel without special boundaries (its registers fit),
-  // then the cells with a wall or prescribed face again, by the kernel that
-  // treats them (it spills; on the double Mach mesh those are 1% of the cells)
+  // Every cell by the kernel without special boundaries (its registers fit);
+  // beside it, on the handle's second stream, the cells with a wall or
+  // prescribed face by the kernel that treats them (it spills and runs few
+  // waves, on the double Mach mesh 1% of the cells: alone it would leave the
+  // chip idle for its latency), into compact buffers that are copied over
+  // those cells' records once both are done.
+  const bool split = sb && d.n_sb > 0;
+  hipStream_t sst = static_cast<hipStream_t>(d.sb_stream);
+  if (split) {
+    hipError_t e1 = hipEventRecord(static_cast<hipEvent_t>(d.sb_fork), st);
+    if (e1 != hipSuccess) return hip_fail(e1, "hipEventRecord");
+    e1 = hipStreamWaitEvent(sst, static_cast<hipEvent_t>(d.sb_fork), 0);
+    if (e1 != hipSuccess) return hip_fail(e1, "hipStreamWaitEvent");
+  }
 #define HWE_ADJ_CELL(TRV, GPV)                                                                                        \
   do {                                                                                                                \
+    if (split)                                                                                                        \
+      hipLaunchKernelGGL((adj_face_kernel<EQ, Real, TRV, GPV, true>), sb_grid, dim3(kFaceBlock<Real>), 0, sst, N, E,    \
+                         NB, P, dt, wbar, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n,         \
+                         static_cast<Real*>(d.sb_la), d.sb_lw, d.sb_sface, d.sb_cells, d.n_sb);                      \
     hipLaunchKernelGGL((adj_face_kernel<EQ, Real, TRV, GPV, false>), grid, dim3(kFaceBlock<Real>), 0, st, N, E, NB, P,  \
                        dt, wbar, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, lacell, d.lwcell, \
                        d.sface, nullptr, 0);                                                                        \
-    if (sb && d.n_sb > 0)                                                                                             \
-      hipLaunchKernelGGL((adj_face_kernel<EQ, Real, TRV, GPV, true>), sb_grid, dim3(kFaceBlock<Real>), 0, st, N, E, NB, \
-                         P, dt, wbar, lw, lg, R, d.nbr, d.cell_edge, d.enl, egp, d.inv_area, nl, d.bnd_n, lacell,     \
-                         d.lwcell, d.sface, d.sb_cells, d.n_sb);                                                      \
   } while (0)
   if (M->opts.edge_rule == 3) {
     if (P.time_rule == 1)
@@ -660,6 +698,16 @@ hwe_status adjoint_impl(hwe_mesh_s* M, const Params& P, const double* wbar, cons
     HWE_ADJ_CELL(0, 2);
   }
 #undef HWE_ADJ_CELL
+  if (split) {
+    hipError_t e1 = hipEventRecord(static_cast<hipEvent_t>(d.sb_join), sst);
+    if (e1 != hipSuccess) return hip_fail(e1, "hipEventRecord");
+    e1 = hipStreamWaitEvent(st, static_cast<hipEvent_t>(d.sb_join), 0);
+    if (e1 != hipSuccess) return hip_fail(e1, "hipStreamWaitEvent");
+    constexpr int W = 7 * NComp<EQ>::m + 3;
+    hipLaunchKernelGGL((adj_face_patch_kernel<NComp<EQ>::m, Real>), dim3(grid_for(int64_t(d.n_sb) * W)), dim3(kBlock),
+                       0, st, N, d.n_sb, d.sb_cells, static_cast<const Real*>(d.sb_la), d.sb_lw, d.sb_sface, lacell,
+                       d.lwcell, d.sface);
+  }
   const dim3 rgrid(grid_for(int64_t(N) * NComp<EQ>::m));
 #define HWE_ADJ_RECON(SBV, NPTV)                                                                                    \
   hipLaunchKernelGGL((adj_recon_kernel<EQ, Real, SBV, NPTV>), rgrid, dim3(kBlock), 0, st, N, NB, P, wbar, grad,     \

@@ -89,6 +89,16 @@ struct DevMesh {
   double* sface = nullptr;
   int32_t* sb_cells = nullptr;  // HostMesh::sb_cells (null when there are none)
   int n_sb = 0;
+  // the face reverse of the listed cells runs beside the one over every cell:
+  // on its own stream (hipStream_t, default priority, created with the list),
+  // joined by two events (hipEvent_t), into compact outputs that a small
+  // kernel copies over the listed cells' records after the join
+  void* sb_stream = nullptr;
+  void* sb_fork = nullptr;
+  void* sb_join = nullptr;
+  void* sb_la = nullptr;       // [n_sb][6][m] Real
+  double* sb_lw = nullptr;     // [n_sb][m]
+  double* sb_sface = nullptr;  // [3][n_sb]
   // adjoint scratch: per-cell coefficient adjoints [N][6][m] (Real) and
   // flux-base adjoints [N][m] (double) handed from the face to the recon kernel
   void* lacell = nullptr;

@@ -660,8 +660,22 @@ hwe_status upload_mesh(hwe_mesh_s* M) {
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.slots), 12 * m * N * sizeof(double)));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.sface), 3 * N * sizeof(double)));
   if (!h.sb_cells.empty()) {
-    HWE_TRY(dev_copy(&d.sb_cells, h.sb_cells.data(), h.sb_cells.size()));
-    d.n_sb = int(h.sb_cells.size());
+    const size_t nsb = h.sb_cells.size();
+    HWE_TRY(dev_copy(&d.sb_cells, h.sb_cells.data(), nsb));
+    d.n_sb = int(nsb);
+    HWE_TRY(dev_alloc(&d.sb_la, 6 * m * nsb * rs));
+    HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.sb_lw), m * nsb * sizeof(double)));
+    HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.sb_sface), 3 * nsb * sizeof(double)));
+    hipStream_t sst;
+    err = hipStreamCreateWithFlags(&sst, hipStreamNonBlocking);
+    if (err != hipSuccess) return hip_fail(err, "hipStreamCreateWithFlags");
+    d.sb_stream = sst;
+    hipEvent_t ev[2];
+    for (int j = 0; j < 2; ++j) {
+      err = hipEventCreateWithFlags(&ev[j], hipEventDisableTiming);
+      if (err != hipSuccess) return hip_fail(err, "hipEventCreateWithFlags");
+      (j == 0 ? d.sb_fork : d.sb_join) = ev[j];
+    }
   }
   HWE_TRY(dev_alloc(&d.lacell, 6 * m * N * rs));
   HWE_TRY(dev_alloc(reinterpret_cast<void**>(&d.lwcell), m * N * sizeof(double)));
@@ -678,9 +692,12 @@ void free_device(hwe_mesh_s* M) {
   hipDeviceSynchronize();
   void* ptrs[] = {d.nbr, d.cell_edge, d.ecell, d.nbr_back, d.bnd_n, d.area, d.tbl, d.nl, d.inv_area,
                   d.gpc, d.enl, d.egp, d.tblf, d.nlf, d.egpf, d.R, d.F, d.G, d.slots, d.sface, d.lacell, d.lwcell,
-                  d.red, d.redi, d.sb_cells};
+                  d.red, d.redi, d.sb_cells, d.sb_la, d.sb_lw, d.sb_sface};
   for (void* p : ptrs)
     if (p) hipFree(p);
+  for (void* e : {d.sb_fork, d.sb_join})
+    if (e) hipEventDestroy(static_cast<hipEvent_t>(e));
+  if (d.sb_stream) hipStreamDestroy(static_cast<hipStream_t>(d.sb_stream));
   for (void* e : d.prof_ev) hipEventDestroy(static_cast<hipEvent_t>(e));
   d = DevMesh();
 }

@@ -155,6 +155,44 @@ def test_mixed_adjoint_with_walls_close_to_fp64():
     assert err <= 1e-4
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_wall_adjoint_graph_replays_equal_eager(prec):
+    """On a mesh with walls and prescribed states the adjoint forks the face
+    reverse of the cells with such a face onto the handle's own stream and
+    joins it back by events.  A HIP graph captured from the caller's stream
+    holds that branch: three replays, each after new adjoint inputs are copied
+    in and with eager adjoints and synchronisations between them, equal the
+    eager adjoint of the same inputs bitwise."""
+    import torch
+    wl = double_mach_workload(n=12)
+    rng = np.random.default_rng(41)
+    s0 = _perturbed(wl, rng)
+    dt = OracleMesh.from_workload(wl).max_dt(s0, 0.3)
+    mesh = _mesh(wl, prec)
+    mesh.set_time(0.012)
+    w, g = mesh.to_device(s0)
+    lw, lg = mesh.to_device(rng.normal(size=s0.shape))
+    ow, og = mesh.empty_state()
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream(device=mesh.device)
+    s.wait_stream(torch.cuda.current_stream(mesh.device))
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            mesh.adjoint(w, g, lw, lg, dt, out=(ow, og), stream=s)
+    torch.cuda.current_stream(mesh.device).wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        nw, ng = mesh.to_device(rng.normal(size=s0.shape))
+        lw.copy_(nw)
+        lg.copy_(ng)
+        graph.replay()
+        torch.cuda.synchronize()
+        rw, rg = mesh.adjoint(w, g, lw, lg, dt)
+        torch.cuda.synchronize()
+        print(prec, "replay", rep, "max |diff|", float((ow - rw).abs().max()), flush=True)
+        assert torch.equal(ow, rw) and torch.equal(og, rg), rep
+
+
 def test_rollout_through_a_moving_boundary_against_the_oracle_jvp():
     """The checkpointed rollout from t0 > 0 sets each step's time (the moving
     switch) in the forward pass, the recomputation and the adjoints: the
