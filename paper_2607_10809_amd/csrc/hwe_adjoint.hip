@@ -298,15 +298,15 @@ __global__ __launch_bounds__(kFaceBlock<Real>, sizeof(Real) == 4 ? 2 : 1) void a
     }
     if (valid) sface[f * sO + (SB ? k : ic)] = s;
   }
-  // sum over the cell's three lanes into its first
-  const int s1 = wl + 1 < 64 ? wl + 1 : wl, s2 = wl + 2 < 64 ? wl + 2 : wl;
+  // sum over the cell's three lanes into its first (lanes 3c + 1 and 3c + 2
+  // reached by whole-wave DPP shifts, no LDS round trip)
 #pragma unroll
   for (int q = 0; q < M; ++q) {
-    const double a1 = __shfl(lWf[q], s1), a2 = __shfl(lWf[q], s2);
+    const double a1 = wave_next(lWf[q]), a2 = wave_next(a1);
     lWf[q] = (lWf[q] + a1) + a2;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      const Real b1 = __shfl(la[j][q], s1), b2 = __shfl(la[j][q], s2);
+      const Real b1 = wave_next(la[j][q]), b2 = wave_next(b1);
       la[j][q] = (la[j][q] + b1) + b2;
     }
   }
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void adj_face_patch_kernel(int N, int n, const
 // lane keeps its component of the limiter's reverse.  The limited
 // coefficients are theta_q a_q; so la_q <- theta_q la_q + (dtheta/da)^T lth.
 template <class Real, int NPT> struct ScalingLimiterRev {
-  int lane0, q, N, i;
+  int q, N, i;
   double gam, W0;
   const double* gpc;
   __device__ __forceinline__ void operator()(const Real (&au)[6], const Real (&la)[6], Real (&lae)[6],
@@ -363,9 +363,9 @@ template <class Real, int NPT> struct ScalingLimiterRev {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
 #pragma unroll
-      for (int j = 0; j < 6; ++j) all[c][j] = __shfl(au[j], lane0 + c);
-      Wb[c] = __shfl(W0, lane0 + c);
-      lth[c] = __shfl(lthq, lane0 + c);
+      for (int j = 0; j < 6; ++j) all[c][j] = quad_bcast(au[j], c);
+      Wb[c] = quad_bcast(W0, c);
+      lth[c] = quad_bcast(lthq, c);
     }
     double px[NPT], py[NPT];
 #pragma unroll
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void adj_recon_kernel(
     double cross[2][3] = {{0, 0, 0}, {0, 0, 0}};
     const Real* tb = reinterpret_cast<const Real*>(stage) + (i % kTile);
     if constexpr (NPT > 0) {
-      const ScalingLimiterRev<Real, NPT> lim{int(threadIdx.x & 63) & ~3, q, N, i, P.gam, S.W0, gpc};
+      const ScalingLimiterRev<Real, NPT> lim{q, N, i, P.gam, S.W0, gpc};
       recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tb, laq, slot, q, N, wbar, grad, cross, lim);
     } else {
       recon_rev<EQ, Real, SB>(i, NB, P, S, bnd_n, tb, laq, slot, q, N, wbar, grad, cross);

@@ -124,14 +124,14 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(int N, int NB, Params P, 
     Real a[6];
     recon_from_stencil<EQ, Real>(ic, q, N, NB, P, S, bnd_n, tb, wbar, grad, a);
     if constexpr (NPT > 0) {
-      const int lane0 = (threadIdx.x & 63) & ~3;
+      // the cell's four component lanes are an aligned quad
       Real all[4][6];
       double Wb[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) all[c][j] = __shfl(a[j], lane0 + c);
-        Wb[c] = __shfl(S.W0, lane0 + c);
+        for (int j = 0; j < 6; ++j) all[c][j] = quad_bcast(a[j], c);
+        Wb[c] = quad_bcast(S.W0, c);
       }
       double th[4];
       positivity_theta<Real, NPT>(P.gam, Wb, all, px, py, th);

@@ -46,6 +46,14 @@ template <int CTRL> __device__ __forceinline__ double quad_perm(double v) {
   const int lo = quad_perm<CTRL>(__double2loint(v)), hi = quad_perm<CTRL>(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
+// Whole-wave shift by one lane (DPP wave_shl:1, a VALU move): lane l receives
+// lane l + 1's value; the last lane's result is undefined.
+__device__ __forceinline__ int wave_next(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ float wave_next(float v) { return __int_as_float(wave_next(__float_as_int(v))); }
+__device__ __forceinline__ double wave_next(double v) {
+  const int lo = wave_next(__double2loint(v)), hi = wave_next(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
 // A 4x4 transpose across each aligned quad: lane q holds column q of the
 // block in t[0..3] on entry and row q on exit (two DPP rounds: the
 // off-diagonal 2x2 blocks swap, then the entries within them).
