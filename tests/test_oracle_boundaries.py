@@ -27,8 +27,9 @@ import pytest
 
 from oracle import OracleMesh
 from oracle.oracle import BND_KINDS
-from workloads import (DMR_A, DMR_B, double_mach_workload, forward_step_workload, moving_shock_workload,
-                       piecewise_average_states, shock_tube_workload, split_square_mesh, wedge_workload)
+from workloads import (DMR_A, DMR_B, cell_average_states, double_mach_workload, forward_step_workload,
+                       moving_shock_workload, piecewise_average_states, shock_tube_workload, split_square_mesh,
+                       wedge_workload)
 from workloads.problems import _two_state
 
 pytestmark = pytest.mark.usefixtures("oracle_lib")
@@ -137,6 +138,71 @@ def test_moving_shock_position_and_convergence():
     assert abs(xs2 - xe) <= 0.05 * h2
     assert l1b <= 0.05
     assert l1a / l1b >= 1.6
+
+
+def test_run_and_jvp_follow_the_steps_through_the_moving_switch():
+    """Every entry of the oracle that steps in time evaluates the moving
+    boundary states at the middle of each step, as one step does (whose
+    switch time the shock-position test above fixes): four steps of run, and
+    the primal output of the JVP, equal four single steps from t0, t0 + dt,
+    ... bitwise, on the double Mach mesh while the switch crosses top faces."""
+    wl = double_mach_workload(n=12)
+    om = OracleMesh.from_workload(wl)
+    dt = om.max_dt(wl.state0, 0.3)
+    t0 = 0.012 + 12 * dt          # the switch passes a top face midpoint within the next four steps
+    b = wl.state0
+    for k in range(4):
+        b = om.step(b, dt, t=t0 + k * dt)
+    a = om.run(wl.state0, dt, 4, t=t0)
+    j, _ = om.jvp(wl.state0, np.zeros_like(wl.state0), dt, 4, t=t0)
+    assert np.array_equal(a, b)
+    assert np.array_equal(j, b)
+    # the switch moves across a face within these steps: the top boundary
+    # faces' states are not the same at t0 and at t0 + 4 dt
+    assert np.abs(om.step(wl.state0, dt, t=t0 + 4 * dt) - om.step(wl.state0, dt, t=t0)).max() > 0.0
+
+
+def test_prescribed_ghost_is_a_flat_cell_holding_the_state():
+    """Reading: the ghost across a prescribed face is the cell's mirror image
+    across the face, holding the prescribed state with zero derivative
+    averages.  So the reconstruction of a cell with such a face (candidates,
+    smoothness indicators, weights) equals, to round-off, its reconstruction on
+    the mesh extended by that mirror triangle as an ordinary cell holding the
+    state and zero derivative averages, the face then interior.  The cell's own
+    derivative averages are far from zero, so a ghost that kept them (mirrored)
+    would differ."""
+    mesh = split_square_mesh((6, 6), (0.0, 1.0, 0.0, 1.0), jitter=0.2, seed=33, periodic=False)
+    Wb = [1.4, 0.5, 0.1, 2.9]
+    kw = dict(eq=2, bc=1, box=(0.0, 1.0, 0.0, 1.0), regions=[("A", (-0.01, 0.01, -1.0, 2.0))], states=[Wb, Wb])
+    A = OracleMesh(mesh.nodes, mesh.tris, **kw)
+    kinds = A.face_kinds()
+
+    def f(x, y, t):
+        b = np.exp(-8.0 * ((x - 0.1) ** 2 + (y - 0.5) ** 2))
+        return np.stack([1.0 + 0.4 * b, 0.3 + 0.5 * b, -0.2 * b + 0 * x, 2.5 + 0.8 * b], -1)
+
+    s_A = cell_average_states(mesh, f)
+    checked = 0
+    for k in range(A.N):
+        for fc in range(3):
+            if kinds[k, fc] != 2:
+                continue
+            a, b = mesh.tris[k, fc], mesh.tris[k, (fc + 1) % 3]
+            c = mesh.tris[k, (fc + 2) % 3]
+            nodes = np.concatenate([mesh.nodes, mesh.nodes[c][None] * np.array([[-1.0, 1.0]])])
+            tris = np.concatenate([mesh.tris, np.array([[b, a, len(mesh.nodes)]])]).astype(np.int32)
+            P = nodes[tris[-1]]
+            assert (P[1, 0] - P[0, 0]) * (P[2, 1] - P[0, 1]) - (P[1, 1] - P[0, 1]) * (P[2, 0] - P[0, 0]) > 0
+            B = OracleMesh(nodes, tris, **kw)
+            s_B = np.concatenate([s_A, np.zeros((3, 4, 1))], axis=2)
+            s_B[0, :, -1] = Wb
+            rA, rB = A.recon_cell(s_A, k), B.recon_cell(s_B, k)
+            assert np.abs(s_A[1:, :, k]).max() > 0.3
+            for key in ("p", "beta", "omega"):
+                err = np.abs(rA[key] - rB[key]).max() / np.abs(rA[key]).max()
+                assert err <= 1e-11, (k, key, err)
+            checked += 1
+    assert checked >= 6
 
 
 def test_double_mach_far_field_converges_to_the_moving_shock():

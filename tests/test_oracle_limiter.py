@@ -9,7 +9,8 @@ the cell's edge Gauss points; its definition fixes what to check:
 * a cell whose unlimited reconstruction is admissible at those points keeps
   theta = 1 (the limiter is inactive);
 * a cell scaled for its pressure touches the bound: its smallest pressure over
-  the points is eps (the scaling is the largest admissible one);
+  the points is eps (the scaling is the largest admissible one); so does a
+  cell scaled for its density alone, in its smallest density, to a few ulps;
 * the scaling is about the average, so the cell averages are untouched.
 """
 import numpy as np
@@ -84,6 +85,33 @@ def test_limiter_bounds_activity_and_touching(rule):
         mids = np.array([0.5 * (V[k, f] + V[k, (f + 1) % 3]) for f in range(3)])
         avg = lim.eval_recon(s, k, mids)[:, :, 0].mean(axis=0)
         assert np.abs(avg - s[0, :, k]).max() <= 1e-12 * np.abs(s[0, :, k]).max(), k
+
+
+@pytest.mark.parametrize("rule", [2, 3])
+def test_density_scaling_touches_eps(rule):
+    """A cell scaled for its density and not for its pressure: the density
+    scale is the largest in [0, 1] that keeps the density >= eps at the edge
+    points, so the smallest limited density over them is eps itself, to a few
+    ulps of the cell's average density (eps = min(1e-13, rho_bar, p_bar) is
+    far above that rounding on this data, so a scale that ignored eps, or that
+    kept a margin, fails)."""
+    wl = riemann_workload(n=24)
+    lim = OracleMesh.from_workload(wl, positivity=1, edge_rule=rule)
+    V = lim.cell_vertices()
+    n = 0
+    for seed in (41, 43, 47, 53):
+        s = near_vacuum_state(wl, seed, "density")
+        for k in range(lim.N):
+            th = lim.recon_theta(s, k)
+            if not (th[0] < 1.0 and th[1] == 1.0):
+                continue
+            rho = lim.eval_recon(s, k, _edge_points(V[k], rule))[:, 0, 0]
+            Wb = s[0, :, k]
+            eps = min(1e-13, Wb[0], _pressure(Wb[None, :])[0])
+            assert abs(rho.min() - eps) <= 16 * np.finfo(float).eps * Wb[0], (seed, k, rho.min(), eps, Wb[0])
+            n += 1
+    print(f"{rule}-point rule: {n} cells scaled for the density alone", flush=True)
+    assert n > 0
 
 
 def test_limiter_jvp_against_central_differences():

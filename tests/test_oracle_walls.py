@@ -6,7 +6,10 @@ wall Gauss point is the reflected interior value.
 * a closed box conserves mass to round-off (no mass crosses a wall);
 * the Lax and Sod shock tubes, run as 2-D strips between walls, converge to the
   exact 1-D Riemann solution (tests/exact_riemann.py, written from the shock and
-  rarefaction relations) in L1.
+  rarefaction relations) in L1;
+* a wall is a mirror: the step on a half domain with a wall equals the step on
+  the domain doubled by the mirror image of its mesh, from mirror-symmetric
+  data, with momentum across the wall.
 """
 import numpy as np
 import pytest
@@ -82,3 +85,55 @@ def test_shock_tubes_converge_to_the_exact_riemann_solution(name, bound):
     assert np.isfinite(s).all()
     assert e100 < bound, (e50, e100)
     assert e50 / e100 > 1.4, (e50, e100)
+
+
+def _mirror_state(s):
+    """The state of the mirror image across x = 0: density, y-momentum and
+    energy even in x, x-momentum odd; the x-derivative averages change sign
+    where the field is even, the y-derivative averages where it is odd."""
+    t = s.copy()
+    t[0, 1] *= -1.0
+    t[1, [0, 2, 3]] *= -1.0
+    t[2, 1] *= -1.0
+    return t
+
+
+def test_wall_step_equals_the_mirror_image_flow():
+    """The reading of a reflective wall (the ghost cell is the cell's mirror
+    image across the face holding the reflected average and both rows of the
+    derivative averages reflected; the exterior value at a wall point is the
+    reflected interior value; the flux viscosity takes the reflected average)
+    makes a wall equivalent to a mirror.  So five steps on [0, 1]^2 with a wall
+    at x = 0 equal, cell by cell to round-off, five steps on [-1, 1] x [0, 1]
+    meshed by the same triangles and their mirror images (no wall at x = 0),
+    from the data and its mirror image; the flow crosses x = 0 where the wall
+    stands, so the reflection of the normal momentum is exercised."""
+    half = split_square_mesh((8, 8), (0.0, 1.0, 0.0, 1.0), jitter=0.2, seed=31, periodic=False)
+    nodes, tris = half.nodes, half.tris.astype(np.int64)
+    on_axis = nodes[:, 0] == 0.0
+    image = np.empty(len(nodes), dtype=np.int64)
+    image[on_axis] = np.flatnonzero(on_axis)
+    image[~on_axis] = len(nodes) + np.arange(int((~on_axis).sum()))
+    full_nodes = np.concatenate([nodes, nodes[~on_axis] * np.array([-1.0, 1.0])])
+    full_tris = np.concatenate([tris, image[tris][:, [0, 2, 1]]]).astype(np.int32)   # counter-clockwise
+
+    def f(x, y, t):
+        b = np.exp(-20.0 * ((x - 0.25) ** 2 + (y - 0.5) ** 2))
+        r, u, v, p = 1.0 + 0.3 * b, -0.6 * b, 0.1 + 0 * x, 1.0 + 0.2 * b
+        return np.stack([r, r * u, r * v, p / (GAMMA - 1) + 0.5 * r * (u * u + v * v)], -1)
+
+    s_half = cell_average_states(half, f)
+    s_full = np.concatenate([s_half, _mirror_state(s_half)], axis=2)
+    wall = OracleMesh(nodes, half.tris, eq=2, bc=1, box=(0.0, 1.0, 0.0, 1.0), walls=0b0001)
+    mirror = OracleMesh(full_nodes, full_tris, eq=2, bc=1, box=(-1.0, 1.0, 0.0, 1.0))
+    dt = wall.max_dt(s_half, 0.3)
+    a = wall.run(s_half, dt, 5)
+    b = mirror.run(s_full, dt, 5)
+    N = s_half.shape[2]
+    assert np.abs(s_half[0, 1, :]).max() > 0.05           # momentum towards the wall
+    for blk in range(3):
+        scale = np.abs(a[blk]).max()
+        e_in = np.abs(b[blk, :, :N] - a[blk]).max() / scale
+        e_img = np.abs(b[blk, :, N:] - _mirror_state(a)[blk]).max() / scale
+        print(f"block {blk}: wall vs mirror {e_in:.2e}, image {e_img:.2e}", flush=True)
+        assert e_in <= 1e-12 and e_img <= 1e-12
