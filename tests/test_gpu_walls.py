@@ -7,7 +7,10 @@
 * a longer strip (38,400 triangles): a 40-step prefix and one late step, also
   with the limiter;
 * uniform states between walls stay uniform; a closed box conserves mass;
-* the adjoint refuses meshes with walls.
+* a wall is a mirror, at the size of the vortex workload: the step on a half
+  domain with a wall equals the step on the domain doubled by the mirror image
+  of its mesh, from mirror-symmetric data with momentum across the wall.
+(The adjoint on wall meshes is tested in test_gpu_adjoint.py.)
 """
 import os
 import sys
@@ -149,3 +152,55 @@ def test_closed_box_conserves_mass_and_matches_the_oracle():
     assert np.isfinite(got).all()
     assert drift <= 1e-13 and e5 <= 1e-12 and e1 <= 1e-12
 
+
+
+def _mirror_state(s):
+    """The mirror image across x = 0 of a [3][4][N] state: density, y-momentum
+    and energy even in x, x-momentum odd."""
+    t = s.copy()
+    t[0, 1] *= -1.0
+    t[1, [0, 2, 3]] *= -1.0
+    t[2, 1] *= -1.0
+    return t
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_wall_equals_the_mirror_image_flow_full_size(prec):
+    """The property the oracle's walls-as-mirrors pin checks on a small mesh,
+    on the GPU at the vortex workload's size: 204,800 triangles on [0, 1]^2
+    with a wall at x = 0, 20 steps from data with momentum across the wall,
+    against 20 steps on the 409,600 triangles of the domain doubled by the
+    mirror image of the mesh (no wall there), from the data and its mirror
+    image.  Both halves of the doubled run match (the image mirrored back):
+    FP64 to 1e-12 of each block's largest value, mixed to 2e-5."""
+    from paper_2607_10809_amd.hwe import Mesh
+    half = split_square_mesh((320, 320), (0.0, 1.0, 0.0, 1.0), jitter=0.1, seed=3, periodic=False)
+    nodes, tris = half.nodes, half.tris.astype(np.int64)
+    on_axis = nodes[:, 0] == 0.0
+    image = np.empty(len(nodes), dtype=np.int64)
+    image[on_axis] = np.flatnonzero(on_axis)
+    image[~on_axis] = len(nodes) + np.arange(int((~on_axis).sum()))
+    full_nodes = np.concatenate([nodes, nodes[~on_axis] * np.array([-1.0, 1.0])])
+    full_tris = np.concatenate([tris, image[tris][:, [0, 2, 1]]]).astype(np.int32)
+
+    def f(x, y, t):
+        b = np.exp(-20.0 * ((x - 0.25) ** 2 + (y - 0.5) ** 2))
+        r, u, v, p = 1.0 + 0.3 * b, -0.6 * b, 0.1 + 0 * x, 1.0 + 0.2 * b
+        return np.stack([r, r * u, r * v, p / (GAMMA - 1) + 0.5 * r * (u * u + v * v)], -1)
+
+    s_half = cell_average_states(half, f)
+    s_full = np.concatenate([s_half, _mirror_state(s_half)], axis=2)
+    wall = Mesh(nodes, half.tris, eq="euler", bc="transmissive", box=(0.0, 1.0, 0.0, 1.0), precision=prec,
+                walls=0b0001)
+    mirror = Mesh(full_nodes, full_tris, eq="euler", bc="transmissive", box=(-1.0, 1.0, 0.0, 1.0), precision=prec)
+    dt = wall.max_dt(wall.to_device(s_half)[0], 0.3)
+    a = gpu_run(wall, s_half, dt, 20)
+    b = gpu_run(mirror, s_full, dt, 20)
+    N = s_half.shape[2]
+    bound = 1e-12 if prec == "fp64" else 2e-5
+    for blk in range(3):
+        scale = np.abs(a[blk]).max()
+        e_in = np.abs(b[blk, :, :N] - a[blk]).max() / scale
+        e_img = np.abs(b[blk, :, N:] - _mirror_state(a)[blk]).max() / scale
+        print(f"{prec} block {blk}: wall vs mirror {e_in:.2e}, image {e_img:.2e}", flush=True)
+        assert e_in <= bound and e_img <= bound
