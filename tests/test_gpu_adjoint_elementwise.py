@@ -6,7 +6,8 @@ pinned in tests/test_oracle_reverse.py), on every cell, every component and
 all three state blocks (the averages of W, W_x and W_y): relative max-norm per
 block within 1e-10 in FP64.  Cases: linear advection on the 800-triangle mesh,
 the vortex (1,152 triangles), the double Mach reflection (walls, prescribed
-inflow, the moving switch; 1,152 triangles), the four-quadrant Riemann
+inflow, the moving switch; 1,152 triangles, and both meshes at the full
+204,800 triangles), the four-quadrant Riemann
 problem with the scaling limiter acting through its pressure branch and
 through its density branch (1,152 triangles), and the method's variants (the
 2-point time rule, the 3-point edge rule, weighted Step-2 rows) on the vortex
@@ -78,6 +79,13 @@ def _case(name):
         om = OracleMesh.from_workload(wl, **kw)
         s0 = wl.state0 * (1.0 + 1e-3 * rng.uniform(-1, 1, wl.state0.shape))
         return wl, om, kw, s0, om.max_dt(s0, 0.3), 0.0 if name.startswith("vortex") else 0.012
+    if name in ("vortex_full", "double_mach_full"):
+        # the full 204,800-triangle meshes of the vortex workload and of the
+        # double Mach reflection (walls, inflow, the moving switch)
+        wl = vortex_workload() if name == "vortex_full" else double_mach_workload(n=160)
+        om = OracleMesh.from_workload(wl)
+        s0 = wl.state0 * (1.0 + 1e-3 * rng.uniform(-1, 1, wl.state0.shape))
+        return wl, om, {}, s0, om.max_dt(s0, 0.3), 0.0 if name == "vortex_full" else 0.012
     if name in ("riemann_limited_pressure_n24", "riemann_limited_density_n24"):
         wl = riemann_workload(n=24)
         om = OracleMesh.from_workload(wl, positivity=1)
@@ -99,6 +107,26 @@ def test_one_step_adjoint_element_by_element(name):
         print(f"{name} ({om.N} triangles) seed {seed}: element-wise rel max per block "
               f"W {err[0].max():.2e}, Wx {err[1].max():.2e}, Wy {err[2].max():.2e}", flush=True)
         assert err.max() <= FP64
+
+
+@pytest.mark.parametrize("name,prec", [("vortex_full", "fp64"), ("vortex_full", "mixed"),
+                                       ("double_mach_full", "fp64")])
+def test_full_size_one_step_adjoint_element_by_element(name, prec):
+    """One step's adjoint on the full 204,800-triangle meshes (the vortex
+    workload's, in the launch configuration the benchmark times, and the
+    double Mach reflection's, where the cells with a wall or inflow face are
+    reversed beside the others on the handle's second stream) against the
+    oracle's reverse mode, every entry: FP64 within 1e-10 of each block's
+    largest value, the mixed path within 1e-4."""
+    wl, om, kw, s0, dt, t0 = _case(name)
+    mesh = _mesh(wl, prec, **kw)
+    lam = np.random.default_rng(11).normal(size=s0.shape)
+    ref = om.vjp(s0, lam, dt, 1, t=t0)
+    got = _gpu_vjp(mesh, s0, lam, dt, t=t0)
+    err = _block_err(got, ref)
+    print(f"{name} {prec} ({om.N} triangles): element-wise rel max per block W {err[0].max():.2e}, "
+          f"Wx {err[1].max():.2e}, Wy {err[2].max():.2e}", flush=True)
+    assert err.max() <= (FP64 if prec == "fp64" else 1e-4)
 
 
 def test_one_step_adjoint_element_by_element_density_branch():
