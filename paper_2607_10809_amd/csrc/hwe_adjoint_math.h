@@ -887,28 +887,31 @@ __host__ __device__ __forceinline__ void recon_rev(int i, int NB, const Params& 
   double lWsum = 0.0;
   if (!P.linear) {
     double lw[4];
-    lw[0] = lk1 / g1;
+    const double ig1 = 1.0 / g1;
+    lw[0] = lk1 * ig1;
     for (int f = 0; f < 3; ++f) {
-      lw[0] -= lkl[f] * P.lw[f + 1] / g1;
+      lw[0] -= lkl[f] * P.lw[f + 1] * ig1;
       lw[f + 1] = lkl[f];
     }
     // w_l = wb_l / S
     double dotw = 0.0;
     for (int l = 0; l < 4; ++l) dotw += lw[l] * w[l];
     double lwb[4];
-    for (int l = 0; l < 4; ++l) lwb[l] = (lw[l] - dotw) / ssum;
+    const double iss = 1.0 / ssum;
+    for (int l = 0; l < 4; ++l) lwb[l] = (lw[l] - dotw) * iss;
     double lkappa = 0.0, lw2 = 0.0, lbeta[4] = {0, 0, 0, 0};
     if (kappa != 0.0) {
       for (int l = 0; l < 4; ++l) {
-        lkappa += lwb[l] * P.lw[l] / Dl[l];
-        const double lD = -lwb[l] * P.lw[l] * kappa / (Dl[l] * Dl[l]);
+        const double iD = 1.0 / Dl[l], t = lwb[l] * P.lw[l] * iD;
+        lkappa += t;
+        const double lD = -t * kappa * iD;
         lw2 += lD * (2.0 * w2 * P.eps + beta[l]);
         lbeta[l] += lD * w2;
       }
     }
     const double lwave = 2.0 * wave * lw2;
     lWsum = 0.25 * lwave;
-    const double lts = 2.0 * ts / 9.0 * lkappa;
+    const double lts = (2.0 / 9.0) * ts * lkappa;
     for (int l = 1; l < 4; ++l) {
       const double df = beta[0] - beta[l];
       const double sg = df > 0 ? 1.0 : (df < 0 ? -1.0 : 0.0);
