@@ -550,10 +550,40 @@ def test_dot_product_with_the_scaling_limiter(case):
     assert nlim >= (100 if branch == "pressure" else 1)
 
 
+def _face_neighbours(tris):
+    """(N, 3) neighbour of each cell across each face (the cell itself across a
+    boundary face, as its mirrored ghost holds its average)."""
+    tris = np.asarray(tris, dtype=np.int64)
+    N = len(tris)
+    a = np.concatenate([tris[:, 0], tris[:, 1], tris[:, 2]])
+    b = np.concatenate([tris[:, 1], tris[:, 2], tris[:, 0]])
+    key = np.minimum(a, b) * (int(tris.max()) + 1) + np.maximum(a, b)
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    same = np.flatnonzero(ks[1:] == ks[:-1])
+    fa, fb = order[same], order[same + 1]                  # face ids f * N + cell
+    nb = np.repeat(np.arange(N)[:, None], 3, axis=1)
+    nb[fa % N, fa // N] = fb % N
+    nb[fb % N, fb // N] = fa % N
+    return nb
+
+
 def test_c4_adjoint_with_the_limiter_full_size():
     """The adjoint at the 980,000-triangle Riemann configuration with the
     limiter on, at a state the GPU reached after 100 steps at CFL 0.2: the dot
-    product against the oracle's JVP of the same step."""
+    product against the oracle's JVP of the same step, and every entry against
+    the oracle's reverse mode (relative to its block's largest, 1e-10), except
+    where the step's linearization is set by round-off.  That is where the
+    gas is at rest: there a momentum component is zero up to round-off over a
+    whole stencil, so its W_ave is the 1e-30 floor plus noise, the nonlinear
+    weights of eq. (nonlinearweight) are ratios of noise-level smoothness
+    indicators, and the derivative through W_ave (the cell-average block only)
+    multiplies noise-level candidates by 1/W_ave.  Two correct FP64
+    evaluations differ there at the 1e-3 level (the oracle against itself
+    from a one-ulp perturbed state: 3e-3); those entries, the cell averages'
+    adjoints of a component whose stencil average at the cell or a neighbour
+    is below 1e-12 of the component's largest value (about 8% of the
+    entries), are reported, not compared."""
     import torch
     wl = riemann_workload()
     mesh = _mesh(wl, positivity=True)
@@ -575,6 +605,19 @@ def test_c4_adjoint_with_the_limiter_full_size():
     scale = float(np.abs(vj * v).sum())
     print("C4 limited adjoint: <J^T l, v> =", a, "<l, J v> =", b, "rel", abs(a - b) / scale, flush=True)
     assert abs(a - b) <= 1e-11 * scale
+    ref = om.vjp(s, lam, dt, 1)
+    rel = np.abs(vj - ref) / np.abs(ref).max(axis=-1, keepdims=True)
+    nb = _face_neighbours(wl.mesh.tris)
+    W = s[0]
+    wave = (W + W[:, nb[:, 0]] + W[:, nb[:, 1]] + W[:, nb[:, 2]]) / 4.0
+    tiny = np.abs(wave) < 1e-12 * np.abs(W).max(axis=1, keepdims=True)
+    mask = np.zeros(rel.shape, dtype=bool)
+    mask[0] = tiny | tiny[:, nb[:, 0]] | tiny[:, nb[:, 1]] | tiny[:, nb[:, 2]]
+    print(f"C4 limited adjoint element by element: rel max per block {rel[~mask].max():.2e} on "
+          f"{(~mask).mean():.1%} of the entries; {rel[mask].max():.2e} where the linearization is set by "
+          f"round-off", flush=True)
+    assert rel[~mask].max() <= 1e-10
+    assert mask.mean() < 0.15
 
 
 def test_mixed_adjoint_with_the_limiter_close_to_fp64():
