@@ -110,7 +110,7 @@ def test_one_step_adjoint_element_by_element(name):
 
 
 @pytest.mark.parametrize("name,prec", [("vortex_full", "fp64"), ("vortex_full", "mixed"),
-                                       ("double_mach_full", "fp64")])
+                                       ("double_mach_full", "fp64"), ("double_mach_full", "mixed")])
 def test_full_size_one_step_adjoint_element_by_element(name, prec):
     """One step's adjoint on the full 204,800-triangle meshes (the vortex
     workload's, in the launch configuration the benchmark times, and the
